@@ -1,0 +1,203 @@
+"""Pins of the oracle's equilibria and collision (single node, no streaming).
+
+Each test compares the oracle with something it does not compute itself:
+eq. 10 typed out, the product form of the equilibrium, the textbook cubic
+D3Q27 weights, BGK as the special case of equal rates, exact conservation,
+the independent central-moment route (eq. 3a + dense solve), the closed-form
+strain-rate solution of eq. 65, and the first-order source identity of App. D.
+"""
+
+import pytest
+import torch
+
+import oracle
+from oracle import collision as C
+from oracle import direct as D
+from oracle import equilibrium as EQ
+from oracle import lattice as L
+
+DT = torch.float64
+
+
+def _rand_state(n, seed, r, s, cs2, amp_u=0.08, noise=2e-3):
+    g = torch.Generator().manual_seed(seed)
+    rho = 1.0 + 0.05 * (torch.rand(n, generator=g, dtype=DT) - 0.5)
+    u = amp_u * (torch.rand(n, 3, generator=g, dtype=DT) - 0.5)
+    f = EQ.feq(rho, u, r, s, cs2)
+    f = f + noise * (torch.rand(n, 27, generator=g, dtype=DT) - 0.5) * f
+    return f, g
+
+
+# ------------------------------------------------------------------ equilibria
+
+@pytest.mark.parametrize("r,s,cs2", [(1.0, 1.0, 1 / 3), (1.0, 0.5, 1 / 12), (0.5, 0.25, 1 / 48)])
+def test_raw_equilibrium_is_eq10(r, s, cs2):
+    g = torch.Generator().manual_seed(1)
+    rho = 1 + 0.1 * torch.rand(16, generator=g, dtype=DT)
+    u = 0.2 * (torch.rand(16, 3, generator=g, dtype=DT) - 0.5)
+    m = EQ.raw_equilibrium(rho, u, cs2)
+    x, y, z = u[:, 0], u[:, 1], u[:, 2]
+    c = cs2
+    want = {
+        (0, 0, 0): rho, (1, 0, 0): rho * x, (0, 1, 0): rho * y, (0, 0, 1): rho * z,
+        (1, 1, 0): rho * x * y, (1, 0, 1): rho * x * z, (0, 1, 1): rho * y * z,
+        (2, 0, 0): c * rho + rho * x * x, (0, 2, 0): c * rho + rho * y * y, (0, 0, 2): c * rho + rho * z * z,
+        (1, 2, 0): c * rho * x + rho * x * y * y, (1, 0, 2): c * rho * x + rho * x * z * z,
+        (2, 1, 0): c * rho * y + rho * x * x * y, (0, 1, 2): c * rho * y + rho * y * z * z,
+        (2, 0, 1): c * rho * z + rho * x * x * z, (0, 2, 1): c * rho * z + rho * y * y * z,
+        (1, 1, 1): rho * x * y * z,
+        (2, 2, 0): c * c * rho + rho * c * (x * x + y * y) + rho * x * x * y * y,
+        (2, 0, 2): c * c * rho + rho * c * (x * x + z * z) + rho * x * x * z * z,
+        (0, 2, 2): c * c * rho + rho * c * (y * y + z * z) + rho * y * y * z * z,
+        (2, 1, 1): rho * (c + x * x) * y * z, (1, 2, 1): rho * (c + y * y) * x * z,
+        (1, 1, 2): rho * (c + z * z) * x * y,
+        (1, 2, 2): c * c * rho * x + rho * c * x * (y * y + z * z) + rho * x * y * y * z * z,
+        (2, 1, 2): c * c * rho * y + rho * c * y * (x * x + z * z) + rho * x * x * y * z * z,
+        (2, 2, 1): c * c * rho * z + rho * c * z * (x * x + y * y) + rho * x * x * y * y * z,
+        (2, 2, 2): c ** 3 * rho + rho * c * c * (x * x + y * y + z * z)
+        + rho * c * (x * x * y * y + y * y * z * z + x * x * z * z) + rho * x * x * y * y * z * z,
+    }
+    for mnp, val in want.items():
+        assert torch.allclose(m[:, L.MIDX[mnp]], val, atol=1e-15, rtol=1e-13), mnp
+
+
+@pytest.mark.parametrize("r,s,cs2", [(1.0, 0.5, 1 / 12), (0.5, 0.25, 1 / 48), (0.8, 1.3, 0.2)])
+def test_feq_product_form(r, s, cs2):
+    """f_eq = rho W_x(ebar_x) W_y(ebar_y) W_z(ebar_z), W(0) = 1-(cs2+u^2)/c^2, W(+-) = ((cs2+u^2)/c^2 +- u/c)/2."""
+    g = torch.Generator().manual_seed(2)
+    rho = 1 + 0.1 * torch.rand(10, generator=g, dtype=DT)
+    u = 0.2 * (torch.rand(10, 3, generator=g, dtype=DT) - 0.5)
+    f = EQ.feq(rho, u, r, s, cs2)
+    speeds = (1.0, r, s)
+    eb = L.ebar()
+    want = rho[:, None].expand(10, 27).clone()
+    for d in range(3):
+        c = speeds[d]
+        q = (cs2 + u[:, d] ** 2) / c ** 2
+        W0 = 1 - q
+        Wp = 0.5 * (q + u[:, d] / c)
+        Wm = 0.5 * (q - u[:, d] / c)
+        for a in range(27):
+            want[:, a] *= {0: W0, 1: Wp, -1: Wm}[int(eb[a, d])]
+    assert torch.allclose(f, want, atol=1e-15, rtol=1e-13)
+
+
+def test_cubic_rest_weights():
+    w = EQ.rest_weights(1.0, 1.0, 1.0 / 3.0)
+    want = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
+    eb = L.ebar()
+    for a in range(27):
+        assert w[a].item() == pytest.approx(want[int(eb[a].abs().sum())], rel=1e-15)
+
+
+@pytest.mark.parametrize("r,s,cs2", [(1.0, 0.5, 1 / 12), (0.5, 0.25, 1 / 48)])
+def test_feq_central_moments(r, s, cs2):
+    """Central moments of f_eq (eq. 3a evaluated directly) are those of eq. 9."""
+    g = torch.Generator().manual_seed(3)
+    rho = 1 + 0.1 * torch.rand(6, generator=g, dtype=DT)
+    u = 0.2 * (torch.rand(6, 3, generator=g, dtype=DT) - 0.5)
+    f = EQ.feq(rho, u, r, s, cs2)
+    k = torch.einsum("nka,na->nk", D.central_moment_matrix(u, r, s), f)
+    assert torch.allclose(k, EQ.central_equilibrium(rho, cs2), atol=1e-14)
+
+
+# ------------------------------------------------------------------ collision special cases
+
+@pytest.mark.parametrize("r,s,cs2", [(1.0, 1.0, 1 / 3), (0.7, 0.4, 0.04)])
+def test_all_rates_one_gives_equilibrium(r, s, cs2):
+    p = oracle.Params(1, 1, 1, r=r, s=s, cs2=cs2, omega_nu=1.0, omega_xi=1.0, omega_hi=1.0, corr="off")
+    f, _ = _rand_state(20, 4, r, s, cs2)
+    rho, u = C.macroscopic(f, torch.zeros(20, 3, dtype=DT), p)
+    ft = C.collide(f, torch.zeros(20, 3, dtype=DT), p)
+    assert torch.allclose(ft, EQ.feq(rho, u, r, s, cs2), atol=1e-15, rtol=1e-13)
+
+
+@pytest.mark.parametrize("omega", [0.6, 1.3, 1.8])
+def test_equal_rates_give_bgk(omega):
+    r, s, cs2 = 0.8, 0.6, 0.1
+    p = oracle.Params(1, 1, 1, r=r, s=s, cs2=cs2, omega_nu=omega, omega_xi=omega, omega_hi=omega,
+                      omega_1=omega, corr="off")
+    f, _ = _rand_state(20, 5, r, s, cs2)
+    zero = torch.zeros(20, 3, dtype=DT)
+    rho, u = C.macroscopic(f, zero, p)
+    ft = C.collide(f, zero, p)
+    want = (1 - omega) * f + omega * EQ.feq(rho, u, r, s, cs2)
+    assert torch.allclose(ft, want, atol=1e-14)
+
+
+@pytest.mark.parametrize("corr", ["off", "lowmach", "local", "full"])
+def test_conservation_and_source(corr):
+    r, s, cs2 = 0.5, 0.25, 1 / 48
+    p = oracle.Params(1, 1, 1, r=r, s=s, cs2=cs2, omega_nu=1.5, omega_xi=1.2, corr=corr)
+    f, g = _rand_state(30, 6, r, s, cs2, amp_u=0.03)
+    force = 1e-3 * (torch.rand(30, 3, generator=g, dtype=DT) - 0.5)
+    grad = 1e-3 * (torch.rand(30, 3, generator=g, dtype=DT) - 0.5)
+    ft = C.collide(f, force, p, grad_rho=grad)
+    e = L.velocities(r, s)
+    assert torch.allclose(ft.sum(-1), f.sum(-1), atol=1e-15, rtol=1e-14)
+    assert torch.allclose(ft @ e, f @ e + force, atol=1e-15)
+    # post-collision first-order central moments are F/2 for any omega_1 (App. D)
+    rho, u = C.macroscopic(f, force, p)
+    k1 = torch.einsum("nka,na->nk", D.central_moment_matrix(u, r, s), ft)[:, 1:4]
+    assert torch.allclose(k1, 0.5 * force, atol=1e-15)
+
+
+@pytest.mark.parametrize("corr", ["off", "lowmach", "local", "full"])
+@pytest.mark.parametrize("r,s", [(1.0, 0.5), (0.5, 0.25), (1.4, 0.7)])
+def test_factor_chain_equals_direct_route(corr, r, s):
+    cs2 = min(r * r, s * s) / 3
+    p = oracle.Params(1, 1, 1, r=r, s=s, omega_nu=1.4, omega_xi=1.1, omega_hi=0.9, corr=corr)
+    f, g = _rand_state(40, 7, r, s, cs2)
+    force = 1e-3 * (torch.rand(40, 3, generator=g, dtype=DT) - 0.5)
+    grad = 1e-2 * (torch.rand(40, 3, generator=g, dtype=DT) - 0.5)
+    a = C.collide(f, force, p, grad_rho=grad)
+    b = D.collide(f, force, p, grad_rho=grad)
+    assert torch.allclose(a, b, atol=1e-14)
+
+
+def test_uniform_equilibrium_is_fixed_point():
+    r, s, cs2 = 0.5, 0.25, 1 / 48
+    p = oracle.Params(1, 1, 1, r=r, s=s, omega_nu=1.6, omega_xi=1.3, corr="local")
+    rho = torch.full((5,), 1.02, dtype=DT)
+    u = torch.tensor([[0.01, -0.02, 0.005]] * 5, dtype=DT)
+    f = EQ.feq(rho, u, r, s, cs2)
+    ft = C.collide(f, torch.zeros(5, 3, dtype=DT), p)
+    assert torch.allclose(ft, f, atol=1e-16, rtol=1e-14)
+
+
+def test_lowmach_cubic_limit_has_no_correction():
+    """At r = s = 1, cs2 = 1/3 the low-Mach corrections vanish (remark in Sec. 2.4)."""
+    p_low = oracle.Params(1, 1, 1, r=1.0, s=1.0, cs2=1 / 3, omega_nu=1.3, omega_xi=1.1, corr="lowmach")
+    p_off = oracle.Params(1, 1, 1, r=1.0, s=1.0, cs2=1 / 3, omega_nu=1.3, omega_xi=1.1, corr="off")
+    f, g = _rand_state(25, 8, 1.0, 1.0, 1 / 3)
+    force = 1e-3 * (torch.rand(25, 3, generator=g, dtype=DT) - 0.5)
+    assert torch.allclose(C.collide(f, force, p_low), C.collide(f, force, p_off), atol=1e-16, rtol=1e-15)
+    # with the 3u^2 terms the corrections do not vanish (they are not grid corrections)
+    p_loc = oracle.Params(1, 1, 1, r=1.0, s=1.0, cs2=1 / 3, omega_nu=1.3, omega_xi=1.1, corr="local")
+    assert (C.collide(f, force, p_loc) - C.collide(f, force, p_off)).abs().max() > 1e-10
+
+
+def test_strain_rate_closed_form():
+    """The dense solve of App. D's 3x3 system equals its closed-form solution (eq. 65)."""
+    r, s = 0.5, 0.25
+    p = oracle.Params(1, 1, 1, r=r, s=s, omega_nu=1.5, omega_xi=1.2, corr="local")
+    f, _ = _rand_state(12, 9, r, s, p.cs2)
+    zero = torch.zeros(12, 3, dtype=DT)
+    _, info = C.collide(f, zero, p, return_info=True)
+    rho, u, mc = info["rho"], info["u"], info["mc"]
+    k200, k020, k002 = (mc[:, L.MIDX[m]] for m in ((2, 0, 0), (0, 2, 0), (0, 0, 2)))
+    R_b = k200 + k020 + k002 - 3 * p.cs2 * rho
+    R_s1, R_s2 = k200 - k020, k200 - k002
+    cs2, wn, wx = p.cs2, p.omega_nu, p.omega_xi
+    ux, uy, uz = u[:, 0], u[:, 1], u[:, 2]
+    C_sx = (-2 * cs2 / wn + (3 * cs2 - 1) / 2 + 1.5 * ux ** 2) * rho
+    C_bx = (-2 * cs2 / wx + (3 * cs2 - 1) / 2 + 1.5 * ux ** 2) * rho
+    C_sy = (2 * cs2 / wn - (3 * cs2 - r * r) / 2 - 1.5 * uy ** 2) * rho
+    C_by = (-2 * cs2 / wx + (3 * cs2 - r * r) / 2 + 1.5 * uy ** 2) * rho
+    C_sz = (2 * cs2 / wn - (3 * cs2 - s * s) / 2 - 1.5 * uz ** 2) * rho
+    C_bz = (-2 * cs2 / wx + (3 * cs2 - s * s) / 2 + 1.5 * uz ** 2) * rho
+    dxux = ((-C_sz * C_by * R_s1 - C_sy * (C_bz * R_s2 - C_sz * R_b))
+            / (-C_sx * C_sz * C_by - C_sy * (C_sx * C_bz - C_sz * C_bx)))
+    dyuy = (R_s1 - C_sx * dxux) / C_sy
+    dzuz = (R_s2 - C_sx * dxux) / C_sz
+    assert torch.allclose(info["du"], torch.stack([dxux, dyuy, dzuz], -1), atol=1e-14, rtol=1e-10)

@@ -1,0 +1,238 @@
+"""Dynamic pins of the oracle: what the Chapman-Enskog analysis (Sec. 2) fixes.
+
+* linear viscous decay of planar Taylor-Green vortices in the xy, xz and yz
+  planes at rate nu (k_a^2 + k_b^2) with nu from eq. 53 -- the corrections of
+  eq. 38-40 must make these equal on a cuboid grid; with the corrections off
+  (negative control) they are several times off;
+* shear waves decay at nu k^2 along every axis pair;
+* sound travels at cs and its amplitude decays at (2 nu/3 + xi/2) k^2;
+* mass and momentum budgets over many steps (periodic and bounce-back);
+* fully developed rectangular-duct flow against its Fourier series (the
+  generalisation of eq. 70);
+* local strain rates (eq. 49) against the derivative of the velocity.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import analytic as A
+from oracle import collision as C
+from oracle import lbm
+
+DT = torch.float64
+
+
+def _coords(p):
+    return {"x": torch.arange(p.nx, dtype=DT)[None, None, :],
+            "y": torch.arange(p.ny, dtype=DT)[None, :, None] * p.r,
+            "z": torch.arange(p.nz, dtype=DT)[:, None, None] * p.s}
+
+
+def _grid(r, s, axes, lam):
+    speeds = {"x": 1.0, "y": r, "z": s}
+    n = {"x": 1, "y": 1, "z": 1}
+    for a in axes:
+        n[a] = int(round(lam / speeds[a]))
+    return n
+
+
+def _fit_rate(ts, amps):
+    return -np.polyfit(np.asarray(ts, float), np.log(np.abs(np.asarray(amps))), 1)[0]
+
+
+def taylor_green_rate_ratio(r, s, plane, corr, omega=1.2, lam=32.0, steps=200, amp=1e-4):
+    a, b = plane
+    n = _grid(r, s, plane, lam)
+    p = oracle.Params(n["x"], n["y"], n["z"], r=r, s=s, omega_nu=omega, omega_xi=omega, corr=corr)
+    k = 2 * math.pi / lam
+    X = _coords(p)
+    ia, ib = "xyz".index(a), "xyz".index(b)
+    shape_a = (torch.sin(k * X[a]) * torch.cos(k * X[b])).expand(p.shape)
+    u = torch.zeros(3, *p.shape, dtype=DT)
+    u[ia] = amp * shape_a
+    u[ib] = (-amp * torch.cos(k * X[a]) * torch.sin(k * X[b])).expand(p.shape)
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), u, p)
+    ts, amps = [], []
+    for t in range(steps + 1):
+        if t >= 20 and t % 20 == 0:
+            _, uu = lbm.observables(f, p)
+            amps.append(((uu[ia] * shape_a).sum() / (shape_a * shape_a).sum()).item())
+            ts.append(t)
+        f = lbm.step(f, p)
+    nu = A.nu_from_omega(omega, p.cs2)
+    return _fit_rate(ts, amps) / A.taylor_green_decay_rate(nu, k, k)
+
+
+@pytest.mark.parametrize("r,s,steps", [(1.0, 0.5, 200), (0.5, 0.25, 300)])
+def test_taylor_green_planes_decay_at_nu(r, s, steps):
+    ratios = [taylor_green_rate_ratio(r, s, pl, "local", steps=steps) for pl in ("xy", "xz", "yz")]
+    for q in ratios:
+        assert abs(q - 1.0) < 0.025, ratios
+    assert max(ratios) - min(ratios) < 0.02, ratios
+
+
+@pytest.mark.parametrize("r,s", [(1.0, 0.5)])
+def test_taylor_green_without_corrections_is_anisotropic(r, s):
+    """Negative control: with the corrections off the normal-stress viscosity is wrong."""
+    ratios = [taylor_green_rate_ratio(r, s, pl, "off", steps=120) for pl in ("xy", "xz")]
+    assert min(abs(q - 1.0) for q in ratios) > 0.5, ratios
+
+
+def shear_rate_ratio(r, s, a, b, omega=1.3, lam=32.0, steps=160, amp=1e-4):
+    n = _grid(r, s, (b,), lam)
+    p = oracle.Params(n["x"], n["y"], n["z"], r=r, s=s, omega_nu=omega, omega_xi=1.0, corr="local")
+    k = 2 * math.pi / lam
+    X = _coords(p)
+    ia = "xyz".index(a)
+    shape = torch.sin(k * X[b]).expand(p.shape)
+    u = torch.zeros(3, *p.shape, dtype=DT)
+    u[ia] = amp * shape
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), u, p)
+    ts, amps = [], []
+    for t in range(steps + 1):
+        if t >= 20 and t % 20 == 0:
+            _, uu = lbm.observables(f, p)
+            amps.append(((uu[ia] * shape).sum() / (shape * shape).sum()).item())
+            ts.append(t)
+        f = lbm.step(f, p)
+    nu = A.nu_from_omega(omega, p.cs2)
+    return _fit_rate(ts, amps) / A.shear_decay_rate(nu, k)
+
+
+@pytest.mark.parametrize("a,b", [("x", "y"), ("y", "x"), ("x", "z"), ("z", "x"), ("y", "z"), ("z", "y")])
+def test_shear_waves_decay_at_nu(a, b):
+    q = shear_rate_ratio(0.5, 0.25, a, b)
+    assert abs(q - 1.0) < 0.02, q
+
+
+def sound_rates(r, s, axis, omega_nu=1.3, omega_xi=1.1, lam=48.0, steps=480, amp=1e-4):
+    """(measured decay / theory, measured angular frequency / (cs k)) of a standing wave."""
+    n = _grid(r, s, (axis,), lam)
+    p = oracle.Params(n["x"], n["y"], n["z"], r=r, s=s, omega_nu=omega_nu, omega_xi=omega_xi, corr="local")
+    k = 2 * math.pi / lam
+    X = _coords(p)
+    ia = "xyz".index(axis)
+    cshape = torch.cos(k * X[axis]).expand(p.shape)
+    sshape = torch.sin(k * X[axis]).expand(p.shape)
+    rho0 = 1.0 + amp * cshape
+    f = lbm.init_equilibrium(rho0, torch.zeros(3, *p.shape, dtype=DT), p)
+    cs = math.sqrt(p.cs2)
+    ts, energy, dens = [], [], []
+    for t in range(steps + 1):
+        rho, uu = lbm.observables(f, p)
+        a_rho = ((rho - 1.0) * cshape).sum() / (cshape * cshape).sum()
+        a_u = (uu[ia] * sshape).sum() / (sshape * sshape).sum()
+        ts.append(t)
+        energy.append((p.cs2 * a_rho ** 2 + a_u ** 2).item())
+        dens.append(a_rho.item())
+        f = lbm.step(f, p)
+    ts = np.asarray(ts, float)
+    rate = _fit_rate(ts[40:], np.sqrt(energy[40:]))
+    nu = A.nu_from_omega(omega_nu, p.cs2)
+    xi = A.xi_from_omega(omega_xi, p.cs2)
+    # frequency from the zero crossings of the density amplitude
+    d = np.asarray(dens)
+    zc = [i + d[i] / (d[i] - d[i + 1]) for i in range(len(d) - 1) if d[i] * d[i + 1] < 0]
+    half_period = np.mean(np.diff(zc))
+    w = math.pi / half_period
+    return rate / A.sound_decay_rate(nu, xi, k), w / (cs * k)
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "z"])
+def test_sound_speed_and_attenuation(axis):
+    q_rate, q_freq = sound_rates(1.0, 0.5, axis)
+    assert abs(q_freq - 1.0) < 0.01, q_freq
+    assert abs(q_rate - 1.0) < 0.03, q_rate
+
+
+def test_periodic_mass_and_momentum_budget():
+    p = oracle.Params(8, 6, 4, r=0.8, s=0.5, omega_nu=1.4, omega_xi=1.2, corr="local")
+    g = np.random.Generator(np.random.PCG64(11))
+    u = torch.tensor(0.02 * g.standard_normal((3, *p.shape)))
+    rho = torch.tensor(1.0 + 0.01 * g.standard_normal(p.shape))
+    force = (1e-5, -2e-5, 3e-6)
+    f = lbm.init_equilibrium(rho, u, p)
+    e = oracle.lattice.velocities(p.r, p.s)
+    m0 = f.sum()
+    j0 = torch.einsum("a...,ad->d", f, e)
+    steps = 60
+    f = lbm.run(f, p, steps, force=force)
+    assert abs((f.sum() - m0) / m0) < 1e-13
+    j = torch.einsum("a...,ad->d", f, e)
+    want = j0 + steps * p.n * torch.tensor(force, dtype=DT)
+    assert torch.allclose(j, want, atol=1e-12, rtol=0)
+
+
+def test_bounceback_keeps_mass():
+    p = oracle.Params(4, 8, 6, r=1.0, s=0.5, omega_nu=1.3, omega_xi=1.1, corr="local",
+                      bc_y="bounceback", bc_z="bounceback")
+    g = np.random.Generator(np.random.PCG64(12))
+    u = torch.tensor(0.01 * g.standard_normal((3, *p.shape)))
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), u, p)
+    m0 = f.sum()
+    f = lbm.run(f, p, 50, force=(1e-5, 0.0, 0.0))
+    assert abs((f.sum() - m0) / m0) < 1e-13
+
+
+@pytest.mark.parametrize("r,s,ny,nz", [(1.0, 0.5, 16, 24), (0.5, 1.0, 24, 12)])
+def test_duct_matches_series(r, s, ny, nz):
+    """Steady duct flow vs the series solution; walls half a cell outside the nodes."""
+    omega = 1.0
+    p = oracle.Params(1, ny, nz, r=r, s=s, omega_nu=omega, omega_xi=omega, corr="local",
+                      bc_y="bounceback", bc_z="bounceback")
+    nu = A.nu_from_omega(omega, p.cs2)
+    a, b = ny * r / 2, nz * s / 2
+    fx = A.duct_force_for_centre_velocity(1e-3, a, b, 1.0, nu)
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), torch.zeros(3, *p.shape, dtype=DT), p)
+    f = lbm.run(f, p, 1500, force=(fx, 0.0, 0.0))
+    rho, u = lbm.observables(f, p, force=(fx, 0.0, 0.0))
+    y = (np.arange(ny) + 0.5) * r - a
+    z = (np.arange(nz) + 0.5) * s - b
+    Z, Y = np.meshgrid(z, y, indexing="ij")
+    ref = A.duct_series(Y, Z, a, b, fx, 1.0, nu)
+    num = u[0, :, :, 0].numpy()
+    err = np.linalg.norm(num - ref) / np.linalg.norm(ref)
+    assert err < 0.02, err
+
+
+def test_strain_rates_match_velocity_gradient():
+    """d_a u_a from the non-equilibrium moments (eq. 49) vs the derivative of the velocity.
+
+    A planar Taylor-Green mode in the xz plane; both sides are projected on the
+    mode shape (so the derivative of u is exact) and averaged over one acoustic
+    period, which removes the sound wave that the equilibrium start excites.
+    """
+    r, s, lam = 0.5, 0.25, 16.0
+    p = oracle.Params(16, 1, 64, r=r, s=s, omega_nu=1.3, omega_xi=1.1, corr="local")
+    k = 2 * math.pi / lam
+    X = _coords(p)
+    sx = (torch.sin(k * X["x"]) * torch.cos(k * X["z"])).expand(p.shape)
+    sz = (torch.cos(k * X["x"]) * torch.sin(k * X["z"])).expand(p.shape)
+    cc = (torch.cos(k * X["x"]) * torch.cos(k * X["z"])).expand(p.shape)
+    amp = 1e-4
+    u = torch.zeros(3, *p.shape, dtype=DT)
+    u[0] = amp * sx
+    u[2] = -amp * sz
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), u, p)
+    f = lbm.run(f, p, 40)
+
+    def proj(a, sh):
+        return ((a * sh).sum() / (sh * sh).sum()).item()
+
+    period = int(round(lam / math.sqrt(p.cs2)))
+    acc = np.zeros(5)
+    for _ in range(period):
+        _, uu = lbm.observables(f, p)
+        _, info = C.collide(lbm.to_nodes(f), torch.zeros(p.n, 3, dtype=DT), p, return_info=True)
+        du = info["du"].T.reshape(3, *p.shape)
+        acc += [proj(du[0], cc), k * proj(uu[0], sx), proj(du[2], cc), k * proj(uu[2], sz),
+                du[1].abs().max().item()]
+        f = lbm.step(f, p)
+    acc /= period
+    assert abs(acc[0] / acc[1] - 1) < 0.03, acc
+    assert abs(acc[2] / acc[3] - 1) < 0.03, acc
+    assert acc[4] < 0.02 * abs(acc[1])          # no y dependence -> d_y u_y ~ 0
