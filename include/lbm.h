@@ -1,0 +1,195 @@
+/*
+ * C ABI of the MI355X cuboid D3Q27 central-moment lattice Boltzmann step.
+ *
+ * Method: the 3D cuboid central-moment LB scheme (3DCCM-LBM) of Yahia,
+ * Schupbach and Premnath, arXiv:2107.14774.  One step gathers the 27
+ * populations of a node (streaming, Sec. 3.2), takes raw moments (App. A),
+ * scales them by the grid aspect ratios r, s (App. B, eq. 59), shifts them to
+ * central moments about the force-shifted velocity of eq. 12 (App. C),
+ * relaxes them with the shear rate omega_nu, the bulk rate omega_xi and unit
+ * rates for every higher order, using the extended equilibria whose
+ * corrections cancel the grid-anisotropy and non-Galilean-invariant errors
+ * (Sec. 2.4, eq. 38-40) with strain rates from the local system of App. D
+ * (eq. 44-49), adds the body force through eq. 11c, and maps back (App. E-G).
+ * Streaming is periodic along x and periodic or halfway bounce-back (Sec. 4
+ * with a stationary wall) along y and z.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Lattice units: dx = dt = 1, dy = r, dz = s (Sec. 2.1).  Velocities and
+ *   forces are in x-lengths per step.
+ * - Node index n = (z * ny + y) * nx + x, x fastest.  Fields are SoA:
+ *   a scalar field is n_nodes values, a vector field is [3][n_nodes].
+ * - Direction order alpha = 0..26 is that of eq. 1a-c.  "Natural" population
+ *   arrays are [27][n_nodes] (double unless stated), f_alpha(x, t) after
+ *   streaming, i.e. the state from which eq. 12 reads rho and u.
+ * - A "state" is opaque device memory of lbm_state_bytes() bytes holding one
+ *   time level in the library's own layout: per direction an array of
+ *   lbm_state_stride() elements (float, or 16-bit for the reduced-storage
+ *   modes) holding scaled deviations from the rest equilibrium w_alpha rho0,
+ *   placed so that the next step can gather them (pull scheme).
+ * - Memory: the caller allocates every device buffer (PyTorch in the Python
+ *   binding); the library never allocates or frees device memory.  The only
+ *   host allocation is the handle.  All pointers to device memory must be
+ *   16-byte aligned.
+ * - Streams: hip_stream is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Every call only enqueues work and returns; no call synchronises
+ *   unless its comment says so.
+ * - Errors: every int-returning call returns LBM_OK (0) or a negative status;
+ *   lbm_last_error() returns a thread-local message for the last failure.
+ *   No C++ exception crosses the ABI.
+ */
+#ifndef CUBOID_LBM_H
+#define CUBOID_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument (sizes, rates, pointers, alignment) */
+  LBM_EHIP = -2,        /* HIP runtime or launch error; message from HIP */
+  LBM_ESTATE = -3,      /* handle/state misuse (e.g. NULL handle) */
+  LBM_ENONFINITE = -4   /* lbm_check_sums found a NaN/Inf total */
+};
+
+enum lbm_bc { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 };
+
+/* Population storage.  F32 stores (f - w rho0) in float.  F16 and BF16 store
+ * (f - w rho0) * sigma_alpha rounded to nearest even, sigma_alpha a power of
+ * two near 1 / w_alpha; every arithmetic step is FP32. */
+enum lbm_storage { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
+
+/* Extended-equilibrium corrections (Sec. 2.4 / App. D).
+ * OFF:     plain central-moment collision on the cuboid lattice;
+ * LOWMACH: theta without the 3u^2 terms (last remark of Sec. 2.4);
+ * LOCAL:   theta with the 3u^2 terms; the density-gradient (lambda) terms,
+ *          which need a non-local finite difference, are left out. */
+enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2 };
+
+typedef struct lbm_params {
+  int32_t nx, ny, nz;   /* grid nodes; each >= 1; ny, nz >= 2 on a bounce-back axis */
+  double r, s;          /* grid aspect ratios dy/dx and dz/dx (Sec. 2.1), > 0 */
+  double cs2;           /* squared sound speed; <= 0 selects min(r^2, s^2)/3 (end of Sec. 2.5) */
+  double omega_nu;      /* shear rate, 0 < omega_nu < 2: nu = cs2 (1/omega_nu - 1/2) (eq. 53) */
+  double omega_xi;      /* bulk rate, 0 < omega_xi < 2: xi = (2 cs2/3)(1/omega_xi - 1/2) */
+  double omega_hi;      /* rate of every third- and higher-order moment; must be 1 (App. D) */
+  int32_t bc_y, bc_z;   /* enum lbm_bc; x is always periodic */
+  int32_t storage;      /* enum lbm_storage */
+  int32_t corr;         /* enum lbm_corr */
+  double rho0;          /* reference density of the stored deviations, > 0 (usually 1) */
+  double force[3];      /* uniform body force used when no force field is passed */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Validate p and create a host-side handle holding the derived constants.
+ * Rejects (LBM_EINVAL): a size < 1 (or < 2 on a bounce-back axis), more than
+ * 2^31 - 1 nodes, r or s <= 0, a rate outside (0, 2), omega_hi != 1, a sound
+ * speed that makes a rest weight <= 0 (cs2 >= min(1, r^2, s^2)), unknown enum
+ * values, rho0 <= 0. */
+int lbm_create(const lbm_params* p, lbm_handle** out);
+void lbm_destroy(lbm_handle* h);
+
+/* Bytes of one state (27 * stride * element size) and the per-direction
+ * stride in elements (>= n_nodes, padded). */
+size_t lbm_state_bytes(const lbm_handle* h);
+int64_t lbm_state_stride(const lbm_handle* h);
+int64_t lbm_num_nodes(const lbm_handle* h);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* lbm_last_error(void);
+
+/* Initial state f(x, 0) = f_eq(rho, u) (+ perturb), eq. 9 mapped to
+ * populations (equivalently f_eq = Q^-1 m_eq, eq. 10 and eq. 56), computed in
+ * FP64 and rounded once into the storage format.
+ *   rho:     device double[n_nodes] or NULL (then rho = rho0 everywhere)
+ *   u:       device double[3][n_nodes] or NULL (then u = 0)
+ *   perturb: device double[27][n_nodes] added to f_eq, or NULL
+ *   state:   device, lbm_state_bytes(h) bytes, written. */
+int lbm_init(lbm_handle* h, void* state, const double* rho, const double* u,
+             const double* perturb, void* hip_stream);
+
+/* Write natural populations f (device double[27][n_nodes]) into a state,
+ * and read them back.  lbm_export(lbm_import(f)) returns f up to the
+ * rounding of the storage format. */
+int lbm_import(lbm_handle* h, void* state, const double* f, void* hip_stream);
+int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream);
+
+/* Advance nsteps >= 0 collide-and-stream steps (Sec. 3.2).  The current state
+ * is in state_a on entry; state_b is scratch of the same size (must differ
+ * from state_a).  On return the current state is in state_a when nsteps is
+ * even and in state_b when it is odd.
+ *   force: device float[3][n_nodes] per-node body force, or NULL to use
+ *          p->force for every node. */
+int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
+             const float* force, void* hip_stream);
+
+/* Observables of a state (eq. 12 / the last bullet of Sec. 3.2):
+ * rho = sum f, u = (sum f e + F/2) / rho.
+ *   rho:  device float[n_nodes] or NULL
+ *   u:    device float[3][n_nodes] or NULL
+ *   sums: device double[5] or NULL: total mass sum rho, momentum sum rho u
+ *         (3), kinetic energy sum rho |u|^2 / 2, each per node (multiply by
+ *         r s for a physical volume), accumulated in FP64.
+ *   force: as in lbm_step. */
+int lbm_moments(lbm_handle* h, const void* state, const float* force, float* rho,
+                float* u, double* sums, void* hip_stream);
+
+/* Synchronises hip_stream, copies the 5 sums to the host (out may be NULL)
+ * and returns LBM_ENONFINITE if any is NaN or Inf. */
+int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream);
+
+/* ---------------------------------------------------------------- adjoint
+ * The step maps a state h(t) to h(t+1) = C(S(h(t)); F): S streams (a
+ * permutation of the population slots), C collides every node.  The adjoint
+ * step is lambda(t) = [dh(t+1)/dh(t)]^T lambda(t+1), with lambda(t) indexed
+ * like the state's slots (float[27][stride], not scaled) and taken with
+ * respect to the real-valued populations (the rounding of 16-bit storage is
+ * not differentiated).
+ *
+ *   state_t:    the state h(t) before the step (read)
+ *   adj_in:     lambda(t+1), device float[27][stride] (read)
+ *   adj_out:    lambda(t),   device float[27][stride] (written; != adj_in)
+ *   force:      as in lbm_step
+ *   grad_force: device float[3][n_nodes] or NULL: += (dh(t+1)/dF)^T lambda(t+1)
+ *               for a per-node force field
+ *   grad_force_uniform: device double[3] or NULL: += the same summed over
+ *               nodes (gradient with respect to the uniform force). */
+int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
+                     float* adj_out, const float* force, float* grad_force,
+                     double* grad_force_uniform, void* hip_stream);
+
+/* lambda(T) from cotangents of the observables of a state (the transpose of
+ * lbm_moments' rho/u map):
+ *   g_rho: device float[n_nodes] or NULL;  g_u: device float[3][n_nodes] or NULL
+ *   adj:   device float[27][stride], written (overwritten, not accumulated)
+ *   grad_force: device float[3][n_nodes] or NULL, += d(u)/dF^T g_u (the F/2 of eq. 12). */
+int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force,
+                        const float* g_rho, const float* g_u, float* adj,
+                        float* grad_force, void* hip_stream);
+
+/* Cotangents of the initial fields from lambda(0) (transpose of lbm_init's
+ * f_eq(rho, u) map at the given rho, u):
+ *   adj:   device float[27][stride] (read)
+ *   rho, u: as in lbm_init (NULL = rho0 / zero)
+ *   g_rho: device double[n_nodes] or NULL, written
+ *   g_u:   device double[3][n_nodes] or NULL, written */
+int lbm_init_adjoint(lbm_handle* h, const float* adj, const double* rho,
+                     const double* u, double* g_rho, double* g_u, void* hip_stream);
+
+/* Reorder a slot-indexed float array (an adjoint) into natural order and
+ * back: natural[alpha][n] is the slot that the next step gathers as
+ * f_alpha at node n.  natural is device double[27][n_nodes]. */
+int lbm_adjoint_to_natural(lbm_handle* h, const float* slots, double* natural, void* hip_stream);
+int lbm_adjoint_from_natural(lbm_handle* h, const double* natural, float* slots, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUBOID_LBM_H */

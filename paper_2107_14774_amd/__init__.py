@@ -1,0 +1,11 @@
+"""MI355X-native fused collide-and-stream step of the 3D cuboid central-moment
+lattice Boltzmann scheme on a D3Q27 lattice (arXiv:2107.14774).
+
+The compute path is the HIP library ``liblbm.so`` (C ABI in include/lbm.h,
+sources in ``csrc/``); ``lbm`` is its Python binding and ``adjoint`` the
+autograd wrapper with checkpointing.
+"""
+
+from .lbm import (Lattice, Handle, relaxation_rates, lbm_create, lbm_init, lbm_import, lbm_export,  # noqa: F401
+                  lbm_step, lbm_moments, lbm_check_sums, lbm_step_adjoint, lbm_moments_adjoint,
+                  lbm_init_adjoint, lbm_adjoint_to_natural, lbm_adjoint_from_natural)

@@ -1,0 +1,256 @@
+// C ABI of the library: parameter validation, derived constants, launches.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int64_t padded_stride(int64_t n) {
+  // Round each direction array up to 256 elements, then shift it off a
+  // power-of-two pitch so the 27 streams do not start on the same channel.
+  int64_t s = (n + 255) / 256 * 256;
+  if ((s & (s - 1)) == 0 && s >= 65536) s += 256;
+  if (const char* env = std::getenv("LBM_STRIDE_PAD")) s += std::atoll(env);
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_create(const lbm_params* p, lbm_handle** out) {
+  g_err.clear();
+  if (p == nullptr || out == nullptr) return fail(LBM_EINVAL, "lbm_create: NULL argument");
+  *out = nullptr;
+  lbm_params q = *p;
+  if (q.nx < 1 || q.ny < 1 || q.nz < 1) return fail(LBM_EINVAL, "lbm_create: grid sizes must be >= 1");
+  if ((q.bc_y != LBM_PERIODIC && q.bc_y != LBM_BOUNCEBACK) || (q.bc_z != LBM_PERIODIC && q.bc_z != LBM_BOUNCEBACK))
+    return fail(LBM_EINVAL, "lbm_create: unknown boundary type");
+  if ((q.bc_y == LBM_BOUNCEBACK && q.ny < 2) || (q.bc_z == LBM_BOUNCEBACK && q.nz < 2))
+    return fail(LBM_EINVAL, "lbm_create: a bounce-back axis needs at least 2 nodes");
+  const int64_t n = (int64_t)q.nx * q.ny * q.nz;
+  if (n > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_create: more than 2^31-1 nodes");
+  if (!(q.r > 0.0) || !(q.s > 0.0)) return fail(LBM_EINVAL, "lbm_create: r and s must be > 0");
+  if (!(q.cs2 > 0.0)) q.cs2 = std::fmin(q.r * q.r, q.s * q.s) / 3.0;
+  if (!(q.cs2 < 1.0 && q.cs2 < q.r * q.r && q.cs2 < q.s * q.s))
+    return fail(LBM_EINVAL, "lbm_create: cs2 must be < min(1, r^2, s^2) (positive rest weights)");
+  if (!(q.omega_nu > 0.0 && q.omega_nu < 2.0) || !(q.omega_xi > 0.0 && q.omega_xi < 2.0))
+    return fail(LBM_EINVAL, "lbm_create: omega_nu and omega_xi must lie in (0, 2)");
+  if (q.omega_hi != 1.0) return fail(LBM_EINVAL, "lbm_create: only omega_hi = 1 is implemented");
+  if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
+  if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_LOCAL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
+  if (!(q.rho0 > 0.0)) return fail(LBM_EINVAL, "lbm_create: rho0 must be > 0");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(q.force[d])) return fail(LBM_EINVAL, "lbm_create: non-finite force");
+
+  lbm_handle* h = new (std::nothrow) lbm_handle();
+  if (h == nullptr) return fail(LBM_EINVAL, "lbm_create: out of host memory");
+  h->p = q;
+  h->n = n;
+  h->stride = padded_stride(n);
+  h->elem = q.storage == LBM_F32 ? 4 : 2;
+  h->bytes = (size_t)27 * (size_t)h->stride * h->elem;
+  h->block = 256;
+  if (const char* env = std::getenv("LBM_BLOCK")) {
+    const int b = std::atoi(env);
+    if (b == 64 || b == 128 || b == 256) h->block = b;
+  }
+
+  const double c[3] = {1.0, q.r, q.s};
+  clbm::Consts& k = h->k;
+  clbm::ConstsD& kd = h->kd;
+  k.nx = q.nx; k.ny = q.ny; k.nz = q.nz;
+  k.bb_y = q.bc_y == LBM_BOUNCEBACK;
+  k.bb_z = q.bc_z == LBM_BOUNCEBACK;
+  k.stride = h->stride;
+  k.n = n;
+  k.rho0 = (float)q.rho0; k.cs2 = (float)q.cs2; k.r = (float)q.r; k.s = (float)q.s;
+  k.omega_nu = (float)q.omega_nu; k.omega_xi = (float)q.omega_xi;
+  k.fx = (float)q.force[0]; k.fy = (float)q.force[1]; k.fz = (float)q.force[2];
+  kd.rho0 = q.rho0; kd.cs2 = q.cs2;
+  double W[3][3];
+  for (int d = 0; d < 3; ++d) {
+    const double c2 = c[d] * c[d];
+    k.c2[d] = (float)c2;
+    k.ic[d] = (float)(1.0 / c[d]);
+    k.ic2[d] = (float)(1.0 / c2);
+    kd.ic[d] = 1.0 / c[d];
+    kd.ic2[d] = 1.0 / c2;
+    kd.w0c[d] = 1.0 - q.cs2 / c2;
+    kd.w0s[d] = q.cs2 / (2.0 * c2);
+    k.w0c[d] = (float)kd.w0c[d];
+    k.w0s[d] = (float)kd.w0s[d];
+    W[d][0] = kd.w0s[d]; W[d][1] = kd.w0c[d]; W[d][2] = kd.w0s[d];
+  }
+  for (int a = 0; a < 27; ++a) {
+    const double w = W[0][clbm::kEx[a] + 1] * W[1][clbm::kEy[a] + 1] * W[2][clbm::kEz[a] + 1];
+    kd.w[a] = w;
+    // power-of-two scale near 1/w for the 16-bit formats (exact, so it adds no rounding)
+    const double sig = q.storage == LBM_F32 ? 1.0 : std::ldexp(1.0, (int)std::lround(-std::log2(w)));
+    k.sigma[a] = (float)sig;
+    k.inv_sigma[a] = (float)(1.0 / sig);
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+size_t lbm_state_bytes(const lbm_handle* h) { return h ? h->bytes : 0; }
+int64_t lbm_state_stride(const lbm_handle* h) { return h ? h->stride : 0; }
+int64_t lbm_num_nodes(const lbm_handle* h) { return h ? h->n : 0; }
+
+#define CHECK_HANDLE(h, name) \
+  if ((h) == nullptr) return fail(LBM_ESTATE, name ": NULL handle")
+#define CHECK_PTR(ptr, name, what) \
+  if ((ptr) != nullptr && !aligned(ptr)) return fail(LBM_EINVAL, name ": " what " is not 16-byte aligned")
+#define CHECK_REQ(ptr, name, what) \
+  if ((ptr) == nullptr) return fail(LBM_EINVAL, name ": " what " is NULL"); \
+  CHECK_PTR(ptr, name, what)
+
+int lbm_init(lbm_handle* h, void* state, const double* rho, const double* u, const double* perturb,
+             void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_init");
+  CHECK_REQ(state, "lbm_init", "state");
+  CHECK_PTR(rho, "lbm_init", "rho");
+  CHECK_PTR(u, "lbm_init", "u");
+  CHECK_PTR(perturb, "lbm_init", "perturb");
+  hipError_t e = clbm::launch_init(*h, state, rho, u, perturb, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init");
+}
+
+int lbm_import(lbm_handle* h, void* state, const double* f, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_import");
+  CHECK_REQ(state, "lbm_import", "state");
+  CHECK_REQ(f, "lbm_import", "f");
+  hipError_t e = clbm::launch_import(*h, state, f, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_import");
+}
+
+int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_export");
+  CHECK_REQ(state, "lbm_export", "state");
+  CHECK_REQ(f, "lbm_export", "f");
+  hipError_t e = clbm::launch_export(*h, state, f, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_export");
+}
+
+int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const float* force,
+             void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_step");
+  if (nsteps < 0) return fail(LBM_EINVAL, "lbm_step: nsteps < 0");
+  CHECK_REQ(state_a, "lbm_step", "state_a");
+  CHECK_REQ(state_b, "lbm_step", "state_b");
+  CHECK_PTR(force, "lbm_step", "force");
+  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step: state_a and state_b must differ");
+  void* bufs[2] = {state_a, state_b};
+  for (int32_t t = 0; t < nsteps; ++t) {
+    hipError_t e = clbm::launch_step(*h, bufs[t & 1], bufs[(t + 1) & 1], force, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step");
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, const void* state, const float* force, float* rho, float* u,
+                double* sums, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_moments");
+  CHECK_REQ(state, "lbm_moments", "state");
+  CHECK_PTR(force, "lbm_moments", "force");
+  CHECK_PTR(rho, "lbm_moments", "rho");
+  CHECK_PTR(u, "lbm_moments", "u");
+  CHECK_PTR(sums, "lbm_moments", "sums");
+  hipError_t e = clbm::launch_moments(*h, state, force, rho, u, sums, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments");
+}
+
+int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream) {
+  if (sums_device == nullptr) return fail(LBM_EINVAL, "lbm_check_sums: NULL sums");
+  double tmp[5];
+  hipError_t e = hipMemcpyAsync(tmp, sums_device, sizeof(tmp), hipMemcpyDeviceToHost, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_check_sums");
+  if (out_host) std::memcpy(out_host, tmp, sizeof(tmp));
+  for (double v : tmp)
+    if (!std::isfinite(v)) return fail(LBM_ENONFINITE, "lbm_check_sums: non-finite total");
+  return LBM_OK;
+}
+
+int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out,
+                     const float* force, float* grad_force, double* grad_force_uniform, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_step_adjoint");
+  CHECK_REQ(state_t, "lbm_step_adjoint", "state_t");
+  CHECK_REQ(adj_in, "lbm_step_adjoint", "adj_in");
+  CHECK_REQ(adj_out, "lbm_step_adjoint", "adj_out");
+  CHECK_PTR(force, "lbm_step_adjoint", "force");
+  CHECK_PTR(grad_force, "lbm_step_adjoint", "grad_force");
+  CHECK_PTR(grad_force_uniform, "lbm_step_adjoint", "grad_force_uniform");
+  if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, "lbm_step_adjoint: adj_in == adj_out");
+  hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
+                                           grad_force_uniform, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");
+}
+
+int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force, const float* g_rho,
+                        const float* g_u, float* adj, float* grad_force, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_moments_adjoint");
+  CHECK_REQ(state, "lbm_moments_adjoint", "state");
+  CHECK_REQ(adj, "lbm_moments_adjoint", "adj");
+  CHECK_PTR(force, "lbm_moments_adjoint", "force");
+  CHECK_PTR(g_rho, "lbm_moments_adjoint", "g_rho");
+  CHECK_PTR(g_u, "lbm_moments_adjoint", "g_u");
+  CHECK_PTR(grad_force, "lbm_moments_adjoint", "grad_force");
+  hipError_t e = clbm::launch_moments_adjoint(*h, state, force, g_rho, g_u, adj, grad_force,
+                                              (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_moments_adjoint");
+}
+
+int lbm_init_adjoint(lbm_handle* h, const float* adj, const double* rho, const double* u, double* g_rho,
+                     double* g_u, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_init_adjoint");
+  CHECK_REQ(adj, "lbm_init_adjoint", "adj");
+  CHECK_PTR(rho, "lbm_init_adjoint", "rho");
+  CHECK_PTR(u, "lbm_init_adjoint", "u");
+  CHECK_PTR(g_rho, "lbm_init_adjoint", "g_rho");
+  CHECK_PTR(g_u, "lbm_init_adjoint", "g_u");
+  hipError_t e = clbm::launch_init_adjoint(*h, adj, rho, u, g_rho, g_u, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_init_adjoint");
+}
+
+int lbm_adjoint_to_natural(lbm_handle* h, const float* slots, double* natural, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_adjoint_to_natural");
+  CHECK_REQ(slots, "lbm_adjoint_to_natural", "slots");
+  CHECK_REQ(natural, "lbm_adjoint_to_natural", "natural");
+  hipError_t e = clbm::launch_adjoint_natural(*h, slots, natural, 1, nullptr, nullptr, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_to_natural");
+}
+
+int lbm_adjoint_from_natural(lbm_handle* h, const double* natural, float* slots, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_adjoint_from_natural");
+  CHECK_REQ(slots, "lbm_adjoint_from_natural", "slots");
+  CHECK_REQ(natural, "lbm_adjoint_from_natural", "natural");
+  hipError_t e = clbm::launch_adjoint_natural(*h, nullptr, nullptr, 0, natural, slots, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_from_natural");
+}
+
+}  // extern "C"

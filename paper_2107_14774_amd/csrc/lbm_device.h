@@ -1,0 +1,332 @@
+// Device-side building blocks of the cuboid D3Q27 central-moment step (gfx950).
+//
+// Layout: a state is 27 arrays (one per direction of eq. 1a-c) of `stride`
+// elements; element n of array alpha is a population slot.  Slots hold the
+// deviation (f - w_alpha rho0) scaled by sigma_alpha (1 for FP32 storage).
+// Pull scheme: the step at node x gathers f_alpha(x) from slot
+// (alpha, x - ebar_alpha), or from (opposite(alpha), x) when x - ebar_alpha
+// lies beyond a bounce-back wall (Sec. 4, stationary wall), and writes its
+// post-collision populations to the slots (alpha, x) of the other buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace clbm {
+
+// eq. 1a-c: integer velocity components; e = (ebar_x, r ebar_y, s ebar_z).
+constexpr int kEx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int kEy[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int kEz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+
+constexpr int opposite_of(int a) {
+  for (int b = 0; b < 27; ++b)
+    if (kEx[b] == -kEx[a] && kEy[b] == -kEy[a] && kEz[b] == -kEz[a]) return b;
+  return -1;
+}
+
+// Direction with components (i-1, j-1, k-1), i, j, k in {0, 1, 2}.
+constexpr int dir_of(int i, int j, int k) {
+  for (int a = 0; a < 27; ++a)
+    if (kEx[a] == i - 1 && kEy[a] == j - 1 && kEz[a] == k - 1) return a;
+  return -1;
+}
+
+// Per-launch constants, passed by value as a kernel argument.
+struct Consts {
+  int nx, ny, nz;
+  int bb_y, bb_z;          // 1 = halfway bounce-back walls on that axis
+  int64_t stride;          // elements between direction arrays
+  int64_t n;               // nodes
+  float rho0, cs2, r, s;
+  float omega_nu, omega_xi;
+  float fx, fy, fz;        // uniform force
+  float c2[3];             // squared particle speeds 1, r^2, s^2
+  float ic[3], ic2[3];     // 1/c, 1/c^2 per axis
+  float w0c[3], w0s[3];    // rest weights per axis: centre 1 - cs2/c^2, side cs2/(2 c^2)
+  float sigma[27];         // storage scale per direction
+  float inv_sigma[27];
+};
+
+// FP64 copies for the one-time conversions (init, import, export).
+struct ConstsD {
+  double rho0, cs2;
+  double ic[3], ic2[3];
+  double w0c[3], w0s[3];
+  double w[27];            // w_alpha = product of the per-axis rest weights
+};
+
+// ----------------------------------------------------------------- storage
+template <int ST> struct Store;
+
+template <> struct Store<0> {
+  using T = float;
+  static __device__ __forceinline__ float load(const T* p) { return *p; }
+  static __device__ __forceinline__ T pack(float v) { return v; }
+};
+
+template <> struct Store<1> {
+  using T = __half;
+  static __device__ __forceinline__ float load(const T* p) { return __half2float(*p); }
+  static __device__ __forceinline__ T pack(float v) { return __float2half_rn(v); }
+};
+
+template <> struct Store<2> {
+  using T = __hip_bfloat16;
+  static __device__ __forceinline__ float load(const T* p) { return __bfloat162float(*p); }
+  static __device__ __forceinline__ T pack(float v) { return __float2bfloat16(v); }
+};
+
+// ----------------------------------------------------------------- indexing
+struct NodeCoord {
+  int x, y, z;
+  int xm, xp, ym, yp, zm, zp;  // periodic neighbours
+};
+
+__device__ __forceinline__ NodeCoord make_coord(int x, int y, int z, const Consts& k) {
+  NodeCoord c;
+  c.x = x; c.y = y; c.z = z;
+  c.xm = (x == 0) ? k.nx - 1 : x - 1;
+  c.xp = (x == k.nx - 1) ? 0 : x + 1;
+  c.ym = (y == 0) ? k.ny - 1 : y - 1;
+  c.yp = (y == k.ny - 1) ? 0 : y + 1;
+  c.zm = (z == 0) ? k.nz - 1 : z - 1;
+  c.zp = (z == k.nz - 1) ? 0 : z + 1;
+  return c;
+}
+
+// Slot from which the node gathers f_a: (a, x - ebar_a) or, across a wall, (opp(a), x).
+template <int A>
+__device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts& k) {
+  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
+  constexpr int opp = opposite_of(A);
+  const int xs = ex == 0 ? c.x : (ex > 0 ? c.xm : c.xp);
+  const int ys = ey == 0 ? c.y : (ey > 0 ? c.ym : c.yp);
+  const int zs = ez == 0 ? c.z : (ez > 0 ? c.zm : c.zp);
+  bool wall = false;
+  if (ey != 0) wall |= k.bb_y && (ey > 0 ? c.y == 0 : c.y == k.ny - 1);
+  if (ez != 0) wall |= k.bb_z && (ez > 0 ? c.z == 0 : c.z == k.nz - 1);
+  const int64_t node = ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;
+  const int64_t src = ((int64_t)zs * k.ny + ys) * k.nx + xs;
+  return wall ? (int64_t)opp * k.stride + node : (int64_t)A * k.stride + src;
+}
+
+template <int A, int ST>
+__device__ __forceinline__ float gather_dev(const typename Store<ST>::T* __restrict__ src,
+                                            const NodeCoord& c, const Consts& k) {
+  const float v = Store<ST>::load(src + gather_slot<A>(c, k));
+  return ST == 0 ? v : v * k.inv_sigma[A];
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_all(const typename Store<ST>::T* __restrict__ src,
+                                           const NodeCoord& c, const Consts& k, float (&df)[27]) {
+  df[A] = gather_dev<A, ST>(src, c, k);
+  if constexpr (A + 1 < 27) gather_all<ST, A + 1>(src, c, k, df);
+}
+
+// ----------------------------------------------------------------- moments
+// Raw moments of order <= 2 of the deviations, in cubic (ebar) units,
+// factorised over z, then y, then x (App. A restricted to orders <= 2).
+struct LowMoments {
+  float m000, m100, m010, m001, m200, m020, m002, m110, m101, m011;
+};
+
+__device__ __forceinline__ LowMoments low_moments(const float (&df)[27]) {
+  float Z0[3][3], Z1[3][3], Z2[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float m = df[dir_of(i, j, 0)], o = df[dir_of(i, j, 1)], p = df[dir_of(i, j, 2)];
+      Z2[i][j] = p + m;
+      Z1[i][j] = p - m;
+      Z0[i][j] = Z2[i][j] + o;
+    }
+  float Y00[3], Y10[3], Y20[3], Y01[3], Y11[3], Y02[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Y20[i] = Z0[i][2] + Z0[i][0];
+    Y10[i] = Z0[i][2] - Z0[i][0];
+    Y00[i] = Y20[i] + Z0[i][1];
+    Y11[i] = Z1[i][2] - Z1[i][0];
+    Y01[i] = Z1[i][0] + Z1[i][1] + Z1[i][2];
+    Y02[i] = Z2[i][0] + Z2[i][1] + Z2[i][2];
+  }
+  LowMoments M;
+  M.m200 = Y00[2] + Y00[0];
+  M.m100 = Y00[2] - Y00[0];
+  M.m000 = M.m200 + Y00[1];
+  M.m110 = Y10[2] - Y10[0];
+  M.m010 = Y10[0] + Y10[1] + Y10[2];
+  M.m020 = Y20[0] + Y20[1] + Y20[2];
+  M.m101 = Y01[2] - Y01[0];
+  M.m001 = Y01[0] + Y01[1] + Y01[2];
+  M.m011 = Y11[0] + Y11[1] + Y11[2];
+  M.m002 = Y02[0] + Y02[1] + Y02[2];
+  return M;
+}
+
+// ----------------------------------------------------------------- per-axis vectors
+// Along one axis (speed c, velocity u), entries for ebar = -1, 0, +1:
+//   D  = E(u) - E(0): equilibrium weights minus rest weights
+//   A0, A1, A2: populations of the unit central moments (1,0,0), (0,1,0),
+//   (0,0,1) of that axis (the 1D inverse of the raw/central moment maps).
+struct AxisVec {
+  float W0[3], E[3], D[3], A0[3], A1[3], A2[3];
+};
+
+__device__ __forceinline__ AxisVec axis_vectors(float u, int d, const Consts& k) {
+  AxisVec v;
+  const float ic = k.ic[d], ic2 = k.ic2[d];
+  const float q = u * u * ic2, h = u * ic;
+  v.W0[0] = k.w0s[d]; v.W0[1] = k.w0c[d]; v.W0[2] = k.w0s[d];
+  v.D[0] = 0.5f * (q - h); v.D[1] = -q; v.D[2] = 0.5f * (q + h);
+  v.A0[0] = v.D[0]; v.A0[1] = 1.0f - q; v.A0[2] = v.D[2];
+  const float uic2 = u * ic2, hic = 0.5f * ic;
+  v.A1[0] = uic2 - hic; v.A1[1] = -2.0f * uic2; v.A1[2] = uic2 + hic;
+  v.A2[0] = 0.5f * ic2; v.A2[1] = -ic2; v.A2[2] = 0.5f * ic2;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v.E[i] = v.W0[i] + v.D[i];
+  return v;
+}
+
+// ----------------------------------------------------------------- collision
+// Post-collision deviations of one node (the collide bullets of Sec. 3.2 with
+// the App. D collision, every higher-order rate 1), in the deviation form
+//   f~ - w rho0 = d_rho E(x)E(x)E + rho0 [D(x)E(x)E + W0(x)D(x)E + W0(x)W0(x)D]
+//                 + sum over the first/second-order non-equilibrium central
+//                   moments Delta_mnp of Delta_mnp A_m(x)A_n(x)A_p,
+// which equals P^-1 S^-1 F(-u) applied to the post-collision central moments.
+template <int CORR>
+__device__ __forceinline__ void collide_node(const float (&df)[27], float fx, float fy, float fz,
+                                             const Consts& k, float (&out)[27]) {
+  const LowMoments M = low_moments(df);
+  const float r = k.r, s = k.s, cs2 = k.cs2, rho0 = k.rho0;
+  const float drho = M.m000;
+  const float jx = M.m100, jy = r * M.m010, jz = s * M.m001;
+  const float Pxx = M.m200, Pyy = k.c2[1] * M.m020, Pzz = k.c2[2] * M.m002;
+  const float Pxy = r * M.m110, Pxz = s * M.m101, Pyz = (r * s) * M.m011;
+  const float rho = rho0 + drho;
+  const float irho = 1.0f / rho;
+  const float ux = (jx + 0.5f * fx) * irho;
+  const float uy = (jy + 0.5f * fy) * irho;
+  const float uz = (jz + 0.5f * fz) * irho;
+  const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const float uF_x = ux * fx, uF_y = uy * fy, uF_z = uz * fz;
+
+  // non-equilibrium parts of the combined second-order central moments (eq. 45-46, e_rho = 0)
+  const float Rb = (Pxx + Pyy + Pzz) - 3.0f * cs2 * drho - rho * (uxx + uyy + uzz) + (uF_x + uF_y + uF_z);
+  const float Rs1 = (Pxx - Pyy) - rho * (uxx - uyy) + (uF_x - uF_y);
+  const float Rs2 = (Pxx - Pzz) - rho * (uxx - uzz) + (uF_x - uF_z);
+  const float kxy = Pxy - rho * ux * uy + 0.5f * (ux * fy + uy * fx);
+  const float kxz = Pxz - rho * ux * uz + 0.5f * (ux * fz + uz * fx);
+  const float kyz = Pyz - rho * uy * uz + 0.5f * (uy * fz + uz * fy);
+
+  const float wn = k.omega_nu, wx = k.omega_xi;
+  float c2d1 = 0.0f, c2d2 = 0.0f, c2s = 0.0f;
+  if constexpr (CORR != 0) {
+    // strain-rate system of App. D divided by rho: C/rho . (rho du) = R
+    const float g = (CORR == 2) ? 1.5f : 0.0f;
+    const float inw = 2.0f * cs2 / wn, inx = 2.0f * cs2 / wx;
+    const float ax = 0.5f * (3.0f * cs2 - 1.0f), ay = 0.5f * (3.0f * cs2 - k.c2[1]), az = 0.5f * (3.0f * cs2 - k.c2[2]);
+    const float csx = -inw + ax + g * uxx, cbx = -inx + ax + g * uxx;
+    const float csy = inw - ay - g * uyy, cby = -inx + ay + g * uyy;
+    const float csz = inw - az - g * uzz, cbz = -inx + az + g * uzz;
+    const float det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
+    const float gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) / det;
+    const float gy = (Rs1 - csx * gx) / csy;
+    const float gz = (Rs2 - csx * gx) / csz;
+    // theta / rho of eq. 38-40 (App. D), times rho du
+    const float hn = 1.0f / wn - 0.5f, hx = 1.0f / wx - 0.5f;
+    const float g3 = (CORR == 2) ? 3.0f : 0.0f;
+    const float tx = -(g3 * uxx + 2.0f * ax), ty = -(g3 * uyy + 2.0f * ay), tz = -(g3 * uzz + 2.0f * az);
+    c2d1 = hn * (tx * gx - ty * gy);
+    c2d2 = hn * (tx * gx - tz * gz);
+    c2s = hx * (tx * gx + ty * gy + tz * gz);
+  }
+  // relaxation of the combined moments, then segregation (B^-1 of App. D)
+  const float D2s = (1.0f - wx) * Rb + wx * c2s;
+  const float D2d1 = (1.0f - wn) * Rs1 + wn * c2d1;
+  const float D2d2 = (1.0f - wn) * Rs2 + wn * c2d2;
+  constexpr float third = 1.0f / 3.0f;
+  const float Dxx = (D2s + D2d1 + D2d2) * third;
+  const float Dyy = (D2s - 2.0f * D2d1 + D2d2) * third;
+  const float Dzz = (D2s + D2d1 - 2.0f * D2d2) * third;
+  const float Dxy = (1.0f - wn) * kxy, Dxz = (1.0f - wn) * kxz, Dyz = (1.0f - wn) * kyz;
+  const float Dx = 0.5f * fx, Dy = 0.5f * fy, Dz = 0.5f * fz;  // post-collision k_100 = F/2
+
+  const AxisVec X = axis_vectors(ux, 0, k);
+  const AxisVec Y = axis_vectors(uy, 1, k);
+  const AxisVec Z = axis_vectors(uz, 2, k);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float eE = drho * X.E[i] + rho0 * X.D[i];
+    const float eW = rho0 * X.W0[i];
+    const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
+    const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
+    const float a2 = Dyy * X.A0[i];
+    const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
+    const float b1 = Dyz * X.A0[i];
+    const float c0 = Dzz * X.A0[i];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float QE = eE * Y.E[j] + eW * Y.D[j];
+      const float QW = eW * Y.W0[j];
+      const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j] + a2 * Y.A2[j];
+      const float Q1 = b0 * Y.A0[j] + b1 * Y.A1[j];
+      const float Q2 = c0 * Y.A0[j];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        out[dir_of(i, j, l)] = QE * Z.E[l] + QW * Z.D[l] + Q0 * Z.A0[l] + Q1 * Z.A1[l] + Q2 * Z.A2[l];
+    }
+  }
+}
+
+// Exact local conservation for FP32 storage.  In exact arithmetic the
+// collision keeps the mass and adds F to the momentum; in FP32 the rounding
+// of the 27 outputs leaves a residual of a few 1e-9 per node that repeats
+// almost unchanged from step to step on a slowly varying flow and therefore
+// accumulates.  The residual, formed in FP64 from the float inputs and
+// outputs, goes into the rest population (mass) and the three axis pairs
+// f_{1,2}, f_{3,4}, f_{5,6} (momentum, antisymmetrically, so their mass and
+// second moments are unchanged).
+__device__ __forceinline__ void conserve(const float (&df)[27], float fx, float fy, float fz,
+                                         const Consts& k, float (&out)[27]) {
+  double m_in = 0.0, x_in = 0.0, y_in = 0.0, z_in = 0.0;
+  double m_out = 0.0, x_out = 0.0, y_out = 0.0, z_out = 0.0;
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    const double vi = (double)df[a], vo = (double)out[a];
+    m_in += vi;
+    m_out += vo;
+    if (kEx[a] != 0) { x_in += kEx[a] * vi; x_out += kEx[a] * vo; }
+    if (kEy[a] != 0) { y_in += kEy[a] * vi; y_out += kEy[a] * vo; }
+    if (kEz[a] != 0) { z_in += kEz[a] * vi; z_out += kEz[a] * vo; }
+  }
+  // momentum residuals in ebar units: (j + F) / c_d - sum out ebar_d
+  const double rx = (x_in - x_out) + (double)fx;
+  const double ry = (y_in - y_out) + (double)fy / (double)k.r;
+  const double rz = (z_in - z_out) + (double)fz / (double)k.s;
+  out[0] = (float)((double)out[0] + (m_in - m_out));
+  out[1] = (float)((double)out[1] + 0.5 * rx);
+  out[2] = (float)((double)out[2] - 0.5 * rx);
+  out[3] = (float)((double)out[3] + 0.5 * ry);
+  out[4] = (float)((double)out[4] - 0.5 * ry);
+  out[5] = (float)((double)out[5] + 0.5 * rz);
+  out[6] = (float)((double)out[6] - 0.5 * rz);
+}
+
+// XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs
+// in turn; renumber so that each XCD walks one contiguous range of tiles
+// (neighbouring rows share cache lines through that XCD's L2).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  constexpr int64_t X = 8;
+  const int64_t per = nb / X, rem = nb % X;
+  const int64_t xcd = b % X, i = b / X;
+  return xcd < rem ? xcd * (per + 1) + i : rem * (per + 1) + (xcd - rem) * per + i;
+}
+
+}  // namespace clbm

@@ -1,0 +1,287 @@
+// Forward kernels: fused collide-and-stream step, initialisation,
+// import/export of natural populations, observables with FP64 totals.
+#include "lbm_internal.h"
+
+namespace clbm {
+
+// ------------------------------------------------------------------ step
+// One thread per node, pull scheme: gather 27 slots of `src`, collide, write
+// the node's 27 slots of `dst` (coalesced along x).
+template <int ST, int CORR>
+__global__ __launch_bounds__(256) void k_step(const typename Store<ST>::T* __restrict__ src,
+                                              typename Store<ST>::T* __restrict__ dst,
+                                              const float* __restrict__ force, Consts k, int bpr) {
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int bxi = (int)(lb % bpr);
+  const int64_t row = lb / bpr;
+  const int y = (int)(row % k.ny), z = (int)(row / k.ny);
+  const int x = bxi * (int)blockDim.x + (int)threadIdx.x;
+  if (x >= k.nx) return;
+  const NodeCoord c = make_coord(x, y, z, k);
+  float df[27];
+  gather_all<ST>(src, c, k, df);
+  const int64_t node = ((int64_t)z * k.ny + y) * k.nx + x;
+  float fx = k.fx, fy = k.fy, fz = k.fz;
+  if (force != nullptr) {
+    fx = force[node];
+    fy = force[k.n + node];
+    fz = force[2 * k.n + node];
+  }
+  float out[27];
+  collide_node<CORR>(df, fx, fy, fz, k, out);
+  if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
+#pragma unroll
+  for (int a = 0; a < 27; ++a)
+    dst[a * k.stride + node] = Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]);
+}
+
+// ------------------------------------------------------------------ init / import / export
+// FP64 equilibrium deviation f_eq(rho, u) - w rho0 of one node, written
+// without cancellation: d_rho E(x)E(x)E + rho0 [D(x)E(x)E + W0(x)D(x)E + W0(x)W0(x)D].
+struct AxisD {
+  double W0[3], E[3], D[3];
+};
+
+__device__ __forceinline__ AxisD axis_d(double u, int d, const ConstsD& kd) {
+  AxisD v;
+  const double q = u * u * kd.ic2[d], h = u * kd.ic[d];
+  v.W0[0] = kd.w0s[d]; v.W0[1] = kd.w0c[d]; v.W0[2] = kd.w0s[d];
+  v.D[0] = 0.5 * (q - h); v.D[1] = -q; v.D[2] = 0.5 * (q + h);
+  for (int i = 0; i < 3; ++i) v.E[i] = v.W0[i] + v.D[i];
+  return v;
+}
+
+__device__ __forceinline__ NodeCoord coord_of(int64_t node, const Consts& k) {
+  const int x = (int)(node % k.nx);
+  const int64_t t = node / k.nx;
+  const int y = (int)(t % k.ny), z = (int)(t / k.ny);
+  return make_coord(x, y, z, k);
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void init_store(typename Store<ST>::T* __restrict__ dst, const NodeCoord& c,
+                                           int64_t node, const AxisD& X, const AxisD& Y, const AxisD& Z,
+                                           double drho, const double* __restrict__ perturb,
+                                           const Consts& k, const ConstsD& kd) {
+  constexpr int i = kEx[A] + 1, j = kEy[A] + 1, l = kEz[A] + 1;
+  double v = drho * X.E[i] * Y.E[j] * Z.E[l]
+           + kd.rho0 * (X.D[i] * Y.E[j] * Z.E[l] + X.W0[i] * Y.D[j] * Z.E[l] + X.W0[i] * Y.W0[j] * Z.D[l]);
+  if (perturb != nullptr) v += perturb[A * k.n + node];
+  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[A]));
+  if constexpr (A + 1 < 27) init_store<ST, A + 1>(dst, c, node, X, Y, Z, drho, perturb, k, kd);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_init(typename Store<ST>::T* __restrict__ dst,
+                                              const double* __restrict__ rho, const double* __restrict__ u,
+                                              const double* __restrict__ perturb, Consts k, ConstsD kd) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const NodeCoord c = coord_of(node, k);
+    const double rn = rho ? rho[node] : kd.rho0;
+    const double ux = u ? u[node] : 0.0, uy = u ? u[k.n + node] : 0.0, uz = u ? u[2 * k.n + node] : 0.0;
+    const AxisD X = axis_d(ux, 0, kd), Y = axis_d(uy, 1, kd), Z = axis_d(uz, 2, kd);
+    init_store<ST>(dst, c, node, X, Y, Z, rn - kd.rho0, perturb, k, kd);
+  }
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void import_store(typename Store<ST>::T* __restrict__ dst, const NodeCoord& c,
+                                             int64_t node, const double* __restrict__ f,
+                                             const Consts& k, const ConstsD& kd) {
+  const double v = f[A * k.n + node] - kd.w[A] * kd.rho0;
+  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[A]));
+  if constexpr (A + 1 < 27) import_store<ST, A + 1>(dst, c, node, f, k, kd);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_import(typename Store<ST>::T* __restrict__ dst,
+                                                const double* __restrict__ f, Consts k, ConstsD kd) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    import_store<ST>(dst, coord_of(node, k), node, f, k, kd);
+  }
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void export_load(const typename Store<ST>::T* __restrict__ src, const NodeCoord& c,
+                                            int64_t node, double* __restrict__ f, const Consts& k,
+                                            const ConstsD& kd) {
+  const double v = (double)Store<ST>::load(src + gather_slot<A>(c, k)) / (double)k.sigma[A];
+  f[A * k.n + node] = kd.w[A] * kd.rho0 + v;
+  if constexpr (A + 1 < 27) export_load<ST, A + 1>(src, c, node, f, k, kd);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_export(const typename Store<ST>::T* __restrict__ src,
+                                                double* __restrict__ f, Consts k, ConstsD kd) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    export_load<ST>(src, coord_of(node, k), node, f, k, kd);
+  }
+}
+
+// ------------------------------------------------------------------ observables
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void k_sums_reset(double* sums, double mass0) {
+  if (threadIdx.x < 5) sums[threadIdx.x] = threadIdx.x == 0 ? mass0 : 0.0;
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_moments(const typename Store<ST>::T* __restrict__ src,
+                                                 const float* __restrict__ force, float* __restrict__ rho_out,
+                                                 float* __restrict__ u_out, double* __restrict__ sums, Consts k) {
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const NodeCoord c = coord_of(node, k);
+    float df[27];
+    gather_all<ST>(src, c, k, df);
+    const LowMoments M = low_moments(df);
+    float fx = k.fx, fy = k.fy, fz = k.fz;
+    if (force != nullptr) {
+      fx = force[node];
+      fy = force[k.n + node];
+      fz = force[2 * k.n + node];
+    }
+    const float rho = k.rho0 + M.m000;
+    const float px = M.m100 + 0.5f * fx, py = k.r * M.m010 + 0.5f * fy, pz = k.s * M.m001 + 0.5f * fz;
+    const float ux = px / rho, uy = py / rho, uz = pz / rho;
+    if (rho_out) rho_out[node] = rho;
+    if (u_out) {
+      u_out[node] = ux;
+      u_out[k.n + node] = uy;
+      u_out[2 * k.n + node] = uz;
+    }
+    // totals from FP64 sums of the stored values (no FP32 rounding of the node sums)
+    double dm = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
+#pragma unroll
+    for (int a = 0; a < 27; ++a) {
+      const double v = (double)df[a];
+      dm += v;
+      if (kEx[a] != 0) dx += kEx[a] * v;
+      if (kEy[a] != 0) dy += kEy[a] * v;
+      if (kEz[a] != 0) dz += kEz[a] * v;
+    }
+    const double qx = dx + 0.5 * (double)fx, qy = (double)k.r * dy + 0.5 * (double)fy;
+    const double qz = (double)k.s * dz + 0.5 * (double)fz;
+    acc[0] += dm;
+    acc[1] += qx;
+    acc[2] += qy;
+    acc[3] += qz;
+    acc[4] += 0.5 * (qx * qx + qy * qy + qz * qz) / ((double)k.rho0 + dm);
+  }
+  if (sums == nullptr) return;
+  __shared__ double part[5][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) part[q][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int nw = (blockDim.x + 63) / 64;
+    double v = 0.0;
+    for (int w = 0; w < nw; ++w) v += part[threadIdx.x][w];
+    atomicAdd(&sums[threadIdx.x], v);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_for(int64_t n, int block, int64_t cap) {
+  int64_t g = (n + block - 1) / block;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+  const int block = h.block;
+  const int bpr = (h.p.nx + block - 1) / block;
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nb), blk(block);
+  const int corr = h.p.corr;
+  switch (h.p.storage) {
+    case LBM_F32: {
+      using T = Store<0>::T;
+      auto s = (const T*)src; auto d = (T*)dst;
+      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<0, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<0, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else hipLaunchKernelGGL((k_step<0, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      break;
+    }
+    case LBM_F16: {
+      using T = Store<1>::T;
+      auto s = (const T*)src; auto d = (T*)dst;
+      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<1, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<1, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else hipLaunchKernelGGL((k_step<1, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      break;
+    }
+    default: {
+      using T = Store<2>::T;
+      auto s = (const T*)src; auto d = (T*)dst;
+      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<2, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<2, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      else hipLaunchKernelGGL((k_step<2, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
+                       const double* perturb, hipStream_t st) {
+  const int g = grid_for(h.n, 256, 65536);
+  switch (h.p.storage) {
+    case LBM_F32: hipLaunchKernelGGL(k_init<0>, g, 256, 0, st, (float*)dst, rho, u, perturb, h.k, h.kd); break;
+    case LBM_F16: hipLaunchKernelGGL(k_init<1>, g, 256, 0, st, (Store<1>::T*)dst, rho, u, perturb, h.k, h.kd); break;
+    default: hipLaunchKernelGGL(k_init<2>, g, 256, 0, st, (Store<2>::T*)dst, rho, u, perturb, h.k, h.kd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const lbm_handle& h, void* dst, const double* f, hipStream_t st) {
+  const int g = grid_for(h.n, 256, 65536);
+  switch (h.p.storage) {
+    case LBM_F32: hipLaunchKernelGGL(k_import<0>, g, 256, 0, st, (float*)dst, f, h.k, h.kd); break;
+    case LBM_F16: hipLaunchKernelGGL(k_import<1>, g, 256, 0, st, (Store<1>::T*)dst, f, h.k, h.kd); break;
+    default: hipLaunchKernelGGL(k_import<2>, g, 256, 0, st, (Store<2>::T*)dst, f, h.k, h.kd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const lbm_handle& h, const void* src, double* f, hipStream_t st) {
+  const int g = grid_for(h.n, 256, 65536);
+  switch (h.p.storage) {
+    case LBM_F32: hipLaunchKernelGGL(k_export<0>, g, 256, 0, st, (const float*)src, f, h.k, h.kd); break;
+    case LBM_F16: hipLaunchKernelGGL(k_export<1>, g, 256, 0, st, (const Store<1>::T*)src, f, h.k, h.kd); break;
+    default: hipLaunchKernelGGL(k_export<2>, g, 256, 0, st, (const Store<2>::T*)src, f, h.k, h.kd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const lbm_handle& h, const void* src, const float* force, float* rho,
+                          float* u, double* sums, hipStream_t st) {
+  if (sums) {
+    hipLaunchKernelGGL(k_sums_reset, 1, 64, 0, st, sums, (double)h.n * h.kd.rho0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int g = grid_for(h.n, 256, 4096);
+  switch (h.p.storage) {
+    case LBM_F32: hipLaunchKernelGGL(k_moments<0>, g, 256, 0, st, (const float*)src, force, rho, u, sums, h.k); break;
+    case LBM_F16: hipLaunchKernelGGL(k_moments<1>, g, 256, 0, st, (const Store<1>::T*)src, force, rho, u, sums, h.k); break;
+    default: hipLaunchKernelGGL(k_moments<2>, g, 256, 0, st, (const Store<2>::T*)src, force, rho, u, sums, h.k); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace clbm

@@ -1,0 +1,42 @@
+// Host-side handle and kernel launchers shared by the translation units of
+// the library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+struct lbm_handle {
+  lbm_params p;
+  clbm::Consts k;
+  clbm::ConstsD kd;
+  int64_t n;         // nodes
+  int64_t stride;    // elements per direction array
+  size_t elem;       // bytes per stored element
+  size_t bytes;      // bytes of one state
+  int block;         // threads per block of the node kernels
+};
+
+namespace clbm {
+
+hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st);
+hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
+                       const double* perturb, hipStream_t st);
+hipError_t launch_import(const lbm_handle& h, void* dst, const double* f, hipStream_t st);
+hipError_t launch_export(const lbm_handle& h, const void* src, double* f, hipStream_t st);
+hipError_t launch_moments(const lbm_handle& h, const void* src, const float* force, float* rho,
+                          float* u, double* sums, hipStream_t st);
+hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in,
+                               float* adj_out, const float* force, float* grad_force,
+                               double* grad_force_uniform, hipStream_t st);
+hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force,
+                                  const float* g_rho, const float* g_u, float* adj,
+                                  float* grad_force, hipStream_t st);
+hipError_t launch_init_adjoint(const lbm_handle& h, const float* adj, const double* rho,
+                               const double* u, double* g_rho, double* g_u, hipStream_t st);
+hipError_t launch_adjoint_natural(const lbm_handle& h, const float* slots, double* natural,
+                                  int to_natural, const double* natural_in, float* slots_out,
+                                  hipStream_t st);
+
+}  // namespace clbm

@@ -1,0 +1,242 @@
+"""Python binding of the cuboid D3Q27 central-moment step (arXiv:2107.14774).
+
+The functions ``lbm_create`` ... ``lbm_adjoint_from_natural`` mirror the C
+entry points of include/lbm.h one to one and only marshal arguments: PyTorch
+tensors supply device memory and the current HIP stream, every step of the
+method runs in the HIP kernels of ``liblbm.so``.  ``Lattice`` bundles a
+handle with state allocation for convenience.
+
+Tensor conventions (see include/lbm.h): fields are [3, nz, ny, nx] / [nz, ny,
+nx] (SoA, x fastest), natural populations [27, nz, ny, nx] float64, states
+are opaque uint8 tensors of ``lbm_state_bytes`` bytes, adjoints float32
+[27, stride].
+"""
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+_ABI_F32 = torch.float32
+_ABI_F64 = torch.float64
+
+
+def relaxation_rates(nu, xi, cs2):
+    """(omega_nu, omega_xi) from shear and bulk viscosity (eq. 53)."""
+    return 1.0 / (nu / cs2 + 0.5), 1.0 / (1.5 * xi / cs2 + 0.5)
+
+
+class Handle:
+    """Owns an ``lbm_handle*``."""
+
+    def __init__(self, raw, params):
+        self.raw = raw
+        self.params = params
+
+    def __del__(self):
+        raw, self.raw = getattr(self, "raw", None), None
+        if raw:
+            try:
+                _lib.load().lbm_destroy(raw)
+            except Exception:  # interpreter shutdown
+                pass
+
+    @property
+    def n(self):
+        return int(_lib.load().lbm_num_nodes(self.raw))
+
+    @property
+    def stride(self):
+        return int(_lib.load().lbm_state_stride(self.raw))
+
+    @property
+    def state_bytes(self):
+        return int(_lib.load().lbm_state_bytes(self.raw))
+
+
+def _require(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name}: need a contiguous CUDA {dtype} tensor of {numel} elements, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return t
+
+
+def _state(h, t, name="state"):
+    if t is None or not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() < h.state_bytes:
+        raise ValueError(f"{name}: need a contiguous CUDA buffer of >= {h.state_bytes} bytes")
+    return t
+
+
+def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, omega_hi=1.0,
+               bc_y="periodic", bc_z="periodic", storage="f32", corr="local", rho0=1.0,
+               force=(0.0, 0.0, 0.0)):
+    lib = _lib.load()
+    p = _lib.LbmParams()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.r, p.s, p.cs2 = r, s, cs2
+    p.omega_nu, p.omega_xi, p.omega_hi = omega_nu, omega_xi, omega_hi
+    p.bc_y, p.bc_z = _lib.BC[bc_y], _lib.BC[bc_z]
+    p.storage, p.corr = _lib.STORAGE[storage], _lib.CORR[corr]
+    p.rho0 = rho0
+    for d in range(3):
+        p.force[d] = float(force[d])
+    raw = _lib.ctypes.c_void_p()
+    _lib.check(lib.lbm_create(_lib.ctypes.byref(p), _lib.ctypes.byref(raw)))
+    return Handle(raw, p)
+
+
+def lbm_init(h, state, rho=None, u=None, perturb=None, stream=None):
+    n = h.n
+    _require(rho, _ABI_F64, n, "rho")
+    _require(u, _ABI_F64, 3 * n, "u")
+    _require(perturb, _ABI_F64, 27 * n, "perturb")
+    _lib.check(_lib.load().lbm_init(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(rho), _lib.ptr(u),
+                                    _lib.ptr(perturb), _lib.stream_ptr(stream)))
+
+
+def lbm_import(h, state, f, stream=None):
+    _require(f, _ABI_F64, 27 * h.n, "f")
+    _lib.check(_lib.load().lbm_import(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(f), _lib.stream_ptr(stream)))
+
+
+def lbm_export(h, state, f, stream=None):
+    _require(f, _ABI_F64, 27 * h.n, "f")
+    _lib.check(_lib.load().lbm_export(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(f), _lib.stream_ptr(stream)))
+
+
+def lbm_step(h, nsteps, state_a, state_b, force=None, stream=None):
+    _require(force, _ABI_F32, 3 * h.n, "force")
+    _lib.check(_lib.load().lbm_step(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
+                                    _lib.ptr(_state(h, state_b, "state_b")), _lib.ptr(force),
+                                    _lib.stream_ptr(stream)))
+
+
+def lbm_moments(h, state, force=None, rho=None, u=None, sums=None, stream=None):
+    n = h.n
+    _require(force, _ABI_F32, 3 * n, "force")
+    _require(rho, _ABI_F32, n, "rho")
+    _require(u, _ABI_F32, 3 * n, "u")
+    _require(sums, _ABI_F64, 5, "sums")
+    _lib.check(_lib.load().lbm_moments(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(force), _lib.ptr(rho),
+                                       _lib.ptr(u), _lib.ptr(sums), _lib.stream_ptr(stream)))
+
+
+def lbm_check_sums(sums, stream=None):
+    """Synchronising NaN/Inf check of the five totals; returns them as a list."""
+    _require(sums, _ABI_F64, 5, "sums")
+    out = (_lib.ctypes.c_double * 5)()
+    _lib.check(_lib.load().lbm_check_sums(_lib.ptr(sums), out, _lib.stream_ptr(stream)))
+    return list(out)
+
+
+def lbm_step_adjoint(h, state_t, adj_in, adj_out, force=None, grad_force=None, grad_force_uniform=None,
+                     stream=None):
+    m = 27 * h.stride
+    _require(adj_in, _ABI_F32, m, "adj_in")
+    _require(adj_out, _ABI_F32, m, "adj_out")
+    _require(force, _ABI_F32, 3 * h.n, "force")
+    _require(grad_force, _ABI_F32, 3 * h.n, "grad_force")
+    _require(grad_force_uniform, _ABI_F64, 3, "grad_force_uniform")
+    _lib.check(_lib.load().lbm_step_adjoint(h.raw, _lib.ptr(_state(h, state_t)), _lib.ptr(adj_in),
+                                            _lib.ptr(adj_out), _lib.ptr(force), _lib.ptr(grad_force),
+                                            _lib.ptr(grad_force_uniform), _lib.stream_ptr(stream)))
+
+
+def lbm_moments_adjoint(h, state, adj, force=None, g_rho=None, g_u=None, grad_force=None, stream=None):
+    n = h.n
+    _require(adj, _ABI_F32, 27 * h.stride, "adj")
+    _require(force, _ABI_F32, 3 * n, "force")
+    _require(g_rho, _ABI_F32, n, "g_rho")
+    _require(g_u, _ABI_F32, 3 * n, "g_u")
+    _require(grad_force, _ABI_F32, 3 * n, "grad_force")
+    _lib.check(_lib.load().lbm_moments_adjoint(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(force),
+                                               _lib.ptr(g_rho), _lib.ptr(g_u), _lib.ptr(adj),
+                                               _lib.ptr(grad_force), _lib.stream_ptr(stream)))
+
+
+def lbm_init_adjoint(h, adj, rho=None, u=None, g_rho=None, g_u=None, stream=None):
+    n = h.n
+    _require(adj, _ABI_F32, 27 * h.stride, "adj")
+    _require(rho, _ABI_F64, n, "rho")
+    _require(u, _ABI_F64, 3 * n, "u")
+    _require(g_rho, _ABI_F64, n, "g_rho")
+    _require(g_u, _ABI_F64, 3 * n, "g_u")
+    _lib.check(_lib.load().lbm_init_adjoint(h.raw, _lib.ptr(adj), _lib.ptr(rho), _lib.ptr(u),
+                                            _lib.ptr(g_rho), _lib.ptr(g_u), _lib.stream_ptr(stream)))
+
+
+def lbm_adjoint_to_natural(h, slots, natural, stream=None):
+    _require(slots, _ABI_F32, 27 * h.stride, "slots")
+    _require(natural, _ABI_F64, 27 * h.n, "natural")
+    _lib.check(_lib.load().lbm_adjoint_to_natural(h.raw, _lib.ptr(slots), _lib.ptr(natural),
+                                                  _lib.stream_ptr(stream)))
+
+
+def lbm_adjoint_from_natural(h, natural, slots, stream=None):
+    _require(slots, _ABI_F32, 27 * h.stride, "slots")
+    _require(natural, _ABI_F64, 27 * h.n, "natural")
+    _lib.check(_lib.load().lbm_adjoint_from_natural(h.raw, _lib.ptr(natural), _lib.ptr(slots),
+                                                    _lib.stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------------- convenience wrapper
+
+@dataclass
+class Moments:
+    rho: torch.Tensor
+    u: torch.Tensor
+    sums: torch.Tensor
+
+
+class Lattice:
+    """A handle plus allocation helpers; fields are torch tensors on ``device``."""
+
+    def __init__(self, nx, ny, nz, device="cuda", **kw):
+        self.h = lbm_create(nx, ny, nz, **kw)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.shape = (nz, ny, nx)
+        self.device = torch.device(device)
+
+    @property
+    def n(self):
+        return self.h.n
+
+    def new_state(self):
+        return torch.empty(self.h.state_bytes, dtype=torch.uint8, device=self.device)
+
+    def new_adjoint(self, zero=True):
+        t = torch.empty(27 * self.h.stride, dtype=torch.float32, device=self.device)
+        return t.zero_() if zero else t
+
+    def field(self, ncomp, dtype=torch.float32):
+        shape = (ncomp, *self.shape) if ncomp > 1 else self.shape
+        return torch.empty(shape, dtype=dtype, device=self.device)
+
+    def init(self, state, rho=None, u=None, perturb=None):
+        lbm_init(self.h, state, *(None if t is None else t.to(self.device, _ABI_F64).contiguous()
+                                  for t in (rho, u, perturb)))
+        return state
+
+    def import_populations(self, state, f):
+        lbm_import(self.h, state, f.to(self.device, _ABI_F64).contiguous())
+        return state
+
+    def export_populations(self, state):
+        f = torch.empty((27, *self.shape), dtype=_ABI_F64, device=self.device)
+        lbm_export(self.h, state, f)
+        return f
+
+    def step(self, a, b, nsteps, force=None):
+        """Advance; returns (current, scratch) after nsteps."""
+        lbm_step(self.h, nsteps, a, b, force)
+        return (a, b) if nsteps % 2 == 0 else (b, a)
+
+    def moments(self, state, force=None, sums=True):
+        rho = self.field(1)
+        u = self.field(3)
+        s = torch.empty(5, dtype=_ABI_F64, device=self.device) if sums else None
+        lbm_moments(self.h, state, force, rho, u, s)
+        return Moments(rho, u, s)
