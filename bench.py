@@ -1,0 +1,237 @@
+"""Benchmark of the fused cuboid D3Q27 collide-and-stream step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--variants f32,f16,bf16,adjoint]
+
+Workload: the decaying Taylor-Green + random-mode flow on the periodic
+512x512x256 cuboid grid (r = 1, s = 1/2, Re 1600), inputs resident in HBM
+before the timed region.  One "step" is one lbm_step launch (gather and
+stream, raw moments, scaling, central moments, collision with the cuboid
+corrections, inverse maps, store) over every node.  `value` is the FP32
+throughput in MLUPS (million lattice-node updates per second); the 16-bit
+deviation-storage variants and the adjoint step are reported beside it.
+
+The roofline object prices the dominant kernel (the FP32 step) against the
+8 TB/s HBM peak with its algorithmic traffic of 216 bytes per node update
+(27 populations read and written once, 4 bytes each); its launch time comes
+from HIP events recorded on the stream the kernel runs on.  `traffic` is the
+measured HBM traffic per launch from the committed rocprofv3 counter summary,
+or null when the kernel sources changed since it was taken.
+
+The CPU baseline times the FP64 oracle (test infrastructure, untuned) on a
+bounded replica of the same workload on the host's cores.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108}
+KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip")
+ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch from profiles/traffic.json if it matches the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    entry = rec.get(kind)
+    if not entry:
+        return None
+    srcs = KERNEL_SOURCES if kind != "adjoint" else ADJOINT_SOURCES
+    if entry.get("source_sha") != sources_sha(srcs):
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def time_steps(lat, a, b, steps, warmup, force=None):
+    """Warm up, then time exactly `steps` launches; returns (wall s, event ms per launch, a, b)."""
+    import paper_2107_14774_amd as P
+    if warmup:
+        a, b = lat.step(a, b, warmup, force)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    P.lbm_step(lat.h, steps, a, b, force, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if steps % 2:
+        a, b = b, a
+    return wall, ev0.elapsed_time(ev1) / steps, a, b
+
+
+def run_forward(w, storage, steps, warmup, u0_dev):
+    import paper_2107_14774_amd as P
+    on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
+    lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
+    a, b = lat.new_state(), lat.new_state()
+    lat.init(a, u=u0_dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {storage}: {w.nx}x{w.ny}x{w.nz}, state {lat.h.state_bytes / 2**30:.2f} GiB, "
+        f"{warmup} warmup + {steps} timed steps")
+    wall, ms_launch, a, b = time_steps(lat, a, b, steps, warmup)
+    m = lat.moments(a)
+    import paper_2107_14774_amd as P2
+    sums = P2.lbm_check_sums(m.sums)
+    mlups = lat.n * steps / wall / 1e6
+    kernel_mlups = lat.n / (ms_launch * 1e-3) / 1e6
+    log(f"[bench] {storage}: {mlups:.0f} MLUPS wall, {kernel_mlups:.0f} MLUPS per launch "
+        f"({ms_launch:.3f} ms/launch), mass {sums[0]:.6f}, energy {sums[4]:.6e}")
+    del a, b, lat
+    torch.cuda.empty_cache()
+    return {"mlups": mlups, "wall_s": wall, "ms_per_launch": ms_launch, "kernel_mlups": kernel_mlups,
+            "mass": sums[0], "energy": sums[4]}
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """Read+write GB/s of a plain device-to-device copy (torch copy kernel) of nbytes."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] device copy of {nbytes / 2**30:.0f} GiB: {ms:.3f} ms, {gbs:.0f} GB/s (read + write)")
+    return gbs
+
+
+def cpu_baseline(w):
+    """FP64 oracle on a 64x64x32 replica of the workload, a few steps, all host cores."""
+    import oracle
+    from oracle import analytic as A
+    from oracle import lbm as OL
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    rep = W.replica(w, 64, 64, 32)
+    p = oracle.Params(rep.nx, rep.ny, rep.nz, r=rep.r, s=rep.s, cs2=rep.cs2,
+                      omega_nu=A.omega_from_nu(rep.nu, rep.cs2), omega_xi=A.omega_from_xi(rep.xi, rep.cs2),
+                      corr="local")
+    u0 = torch.tensor(W.taylor_green(rep.nx, rep.ny, rep.nz, rep.r, rep.s, rep.extra["u0"])
+                      + W.random_modes(rep.nx, rep.ny, rep.nz, rep.r, rep.s, 2, rep.extra["rms"], rep.extra["seed"]))
+    f = OL.init_equilibrium(torch.ones(p.shape, dtype=torch.float64), u0, p)
+    f = OL.step(f, p)
+    steps = 12
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = OL.step(f, p)
+    dt = time.perf_counter() - t0
+    val = p.n * steps / dt / 1e6
+    log(f"[bench] cpu oracle: {val:.4f} MLUPS on {cores} threads ({dt:.1f} s)")
+    return {"value": val, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} steps of the {rep.nx}x{rep.ny}x{rep.nz} replica "
+                      f"(r={rep.r}, s={rep.s}, same viscosity), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--variants", default="f32,f16,bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU z-slab decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = W.DECAYING_512
+    variants = [v for v in args.variants.split(",") if v]
+    log(f"[bench] generating the initial velocity field ({w.nx}x{w.ny}x{w.nz})")
+    u0_dev = torch.from_numpy(W.initial_velocity(w)).to("cuda")
+
+    copy_gbs = copy_bandwidth()
+    res = {}
+    for v in variants:
+        if v in BYTES_PER_LUP:
+            res[v] = run_forward(w, v, args.steps, args.warmup, u0_dev)
+    del u0_dev
+    torch.cuda.empty_cache()
+
+    main_v = "f32" if "f32" in res else next(iter(res))
+    r = res[main_v]
+    achieved = BYTES_PER_LUP[main_v] * (w.n) / (r["ms_per_launch"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main_v),
+                "kernel": "k_step<f32, local corrections>", "algorithmic_bytes_per_lup": BYTES_PER_LUP[main_v],
+                "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    variants_out = {}
+    for v, rv in res.items():
+        ach = BYTES_PER_LUP[v] * w.n / (rv["ms_per_launch"] * 1e-3) / 1e9
+        variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
+                           "hbm_gbs_algorithmic": round(ach, 1), "hbm_frac": round(ach / HBM_PEAK_GBS, 4),
+                           "bytes_per_lup": BYTES_PER_LUP[v]}
+    if "f32" in res:
+        for v in ("f16", "bf16"):
+            if v in res:
+                variants_out[v]["speedup_vs_f32"] = round(res[v]["mlups"] / res["f32"]["mlups"], 3)
+
+    line = {
+        "metric": "MLUPS and % HBM roofline: plain FP32 vs BF16/FP16-storage vs adjoint",
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall_s"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "r": w.r, "s": w.s,
+                   "cs2": w.cs2, "nu": w.nu, "corrections": "local", "boundaries": "periodic",
+                   "storage": main_v},
+        "roofline": roofline,
+        "variants": variants_out,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,18 +64,21 @@ template <int ST> struct Store;
 template <> struct Store<0> {
   using T = float;
   static __device__ __forceinline__ float load(const T* p) { return *p; }
+  static __device__ __forceinline__ float load_val(T v) { return v; }
   static __device__ __forceinline__ T pack(float v) { return v; }
 };
 
 template <> struct Store<1> {
   using T = __half;
   static __device__ __forceinline__ float load(const T* p) { return __half2float(*p); }
+  static __device__ __forceinline__ float load_val(T v) { return __half2float(v); }
   static __device__ __forceinline__ T pack(float v) { return __float2half_rn(v); }
 };
 
 template <> struct Store<2> {
   using T = __hip_bfloat16;
   static __device__ __forceinline__ float load(const T* p) { return __bfloat162float(*p); }
+  static __device__ __forceinline__ float load_val(T v) { return __bfloat162float(v); }
   static __device__ __forceinline__ T pack(float v) { return __float2bfloat16(v); }
 };
 
@@ -210,7 +213,9 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   const float Pxx = M.m200, Pyy = k.c2[1] * M.m020, Pzz = k.c2[2] * M.m002;
   const float Pxy = r * M.m110, Pxz = s * M.m101, Pyz = (r * s) * M.m011;
   const float rho = rho0 + drho;
-  const float irho = 1.0f / rho;
+  // 1/rho: hardware reciprocal refined by one Newton step (about 1 ulp)
+  float irho = __builtin_amdgcn_rcpf(rho);
+  irho = irho * (2.0f - rho * irho);
   const float ux = (jx + 0.5f * fx) * irho;
   const float uy = (jy + 0.5f * fy) * irho;
   const float uz = (jz + 0.5f * fz) * irho;
@@ -236,9 +241,10 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
     const float csy = inw - ay - g * uyy, cby = -inx + ay + g * uyy;
     const float csz = inw - az - g * uzz, cbz = -inx + az + g * uzz;
     const float det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
-    const float gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) / det;
-    const float gy = (Rs1 - csx * gx) / csy;
-    const float gz = (Rs2 - csx * gx) / csz;
+    // closed-form solution of eq. 49 (the corrections only need a few digits of it)
+    const float gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) * __builtin_amdgcn_rcpf(det);
+    const float gy = (Rs1 - csx * gx) * __builtin_amdgcn_rcpf(csy);
+    const float gz = (Rs2 - csx * gx) * __builtin_amdgcn_rcpf(csz);
     // theta / rho of eq. 38-40 (App. D), times rho du
     const float hn = 1.0f / wn - 0.5f, hx = 1.0f / wx - 0.5f;
     const float g3 = (CORR == 2) ? 3.0f : 0.0f;
@@ -289,44 +295,68 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
 // collision keeps the mass and adds F to the momentum; in FP32 the rounding
 // of the 27 outputs leaves a residual of a few 1e-9 per node that repeats
 // almost unchanged from step to step on a slowly varying flow and therefore
-// accumulates.  The residual, formed in FP64 from the float inputs and
-// outputs, goes into the rest population (mass) and the three axis pairs
+// accumulates.  The per-direction changes out - in are small, so their FP32
+// rounding is tiny; their mass and momentum are summed in FP64 and the
+// residual goes into the rest population (mass) and the three axis pairs
 // f_{1,2}, f_{3,4}, f_{5,6} (momentum, antisymmetrically, so their mass and
 // second moments are unchanged).
 __device__ __forceinline__ void conserve(const float (&df)[27], float fx, float fy, float fz,
                                          const Consts& k, float (&out)[27]) {
-  double m_in = 0.0, x_in = 0.0, y_in = 0.0, z_in = 0.0;
-  double m_out = 0.0, x_out = 0.0, y_out = 0.0, z_out = 0.0;
+  double dm = 0.0, dx = 0.0, dy = 0.0, dz = 0.0;
 #pragma unroll
   for (int a = 0; a < 27; ++a) {
-    const double vi = (double)df[a], vo = (double)out[a];
-    m_in += vi;
-    m_out += vo;
-    if (kEx[a] != 0) { x_in += kEx[a] * vi; x_out += kEx[a] * vo; }
-    if (kEy[a] != 0) { y_in += kEy[a] * vi; y_out += kEy[a] * vo; }
-    if (kEz[a] != 0) { z_in += kEz[a] * vi; z_out += kEz[a] * vo; }
+    const double d = (double)(out[a] - df[a]);
+    dm += d;
+    if (kEx[a] != 0) dx += kEx[a] * d;
+    if (kEy[a] != 0) dy += kEy[a] * d;
+    if (kEz[a] != 0) dz += kEz[a] * d;
   }
-  // momentum residuals in ebar units: (j + F) / c_d - sum out ebar_d
-  const double rx = (x_in - x_out) + (double)fx;
-  const double ry = (y_in - y_out) + (double)fy / (double)k.r;
-  const double rz = (z_in - z_out) + (double)fz / (double)k.s;
-  out[0] = (float)((double)out[0] + (m_in - m_out));
-  out[1] = (float)((double)out[1] + 0.5 * rx);
-  out[2] = (float)((double)out[2] - 0.5 * rx);
-  out[3] = (float)((double)out[3] + 0.5 * ry);
-  out[4] = (float)((double)out[4] - 0.5 * ry);
-  out[5] = (float)((double)out[5] + 0.5 * rz);
-  out[6] = (float)((double)out[6] - 0.5 * rz);
+  // residuals in ebar units: the momentum change must be F / c_d along each axis
+  const float rm = (float)(-dm);
+  const float rx = (float)((double)fx - dx);
+  const float ry = (float)((double)(fy * k.ic[1]) - dy);
+  const float rz = (float)((double)(fz * k.ic[2]) - dz);
+  out[0] += rm;
+  out[1] += 0.5f * rx;
+  out[2] -= 0.5f * rx;
+  out[3] += 0.5f * ry;
+  out[4] -= 0.5f * ry;
+  out[5] += 0.5f * rz;
+  out[6] -= 0.5f * rz;
 }
 
 // XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs
 // in turn; renumber so that each XCD walks one contiguous range of tiles
 // (neighbouring rows share cache lines through that XCD's L2).
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  constexpr int64_t X = 8;
-  const int64_t per = nb / X, rem = nb % X;
-  const int64_t xcd = b % X, i = b / X;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t X = 8;
+  const uint32_t per = nb / X, rem = nb % X;
+  const uint32_t xcd = b % X, i = b / X;
   return xcd < rem ? xcd * (per + 1) + i : rem * (per + 1) + (xcd - rem) * per + i;
 }
+
+// Load/store through a uniform base pointer and a 32-bit element index (the
+// byte offset fits in 32 bits), so the address is SGPR base + VGPR offset.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_off_nt(T* __restrict__ base, uint32_t idx, T v) {
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+  if constexpr (sizeof(T) == 4) {
+    __builtin_nontemporal_store(__builtin_bit_cast(float, v), reinterpret_cast<float*>(p));
+  } else {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short*>(p));
+  }
+}
+
+// Per-direction base pointers of the two buffers of a step.
+template <typename T>
+struct DirPtrs {
+  const T* src[27];
+  T* dst[27];
+};
 
 }  // namespace clbm

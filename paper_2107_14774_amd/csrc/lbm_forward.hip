@@ -5,34 +5,59 @@
 namespace clbm {
 
 // ------------------------------------------------------------------ step
-// One thread per node, pull scheme: gather 27 slots of `src`, collide, write
-// the node's 27 slots of `dst` (coalesced along x).
-template <int ST, int CORR>
-__global__ __launch_bounds__(256) void k_step(const typename Store<ST>::T* __restrict__ src,
-                                              typename Store<ST>::T* __restrict__ dst,
-                                              const float* __restrict__ force, Consts k, int bpr) {
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int bxi = (int)(lb % bpr);
-  const int64_t row = lb / bpr;
-  const int y = (int)(row % k.ny), z = (int)(row / k.ny);
-  const int x = bxi * (int)blockDim.x + (int)threadIdx.x;
+// One thread per node, pull scheme: gather 27 slots of the source buffer,
+// collide, write the node's 27 slots of the destination buffer (coalesced
+// along x, non-temporal).  Without walls every source slot is
+// (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
+// base pointer plus a 32-bit node index shared by the three directions of
+// one source row; with walls the general slot rule of gather_slot applies.
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_periodic(const DirPtrs<typename Store<ST>::T>& P,
+                                                const uint32_t (&row)[3][3], const uint32_t (&xs)[3],
+                                                const Consts& k, float (&df)[27]) {
+  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
+  const uint32_t off = row[ey + 1][ez + 1] + xs[ex + 1];
+  const float v = Store<ST>::load_val(ld_off(P.src[A], off));
+  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
+  if constexpr (A + 1 < 27) gather_periodic<ST, A + 1>(P, row, xs, k, df);
+}
+
+template <int ST, int CORR, bool WALLS>
+__global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
+                                              const float* __restrict__ force, Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
   if (x >= k.nx) return;
-  const NodeCoord c = make_coord(x, y, z, k);
+  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
   float df[27];
-  gather_all<ST>(src, c, k, df);
-  const int64_t node = ((int64_t)z * k.ny + y) * k.nx + x;
+  if constexpr (WALLS) {
+    gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
+  } else {
+    // source coordinates x - ebar for ebar = -1, 0, +1
+    const uint32_t xs[3] = {(uint32_t)(x == k.nx - 1 ? 0 : x + 1), (uint32_t)x, (uint32_t)(x == 0 ? k.nx - 1 : x - 1)};
+    const uint32_t ys[3] = {(uint32_t)(y == k.ny - 1 ? 0 : y + 1), (uint32_t)y, (uint32_t)(y == 0 ? k.ny - 1 : y - 1)};
+    const uint32_t zs[3] = {(uint32_t)(z == k.nz - 1 ? 0 : z + 1), (uint32_t)z, (uint32_t)(z == 0 ? k.nz - 1 : z - 1)};
+    uint32_t row[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) row[j][l] = (zs[l] * (uint32_t)k.ny + ys[j]) * (uint32_t)k.nx;
+    gather_periodic<ST>(P, row, xs, k, df);
+  }
   float fx = k.fx, fy = k.fy, fz = k.fz;
   if (force != nullptr) {
-    fx = force[node];
-    fy = force[k.n + node];
-    fz = force[2 * k.n + node];
+    fx = ld_off(force, node);
+    fy = ld_off(force + k.n, node);
+    fz = ld_off(force + 2 * k.n, node);
   }
   float out[27];
   collide_node<CORR>(df, fx, fy, fz, k, out);
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
 #pragma unroll
   for (int a = 0; a < 27; ++a)
-    dst[a * k.stride + node] = Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]);
+    st_off_nt(P.dst[a], node, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]));
 }
 
 // ------------------------------------------------------------------ init / import / export
@@ -201,40 +226,38 @@ static int grid_for(int64_t n, int block, int64_t cap) {
   return (int)g;
 }
 
-hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+template <int ST>
+static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+  using T = typename Store<ST>::T;
   const int block = h.block;
-  const int bpr = (h.p.nx + block - 1) / block;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  DirPtrs<T> P;
+  for (int a = 0; a < 27; ++a) {
+    P.src[a] = (const T*)src + (int64_t)a * h.stride;
+    P.dst[a] = (T*)dst + (int64_t)a * h.stride;
+  }
+  // the 32-bit addressing of the periodic path needs every byte offset below 4 GiB
+  const bool walls = h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * sizeof(T) >= (1ull << 32);
   const dim3 grid((unsigned)nb), blk(block);
-  const int corr = h.p.corr;
-  switch (h.p.storage) {
-    case LBM_F32: {
-      using T = Store<0>::T;
-      auto s = (const T*)src; auto d = (T*)dst;
-      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<0, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<0, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else hipLaunchKernelGGL((k_step<0, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      break;
-    }
-    case LBM_F16: {
-      using T = Store<1>::T;
-      auto s = (const T*)src; auto d = (T*)dst;
-      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<1, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<1, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else hipLaunchKernelGGL((k_step<1, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      break;
-    }
-    default: {
-      using T = Store<2>::T;
-      auto s = (const T*)src; auto d = (T*)dst;
-      if (corr == LBM_CORR_OFF) hipLaunchKernelGGL((k_step<2, 0>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else if (corr == LBM_CORR_LOWMACH) hipLaunchKernelGGL((k_step<2, 1>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      else hipLaunchKernelGGL((k_step<2, 2>), grid, blk, 0, st, s, d, force, h.k, bpr);
-      break;
-    }
+  switch (h.p.corr * 2 + (walls ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_step<ST, 0, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_step<ST, 0, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    case 2: hipLaunchKernelGGL((k_step<ST, 1, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    case 3: hipLaunchKernelGGL((k_step<ST, 1, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    case 4: hipLaunchKernelGGL((k_step<ST, 2, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_step<ST, 2, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+  switch (h.p.storage) {
+    case LBM_F32: return launch_step_t<0>(h, src, dst, force, st);
+    case LBM_F16: return launch_step_t<1>(h, src, dst, force, st);
+    default: return launch_step_t<2>(h, src, dst, force, st);
+  }
 }
 
 hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
