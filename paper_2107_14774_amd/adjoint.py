@@ -1,0 +1,97 @@
+"""Differentiable trajectories of the cuboid LB step (torch.autograd.Function).
+
+``simulate(lat, u0, force, nsteps, checkpoint_every)`` runs
+    f(0) = f_eq(rho0, u0);  nsteps collide-and-stream steps under a per-node
+    body force (or the lattice's uniform force);  u(T) from eq. 12
+and returns u(T) as a differentiable tensor.  Its backward pass runs the
+hand-written adjoint kernels of the library: lbm_moments_adjoint for the
+observables, lbm_step_adjoint once per step in reverse order, and
+lbm_init_adjoint for the initial velocity; the force gradient accumulates
+inside the adjoint step kernel.
+
+Memory: the forward keeps one state every ``checkpoint_every`` steps; the
+backward recomputes one segment at a time from its checkpoint, holding that
+segment's states (at most checkpoint_every of them) while it steps back
+through it.  Peak memory is (nsteps / K + K) states plus two adjoint buffers.
+"""
+
+import torch
+
+from . import lbm as L
+
+
+class _Trajectory(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, force, lat, rho0, nsteps, every):
+        force_t = force if force.numel() else None
+        a, b = lat.new_state(), lat.new_state()
+        lat.init(a, rho=rho0, u=u0)
+        checkpoints = [a.clone()]
+        t = 0
+        while t < nsteps:
+            n = min(every, nsteps - t)
+            a, b = lat.step(a, b, n, force_t)
+            t += n
+            if t < nsteps:
+                checkpoints.append(a.clone())
+        m = lat.moments(a, force_t, sums=False)
+        ctx.lat, ctx.nsteps, ctx.every = lat, nsteps, every
+        ctx.checkpoints, ctx.final = checkpoints, a
+        ctx.force, ctx.rho0 = force_t, rho0
+        ctx.save_for_backward(u0)
+        ctx.force_needs_grad = force.requires_grad
+        return m.u
+
+    @staticmethod
+    def backward(ctx, g_u):
+        lat, h = ctx.lat, ctx.lat.h
+        (u0,) = ctx.saved_tensors
+        force = ctx.force
+        grad_force = None
+        if ctx.force_needs_grad:
+            grad_force = torch.zeros((3, *lat.shape), dtype=torch.float32, device=lat.device)
+        lam = lat.new_adjoint(zero=False)
+        lam_next = lat.new_adjoint(zero=False)
+        L.lbm_moments_adjoint(h, ctx.final, lam, force=force, g_u=g_u.to(torch.float32).contiguous(),
+                              grad_force=grad_force)
+        ctx.final = None
+        nseg = len(ctx.checkpoints)
+        pool = []
+        scratch = lat.new_state()
+        for seg in reversed(range(nseg)):
+            start = seg * ctx.every
+            n = min(ctx.every, ctx.nsteps - start)
+            # states h(start) .. h(start + n - 1) of this segment
+            while len(pool) < n:
+                pool.append(lat.new_state())
+            pool[0].copy_(ctx.checkpoints[seg])
+            for i in range(1, n):
+                L.lbm_step(h, 1, pool[i - 1], scratch, force)
+                pool[i].copy_(scratch)
+            for i in reversed(range(n)):
+                L.lbm_step_adjoint(h, pool[i], lam, lam_next, force, grad_force)
+                lam, lam_next = lam_next, lam
+            ctx.checkpoints[seg] = None
+        g_u0 = torch.empty((3, *lat.shape), dtype=torch.float64, device=lat.device)
+        rho0 = None if ctx.rho0 is None else ctx.rho0.to(torch.float64).contiguous()
+        L.lbm_init_adjoint(h, lam, rho=rho0, u=u0.contiguous(), g_u=g_u0)
+        return g_u0, grad_force, None, None, None, None
+
+
+def simulate(lat, u0, force=None, nsteps=1, checkpoint_every=50, rho0=None):
+    """u(T) after ``nsteps`` steps from f_eq(rho0, u0); differentiable in u0 and force.
+
+    lat:   a ``Lattice``
+    u0:    (3, nz, ny, nx) float64 on the lattice device
+    force: (3, nz, ny, nx) float32 per-node body force, or None for the lattice's uniform force
+    """
+    if force is None:
+        force = torch.empty(0, dtype=torch.float32, device=lat.device)
+    return _Trajectory.apply(u0, force, lat, rho0, int(nsteps), int(checkpoint_every))
+
+
+def uniform_force_gradient(lat, state_t, lam_in, lam_out, force=None):
+    """One adjoint step that also returns d/dF of the uniform force (FP64 [3])."""
+    g = torch.zeros(3, dtype=torch.float64, device=lat.device)
+    L.lbm_step_adjoint(lat.h, state_t, lam_in, lam_out, force, None, g)
+    return g

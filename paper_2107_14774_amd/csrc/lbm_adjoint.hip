@@ -1,23 +1,485 @@
-// Adjoint kernels (reverse mode of the fused step and of its two ends).
+// Adjoint kernels: reverse mode of the fused step and of its two ends.
+//
+// The step maps the state h(t) to h(t+1) = C(S(h(t)); F) where S is the
+// streaming permutation of slots and C the per-node collision.  The adjoint
+// step gathers the node's populations from h(t) (as the forward did),
+// recomputes the collision, applies the transpose of its Jacobian to the
+// node's lambda(t+1) (read from the slots the forward wrote, coalesced) and
+// scatters the result to the slots it gathered from: S is a permutation, so
+// every slot of lambda(t) is written exactly once and no atomics are needed.
+// The transpose is derived by hand from the factorised collision of
+// lbm_device.h; along each axis the vectors satisfy dE/du = dD/du = dA0/du =
+// A1 and dA1/du = 2 A2, which keeps the velocity derivatives short.
 #include "lbm_internal.h"
 
 namespace clbm {
 
-hipError_t launch_step_adjoint(const lbm_handle&, const void*, const float*, float*, const float*, float*,
-                               double*, hipStream_t) {
-  return hipErrorNotSupported;
+// lambda^T dC/d(df, F) at one node: mu = (dC/d df)^T lam, gf = (dC/dF)^T lam.
+template <int CORR>
+__device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, float fy, float fz, const Consts& k,
+                                            const float (&lam)[27], float (&mu)[27], float& gfx, float& gfy,
+                                            float& gfz) {
+  // ---------------------------------------------------------------- forward recomputation
+  const LowMoments M = low_moments(df);
+  const float r = k.r, s = k.s, cs2 = k.cs2, rho0 = k.rho0;
+  const float drho = M.m000;
+  const float jx = M.m100, jy = r * M.m010, jz = s * M.m001;
+  const float Pxx = M.m200, Pyy = k.c2[1] * M.m020, Pzz = k.c2[2] * M.m002;
+  const float Pxy = r * M.m110, Pxz = s * M.m101, Pyz = (r * s) * M.m011;
+  const float rho = rho0 + drho;
+  float irho = __builtin_amdgcn_rcpf(rho);
+  irho = irho * (2.0f - rho * irho);
+  const float ux = (jx + 0.5f * fx) * irho, uy = (jy + 0.5f * fy) * irho, uz = (jz + 0.5f * fz) * irho;
+  const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const float Rb = (Pxx + Pyy + Pzz) - 3.0f * cs2 * drho - rho * (uxx + uyy + uzz) + (ux * fx + uy * fy + uz * fz);
+  const float Rs1 = (Pxx - Pyy) - rho * (uxx - uyy) + (ux * fx - uy * fy);
+  const float Rs2 = (Pxx - Pzz) - rho * (uxx - uzz) + (ux * fx - uz * fz);
+  const float kxy = Pxy - rho * ux * uy + 0.5f * (ux * fy + uy * fx);
+  const float kxz = Pxz - rho * ux * uz + 0.5f * (ux * fz + uz * fx);
+  const float kyz = Pyz - rho * uy * uz + 0.5f * (uy * fz + uz * fy);
+  const float wn = k.omega_nu, wx = k.omega_xi;
+  const float g = (CORR == 2) ? 1.5f : 0.0f, g3 = 2.0f * g;
+  const float hn = 1.0f / wn - 0.5f, hx = 1.0f / wx - 0.5f;
+  float csx = 0, cbx = 0, csy = 1, cby = 0, csz = 1, cbz = 0, det = 1, gx = 0, gy = 0, gz = 0, tx = 0, ty = 0, tz = 0;
+  float c2d1 = 0.0f, c2d2 = 0.0f, c2s = 0.0f;
+  if constexpr (CORR != 0) {
+    const float inw = 2.0f * cs2 / wn, inx = 2.0f * cs2 / wx;
+    const float ax = 0.5f * (3.0f * cs2 - 1.0f), ay = 0.5f * (3.0f * cs2 - k.c2[1]), az = 0.5f * (3.0f * cs2 - k.c2[2]);
+    csx = -inw + ax + g * uxx; cbx = -inx + ax + g * uxx;
+    csy = inw - ay - g * uyy; cby = -inx + ay + g * uyy;
+    csz = inw - az - g * uzz; cbz = -inx + az + g * uzz;
+    det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
+    gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) * __builtin_amdgcn_rcpf(det);
+    gy = (Rs1 - csx * gx) * __builtin_amdgcn_rcpf(csy);
+    gz = (Rs2 - csx * gx) * __builtin_amdgcn_rcpf(csz);
+    tx = -(g3 * uxx + 2.0f * ax); ty = -(g3 * uyy + 2.0f * ay); tz = -(g3 * uzz + 2.0f * az);
+    c2d1 = hn * (tx * gx - ty * gy);
+    c2d2 = hn * (tx * gx - tz * gz);
+    c2s = hx * (tx * gx + ty * gy + tz * gz);
+  }
+  const float D2s = (1.0f - wx) * Rb + wx * c2s;
+  const float D2d1 = (1.0f - wn) * Rs1 + wn * c2d1;
+  const float D2d2 = (1.0f - wn) * Rs2 + wn * c2d2;
+  constexpr float third = 1.0f / 3.0f;
+  const float Dxx = (D2s + D2d1 + D2d2) * third;
+  const float Dyy = (D2s - 2.0f * D2d1 + D2d2) * third;
+  const float Dzz = (D2s + D2d1 - 2.0f * D2d2) * third;
+  const float Dxy = (1.0f - wn) * kxy, Dxz = (1.0f - wn) * kxz, Dyz = (1.0f - wn) * kyz;
+  const float Dx = 0.5f * fx, Dy = 0.5f * fy, Dz = 0.5f * fz;
+  const AxisVec X = axis_vectors(ux, 0, k);
+  const AxisVec Y = axis_vectors(uy, 1, k);
+  const AxisVec Z = axis_vectors(uz, 2, k);
+
+  // ---------------------------------------------------------------- reverse: output tensor products
+  float bux = 0.0f, buy = 0.0f, buz = 0.0f, bdrho = 0.0f;
+  float bDx = 0.0f, bDy = 0.0f, bDz = 0.0f, bDxx = 0.0f, bDyy = 0.0f, bDzz = 0.0f, bDxy = 0.0f, bDxz = 0.0f, bDyz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float eE = drho * X.E[i] + rho0 * X.D[i];
+    const float eW = rho0 * X.W0[i];
+    const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
+    const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
+    const float a2 = Dyy * X.A0[i];
+    const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
+    const float b1 = Dyz * X.A0[i];
+    const float c0 = Dzz * X.A0[i];
+    float eEb = 0.0f, a0b = 0.0f, a1b = 0.0f, a2b = 0.0f, b0b = 0.0f, b1b = 0.0f, c0b = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float LE = 0.0f, L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const float lv = lam[dir_of(i, j, l)];
+        LE += lv * Z.E[l];
+        L0 += lv * Z.A0[l];
+        L1 += lv * Z.A1[l];
+        L2 += lv * Z.A2[l];
+      }
+      const float QE = eE * Y.E[j] + eW * Y.D[j];
+      const float QW = eW * Y.W0[j];
+      const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j] + a2 * Y.A2[j];
+      const float Q1 = b0 * Y.A0[j] + b1 * Y.A1[j];
+      // d/du_z: E', D', A0' = A1 and A1' = 2 A2 (the cotangent of QW is not needed: QW is constant)
+      buz += (QE + QW + Q0) * L1 + 2.0f * Q1 * L2;
+      // y-vectors
+      eEb += LE * Y.E[j];
+      buy += LE * (eE + eW) * Y.A1[j];
+      a0b += L0 * Y.A0[j];
+      a1b += L0 * Y.A1[j];
+      a2b += L0 * Y.A2[j];
+      buy += L0 * (a0 * Y.A1[j] + 2.0f * a1 * Y.A2[j]);
+      b0b += L1 * Y.A0[j];
+      b1b += L1 * Y.A1[j];
+      buy += L1 * (b0 * Y.A1[j] + 2.0f * b1 * Y.A2[j]);
+      c0b += L2 * Y.A0[j];
+      buy += L2 * c0 * Y.A1[j];
+    }
+    // x-coefficients
+    bdrho += eEb * X.E[i];
+    bux += eEb * rho * X.A1[i];
+    bDx += a0b * X.A1[i];
+    bDxx += a0b * X.A2[i];
+    bux += 2.0f * a0b * Dx * X.A2[i];
+    bDy += a1b * X.A0[i];
+    bDxy += a1b * X.A1[i];
+    bux += a1b * (Dy * X.A1[i] + 2.0f * Dxy * X.A2[i]);
+    bDyy += a2b * X.A0[i];
+    bux += a2b * Dyy * X.A1[i];
+    bDz += b0b * X.A0[i];
+    bDxz += b0b * X.A1[i];
+    bux += b0b * (Dz * X.A1[i] + 2.0f * Dxz * X.A2[i]);
+    bDyz += b1b * X.A0[i];
+    bux += b1b * Dyz * X.A1[i];
+    bDzz += c0b * X.A0[i];
+    bux += c0b * Dzz * X.A1[i];
+  }
+  float bfx = 0.5f * bDx, bfy = 0.5f * bDy, bfz = 0.5f * bDz;
+  const float bkxy = (1.0f - wn) * bDxy, bkxz = (1.0f - wn) * bDxz, bkyz = (1.0f - wn) * bDyz;
+  const float bD2s = (bDxx + bDyy + bDzz) * third;
+  const float bD2d1 = (bDxx - 2.0f * bDyy + bDzz) * third;
+  const float bD2d2 = (bDxx + bDyy - 2.0f * bDzz) * third;
+  float bRb = (1.0f - wx) * bD2s, bRs1 = (1.0f - wn) * bD2d1, bRs2 = (1.0f - wn) * bD2d2;
+  float buxx = 0.0f, buyy = 0.0f, buzz = 0.0f;
+  if constexpr (CORR != 0) {
+    // corrections c = theta . g and the strain-rate solve (eq. 49)
+    const float bc2s = wx * bD2s, bc2d1 = wn * bD2d1, bc2d2 = wn * bD2d2;
+    const float sx = hn * (bc2d1 + bc2d2) + hx * bc2s;
+    const float sy = -hn * bc2d1 + hx * bc2s;
+    const float sz = -hn * bc2d2 + hx * bc2s;
+    buxx -= g3 * sx * gx;
+    buyy -= g3 * sy * gy;
+    buzz -= g3 * sz * gz;
+    float bgx = tx * sx;
+    const float bgy = ty * sy, bgz = tz * sz;
+    const float icsy = __builtin_amdgcn_rcpf(csy), icsz = __builtin_amdgcn_rcpf(csz);
+    bRs1 += bgy * icsy;
+    bRs2 += bgz * icsz;
+    float bcsx = -(bgy * icsy + bgz * icsz) * gx;
+    bgx -= (bgy * icsy + bgz * icsz) * csx;
+    float bcsy = -bgy * gy * icsy;
+    float bcsz = -bgz * gz * icsz;
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float bN = bgx * idet, bdet = -bgx * gx * idet;
+    bRs1 -= csz * cby * bN;
+    bRs2 -= csy * cbz * bN;
+    bRb += csy * csz * bN;
+    bcsz += (-cby * Rs1 + csy * Rb) * bN + (-csx * cby + csy * cbx) * bdet;
+    const float bcby = -csz * Rs1 * bN - csx * csz * bdet;
+    bcsy += (-cbz * Rs2 + csz * Rb) * bN + (-csx * cbz + csz * cbx) * bdet;
+    const float bcbz = -csy * Rs2 * bN - csy * csx * bdet;
+    bcsx += (-csz * cby - csy * cbz) * bdet;
+    const float bcbx = csy * csz * bdet;
+    buxx += g * (bcsx + bcbx);
+    buyy += g * (bcby - bcsy);
+    buzz += g * (bcbz - bcsz);
+  }
+  // non-equilibrium second moments
+  const float sR = bRb + bRs1 + bRs2, tRy = bRb - bRs1, tRz = bRb - bRs2;
+  bdrho -= 3.0f * cs2 * bRb;
+  float brho = -(uxx + uyy + uzz) * bRb - (uxx - uyy) * bRs1 - (uxx - uzz) * bRs2 - ux * uy * bkxy - ux * uz * bkxz -
+               uy * uz * bkyz;
+  buxx -= rho * sR;
+  buyy -= rho * tRy;
+  buzz -= rho * tRz;
+  bux += fx * sR + (0.5f * fy - rho * uy) * bkxy + (0.5f * fz - rho * uz) * bkxz;
+  buy += fy * tRy + (0.5f * fx - rho * ux) * bkxy + (0.5f * fz - rho * uz) * bkyz;
+  buz += fz * tRz + (0.5f * fx - rho * ux) * bkxz + (0.5f * fy - rho * uy) * bkyz;
+  bfx += ux * sR + 0.5f * (uy * bkxy + uz * bkxz);
+  bfy += uy * tRy + 0.5f * (ux * bkxy + uz * bkyz);
+  bfz += uz * tRz + 0.5f * (ux * bkxz + uy * bkyz);
+  bux += 2.0f * ux * buxx;
+  buy += 2.0f * uy * buyy;
+  buz += 2.0f * uz * buzz;
+  // u = (j + F/2) / rho
+  const float bjx = bux * irho, bjy = buy * irho, bjz = buz * irho;
+  bfx += 0.5f * bjx;
+  bfy += 0.5f * bjy;
+  bfz += 0.5f * bjz;
+  brho -= (bux * ux + buy * uy + buz * uz) * irho;
+  bdrho += brho;
+  // low moments are linear in df
+  const float bj[3] = {bjx, r * bjy, s * bjz};
+  const float bP[3] = {sR, k.c2[1] * tRy, k.c2[2] * tRz};
+  const float bPxy = r * bkxy, bPxz = s * bkxz, bPyz = (r * s) * bkyz;
+#pragma unroll
+  for (int a = 0; a < 27; ++a) {
+    const int ex = kEx[a], ey = kEy[a], ez = kEz[a];
+    float v = bdrho;
+    if (ex != 0) v += ex * bj[0] + bP[0];
+    if (ey != 0) v += ey * bj[1] + bP[1];
+    if (ez != 0) v += ez * bj[2] + bP[2];
+    if (ex != 0 && ey != 0) v += (float)(ex * ey) * bPxy;
+    if (ex != 0 && ez != 0) v += (float)(ex * ez) * bPxz;
+    if (ey != 0 && ez != 0) v += (float)(ey * ez) * bPyz;
+    mu[a] = v;
+  }
+  gfx = bfx;
+  gfy = bfy;
+  gfz = bfz;
 }
-hipError_t launch_moments_adjoint(const lbm_handle&, const void*, const float*, const float*, const float*,
-                                  float*, float*, hipStream_t) {
-  return hipErrorNotSupported;
+
+// ------------------------------------------------------------------ adjoint step
+template <int A = 0>
+__device__ __forceinline__ void scatter_all(float* __restrict__ dst, const NodeCoord& c, const Consts& k,
+                                            const float (&mu)[27]) {
+  dst[gather_slot<A>(c, k)] = mu[A];
+  if constexpr (A + 1 < 27) scatter_all<A + 1>(dst, c, k, mu);
 }
-hipError_t launch_init_adjoint(const lbm_handle&, const float*, const double*, const double*, double*, double*,
-                               hipStream_t) {
-  return hipErrorNotSupported;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
-hipError_t launch_adjoint_natural(const lbm_handle&, const float*, double*, int, const double*, float*,
-                                  hipStream_t) {
-  return hipErrorNotSupported;
+
+template <int ST, int CORR>
+__global__ __launch_bounds__(256) void k_step_adjoint(const typename Store<ST>::T* __restrict__ state,
+                                                      const float* __restrict__ adj_in, float* __restrict__ adj_out,
+                                                      const float* __restrict__ force, float* __restrict__ grad_force,
+                                                      double* __restrict__ grad_uniform, Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  float gfx = 0.0f, gfy = 0.0f, gfz = 0.0f;
+  if (x < k.nx) {
+    const NodeCoord c = make_coord(x, y, z, k);
+    const int64_t node = ((int64_t)z * k.ny + y) * k.nx + x;
+    float df[27], lam[27], mu[27];
+    gather_all<ST>(state, c, k, df);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) lam[a] = adj_in[a * k.stride + node];
+    float fx = k.fx, fy = k.fy, fz = k.fz;
+    if (force != nullptr) {
+      fx = force[node];
+      fy = force[k.n + node];
+      fz = force[2 * k.n + node];
+    }
+    collide_vjp<CORR>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
+    scatter_all(adj_out, c, k, mu);
+    if (grad_force != nullptr) {
+      grad_force[node] += gfx;
+      grad_force[k.n + node] += gfy;
+      grad_force[2 * k.n + node] += gfz;
+    }
+  }
+  if (grad_uniform != nullptr) {
+    __shared__ double part[3][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double v0 = wave_sum_d((double)gfx), v1 = wave_sum_d((double)gfy), v2 = wave_sum_d((double)gfz);
+    if (lane == 0) { part[0][wave] = v0; part[1][wave] = v1; part[2][wave] = v2; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double v = 0.0;
+      for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) v += part[threadIdx.x][w];
+      atomicAdd(&grad_uniform[threadIdx.x], v);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ observables adjoint
+template <int ST>
+__global__ __launch_bounds__(256) void k_moments_adjoint(const typename Store<ST>::T* __restrict__ state,
+                                                         const float* __restrict__ force, const float* __restrict__ g_rho,
+                                                         const float* __restrict__ g_u, float* __restrict__ adj,
+                                                         float* __restrict__ grad_force, Consts k) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(node % k.nx);
+    const int64_t t = node / k.nx;
+    const NodeCoord c = make_coord(x, (int)(t % k.ny), (int)(t / k.ny), k);
+    float df[27];
+    gather_all<ST>(state, c, k, df);
+    const LowMoments M = low_moments(df);
+    float fx = k.fx, fy = k.fy, fz = k.fz;
+    if (force != nullptr) {
+      fx = force[node];
+      fy = force[k.n + node];
+      fz = force[2 * k.n + node];
+    }
+    const float rho = k.rho0 + M.m000;
+    const float irho = 1.0f / rho;
+    const float ux = (M.m100 + 0.5f * fx) * irho, uy = (k.r * M.m010 + 0.5f * fy) * irho;
+    const float uz = (k.s * M.m001 + 0.5f * fz) * irho;
+    const float gr = g_rho ? g_rho[node] : 0.0f;
+    const float gx = g_u ? g_u[node] : 0.0f, gy = g_u ? g_u[k.n + node] : 0.0f, gz = g_u ? g_u[2 * k.n + node] : 0.0f;
+    const float brho = gr - (gx * ux + gy * uy + gz * uz) * irho;
+    const float bj[3] = {gx * irho, k.r * gy * irho, k.s * gz * irho};
+    float mu[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) {
+      float v = brho;
+      if (kEx[a] != 0) v += kEx[a] * bj[0];
+      if (kEy[a] != 0) v += kEy[a] * bj[1];
+      if (kEz[a] != 0) v += kEz[a] * bj[2];
+      mu[a] = v;
+    }
+    scatter_all(adj, c, k, mu);
+    if (grad_force != nullptr) {
+      grad_force[node] += 0.5f * gx * irho;
+      grad_force[k.n + node] += 0.5f * gy * irho;
+      grad_force[2 * k.n + node] += 0.5f * gz * irho;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ init adjoint (FP64)
+template <int A = 0>
+__device__ __forceinline__ void gather_adj(const float* __restrict__ adj, const NodeCoord& c, const Consts& k,
+                                           double (&l)[27]) {
+  l[A] = (double)adj[gather_slot<A>(c, k)];
+  if constexpr (A + 1 < 27) gather_adj<A + 1>(adj, c, k, l);
+}
+
+__global__ __launch_bounds__(256) void k_init_adjoint(const float* __restrict__ adj, const double* __restrict__ rho,
+                                                      const double* __restrict__ u, double* __restrict__ g_rho,
+                                                      double* __restrict__ g_u, Consts k, ConstsD kd) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(node % k.nx);
+    const int64_t t = node / k.nx;
+    const NodeCoord c = make_coord(x, (int)(t % k.ny), (int)(t / k.ny), k);
+    double l[27];
+    gather_adj(adj, c, k, l);
+    const double rn = rho ? rho[node] : kd.rho0;
+    const double uu[3] = {u ? u[node] : 0.0, u ? u[k.n + node] : 0.0, u ? u[2 * k.n + node] : 0.0};
+    double E[3][3], A1[3][3];
+    for (int d = 0; d < 3; ++d) {
+      const double q = uu[d] * uu[d] * kd.ic2[d], h = uu[d] * kd.ic[d];
+      E[d][0] = kd.w0s[d] + 0.5 * (q - h);
+      E[d][1] = kd.w0c[d] - q;
+      E[d][2] = kd.w0s[d] + 0.5 * (q + h);
+      const double uic2 = uu[d] * kd.ic2[d], hic = 0.5 * kd.ic[d];
+      A1[d][0] = uic2 - hic;
+      A1[d][1] = -2.0 * uic2;
+      A1[d][2] = uic2 + hic;
+    }
+    // f_eq = rho E_x (x) E_y (x) E_z: d/drho = E E E, d/du_d = rho (E with E_d replaced by A1_d)
+    double gr = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double lE = 0.0, lA = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double lv = l[dir_of(i, j, m)];
+          lE += lv * E[2][m];
+          lA += lv * A1[2][m];
+        }
+        gr += lE * E[0][i] * E[1][j];
+        gx += lE * A1[0][i] * E[1][j];
+        gy += lE * E[0][i] * A1[1][j];
+        gz += lA * E[0][i] * E[1][j];
+      }
+    if (g_rho) g_rho[node] = gr;
+    if (g_u) {
+      g_u[node] = rn * gx;
+      g_u[k.n + node] = rn * gy;
+      g_u[2 * k.n + node] = rn * gz;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ slots <-> natural order
+template <int A = 0>
+__device__ __forceinline__ void slots_to_nat(const float* __restrict__ s, const NodeCoord& c, int64_t node,
+                                             double* __restrict__ nat, const Consts& k) {
+  nat[A * k.n + node] = (double)s[gather_slot<A>(c, k)];
+  if constexpr (A + 1 < 27) slots_to_nat<A + 1>(s, c, node, nat, k);
+}
+
+template <int A = 0>
+__device__ __forceinline__ void nat_to_slots(const double* __restrict__ nat, const NodeCoord& c, int64_t node,
+                                             float* __restrict__ s, const Consts& k) {
+  s[gather_slot<A>(c, k)] = (float)nat[A * k.n + node];
+  if constexpr (A + 1 < 27) nat_to_slots<A + 1>(nat, c, node, s, k);
+}
+
+__global__ __launch_bounds__(256) void k_adjoint_natural(const float* __restrict__ slots, double* __restrict__ natural,
+                                                         int to_natural, const double* __restrict__ natural_in,
+                                                         float* __restrict__ slots_out, Consts k) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(node % k.nx);
+    const int64_t t = node / k.nx;
+    const NodeCoord c = make_coord(x, (int)(t % k.ny), (int)(t / k.ny), k);
+    if (to_natural) slots_to_nat(slots, c, node, natural, k);
+    else nat_to_slots(natural_in, c, node, slots_out, k);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_cap(int64_t n, int cap) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+template <int ST>
+static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
+                                        const float* force, float* grad_force, double* grad_uniform, hipStream_t st) {
+  using T = typename Store<ST>::T;
+  const int block = 256;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const T* s = (const T*)state;
+  switch (h.p.corr) {
+    case LBM_CORR_OFF:
+      hipLaunchKernelGGL((k_step_adjoint<ST, 0>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
+                         grad_force, grad_uniform, h.k, bpr);
+      break;
+    case LBM_CORR_LOWMACH:
+      hipLaunchKernelGGL((k_step_adjoint<ST, 1>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
+                         grad_force, grad_uniform, h.k, bpr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_step_adjoint<ST, 2>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
+                         grad_force, grad_uniform, h.k, bpr);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
+                               const float* force, float* grad_force, double* grad_force_uniform, hipStream_t st) {
+  switch (h.p.storage) {
+    case LBM_F32: return launch_step_adjoint_t<0>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
+    case LBM_F16: return launch_step_adjoint_t<1>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
+    default: return launch_step_adjoint_t<2>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
+  }
+}
+
+hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force, const float* g_rho,
+                                  const float* g_u, float* adj, float* grad_force, hipStream_t st) {
+  const int g = grid_cap(h.n, 65536);
+  switch (h.p.storage) {
+    case LBM_F32:
+      hipLaunchKernelGGL(k_moments_adjoint<0>, g, 256, 0, st, (const float*)state, force, g_rho, g_u, adj, grad_force, h.k);
+      break;
+    case LBM_F16:
+      hipLaunchKernelGGL(k_moments_adjoint<1>, g, 256, 0, st, (const Store<1>::T*)state, force, g_rho, g_u, adj,
+                         grad_force, h.k);
+      break;
+    default:
+      hipLaunchKernelGGL(k_moments_adjoint<2>, g, 256, 0, st, (const Store<2>::T*)state, force, g_rho, g_u, adj,
+                         grad_force, h.k);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_adjoint(const lbm_handle& h, const float* adj, const double* rho, const double* u, double* g_rho,
+                               double* g_u, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_adjoint, grid_cap(h.n, 65536), 256, 0, st, adj, rho, u, g_rho, g_u, h.k, h.kd);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_natural(const lbm_handle& h, const float* slots, double* natural, int to_natural,
+                                  const double* natural_in, float* slots_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_natural, grid_cap(h.n, 65536), 256, 0, st, slots, natural, to_natural, natural_in,
+                     slots_out, h.k);
+  return hipGetLastError();
 }
 
 }  // namespace clbm

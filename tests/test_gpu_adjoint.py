@@ -1,0 +1,189 @@
+"""GPU parity of the hand-written adjoint (step, observables, init, trajectory)
+against the FP64 oracle's reverse mode and against central finite differences
+of the GPU forward, through the C ABI."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import gradient as G
+from oracle import lbm as OL
+import workloads as W
+import paper_2107_14774_amd as P
+from paper_2107_14774_amd import adjoint as ADJ
+from helpers import fp32_rounded_state, gpu_lattice, oracle_params, random_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+ADJ_CASES = [
+    ("periodic_ragged_local", (300, 5, 4), 1.0, 0.5, "periodic", "periodic", "local"),
+    ("duct_walls_local", (19, 10, 8), 1.0, 0.25, "bounceback", "bounceback", "local"),
+    ("aniso_lowmach", (16, 9, 12), 0.5, 0.25, "periodic", "bounceback", "lowmach"),
+    ("walls_off", (12, 7, 6), 0.8, 1.2, "bounceback", "periodic", "off"),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_step_adjoint_matches_oracle_vjp(case):
+    name, (nx, ny, nz), r, s, by, bz, corr = case
+    _say("case", name)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_y=by, bc_z=bz)
+    f0 = fp32_rounded_state(random_state(p, 21), p)
+    g = np.random.Generator(np.random.PCG64(22))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32)
+    lam_f = torch.tensor(g.standard_normal((27, *p.shape)))
+    lat = gpu_lattice(p)
+    st = lat.new_state()
+    lat.import_populations(st, f0.cuda())
+    lam_in = lat.new_adjoint()
+    lam_out = lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam_f.cuda(), lam_in)
+    gF = torch.zeros((3, *p.shape), dtype=torch.float32, device="cuda")
+    gFu = torch.zeros(3, dtype=torch.float64, device="cuda")
+    P.lbm_step_adjoint(lat.h, st, lam_in, lam_out, force.cuda(), gF, gFu)
+    got = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_adjoint_to_natural(lat.h, lam_out, got)
+    want_f, want_F = G.step_vjp(f0, p, force.to(DT), lam_f)
+    err = (got.cpu() - want_f).abs().max().item() / want_f.abs().max().item()
+    errF = (gF.cpu().to(DT) - want_F).abs().max().item() / want_F.abs().max().item()
+    errU = (gFu.cpu() - want_F.reshape(3, -1).sum(-1)).abs().max().item() / want_F.reshape(3, -1).sum(-1).abs().max().item()
+    _say(f"{name}: rel max err lambda {err:.2e}, force grad {errF:.2e}, uniform force grad {errU:.2e}")
+    assert err < 2e-6
+    assert errF < 2e-5
+    assert errU < 1e-4
+
+
+def test_adjoint_natural_roundtrip():
+    p = oracle.Params(9, 6, 5, r=1.0, s=0.5, bc_y="bounceback")
+    lat = gpu_lattice(p)
+    nat = torch.randn((27, *p.shape), dtype=DT, device="cuda")
+    slots = lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, nat, slots)
+    back = torch.empty_like(nat)
+    P.lbm_adjoint_to_natural(lat.h, slots, back)
+    assert torch.equal(back, nat.to(torch.float32).to(DT))
+
+
+def test_moments_and_init_adjoint_match_oracle():
+    p = oracle.Params(13, 7, 6, r=0.8, s=0.5, bc_z="bounceback")
+    f0 = fp32_rounded_state(random_state(p, 31), p)
+    g = np.random.Generator(np.random.PCG64(32))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32)
+    g_rho = torch.tensor(g.standard_normal(p.shape)).to(torch.float32)
+    g_u = torch.tensor(g.standard_normal((3, *p.shape))).to(torch.float32)
+    lat = gpu_lattice(p)
+    st = lat.new_state()
+    lat.import_populations(st, f0.cuda())
+    adj = lat.new_adjoint()
+    gF = torch.zeros((3, *p.shape), dtype=torch.float32, device="cuda")
+    P.lbm_moments_adjoint(lat.h, st, adj, force.cuda(), g_rho.cuda(), g_u.cuda(), gF)
+    got = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_adjoint_to_natural(lat.h, adj, got)
+    want = G.observables_vjp(f0, p, force.to(DT), g_rho.to(DT), g_u.to(DT))
+    err = (got.cpu() - want).abs().max().item() / want.abs().max().item()
+    _say(f"moments adjoint rel err {err:.2e}")
+    assert err < 1e-6
+    # force part of the observables: d u / d F = 1 / (2 rho)
+    rho, _ = OL.observables(f0, p, force.to(DT))
+    assert torch.allclose(gF.cpu().to(DT), 0.5 * g_u.to(DT) / rho, rtol=1e-5, atol=1e-9)
+    # init adjoint
+    rho0 = torch.tensor(1.0 + 0.01 * g.standard_normal(p.shape))
+    u0 = torch.tensor(0.02 * g.standard_normal((3, *p.shape)))
+    lam = torch.tensor(g.standard_normal((27, *p.shape))).to(torch.float32)
+    slots = lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam.to(DT).cuda(), slots)
+    gr = torch.empty(p.shape, dtype=DT, device="cuda")
+    gu = torch.empty((3, *p.shape), dtype=DT, device="cuda")
+    P.lbm_init_adjoint(lat.h, slots, rho0.cuda(), u0.cuda(), gr, gu)
+    wr, wu = G.init_vjp(rho0, u0, p, lam.to(DT))
+    e1 = (gr.cpu() - wr).abs().max().item() / wr.abs().max().item()
+    e2 = (gu.cpu() - wu).abs().max().item() / wu.abs().max().item()
+    _say(f"init adjoint rel err rho {e1:.2e}, u {e2:.2e}")
+    assert e1 < 1e-12 and e2 < 1e-12
+
+
+def _loss_gpu(lat, u0, force, target, nsteps, every):
+    u = ADJ.simulate(lat, u0, force, nsteps, every)
+    return 0.5 * ((u.to(DT) - target) ** 2).sum(), u
+
+
+def test_trajectory_gradient_matches_oracle_on_replica():
+    """dL/dF and dL/du0 through 24 steps on a 12x10x8 replica of the adjoint duct workload."""
+    w = W.ADJOINT_DUCT_128
+    p = oracle_params(w, nx=12, ny=10, nz=8)
+    g = np.random.Generator(np.random.PCG64(41))
+    force = torch.tensor(1e-5 * g.standard_normal((3, *p.shape))).to(torch.float32)
+    u0 = torch.tensor(1e-3 * g.standard_normal((3, *p.shape)))
+    target = torch.tensor(1e-3 * g.standard_normal((3, *p.shape)))
+    nsteps = 24
+    L_o, gF_o, gu_o = G.loss_and_gradients(p, torch.ones(p.shape, dtype=DT), u0, force.to(DT), target, nsteps)
+    lat = gpu_lattice(p)
+    uc = u0.cuda().requires_grad_(True)
+    Fc = force.cuda().requires_grad_(True)
+    L_g, _ = _loss_gpu(lat, uc, Fc, target.cuda(), nsteps, 5)
+    L_g.backward()
+    eF = rel_l2(Fc.grad.cpu(), gF_o)
+    eu = rel_l2(uc.grad.cpu(), gu_o)
+    _say(f"replica trajectory: loss rel err {abs(L_g.item() - L_o.item()) / L_o.item():.2e}, "
+         f"dL/dF rel L2 {eF:.2e}, dL/du0 rel L2 {eu:.2e}")
+    assert eF < 1e-4 and eu < 1e-4
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    w = W.ADJOINT_DUCT_128
+    p = oracle_params(w, nx=24, ny=12, nz=10)
+    g = np.random.Generator(np.random.PCG64(42))
+    force = torch.tensor(1e-5 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda()
+    target = torch.tensor(1e-3 * g.standard_normal((3, *p.shape))).cuda()
+    u0 = torch.zeros((3, *p.shape), dtype=DT, device="cuda")
+    lat = gpu_lattice(p)
+    grads = []
+    for every in (1, 7, 40):
+        Fc = force.clone().requires_grad_(True)
+        L_g, _ = _loss_gpu(lat, u0, Fc, target, 40, every)
+        L_g.backward()
+        grads.append(Fc.grad.clone())
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
+def test_full_size_duct_gradient_vs_central_differences():
+    """Adjoint workload at full size: 128x128x64 duct, 500 steps, checkpoint every 50;
+    dL/dF on 16 seeded entries vs central differences of the GPU forward."""
+    w = W.ADJOINT_DUCT_128
+    p = oracle_params(w)
+    force = torch.from_numpy(W.body_force_field(w)).to(torch.float32).cuda()
+    target = torch.from_numpy(W.target_velocity(w)).cuda()
+    u0 = torch.zeros((3, *p.shape), dtype=DT, device="cuda")
+    lat = gpu_lattice(p)
+    Fc = force.clone().requires_grad_(True)
+    L_g, _ = _loss_gpu(lat, u0, Fc, target, w.steps, w.extra["checkpoint"])
+    L_g.backward()
+    grad = Fc.grad
+    idx = W.sample_indices(w.extra["fd_entries"], force.numel(), w.extra["fd_seed"])
+    h = 1e-5
+    worst = 0.0
+    scale = grad.abs().max().item()
+    with torch.no_grad():
+        for flat in idx:
+            c = np.unravel_index(int(flat), force.shape)
+            Fp, Fm = force.clone(), force.clone()
+            Fp[c] += h
+            Fm[c] -= h
+            lp, _ = _loss_gpu(lat, u0, Fp, target, w.steps, w.steps)
+            lm, _ = _loss_gpu(lat, u0, Fm, target, w.steps, w.steps)
+            fd = ((lp - lm) / (2 * h)).item()
+            ad = grad[c].item()
+            worst = max(worst, abs(fd - ad) / scale)
+            _say(f"entry {c}: adjoint {ad:.6e} fd {fd:.6e}")
+    _say(f"full-size duct: worst |fd - adjoint| / max|grad| = {worst:.2e}")
+    assert worst < 1e-3
