@@ -39,6 +39,8 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108}
+# adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
+ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
 KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip")
 ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint.hip")
 
@@ -135,6 +137,74 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     return gbs
 
 
+def run_adjoint(kind, steps, warmup):
+    """Adjoint step kernel alone (repeated on one state), then one full backward pass."""
+    import paper_2107_14774_amd as P
+    from paper_2107_14774_amd import adjoint as ADJ
+    if kind == "adjoint_f32":
+        w, storage = W.ADJOINT_DUCT_128, "f32"
+    else:
+        w, storage = W.ADJOINT_F16_384, "f16"
+    on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
+    lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
+    force = None
+    if kind == "adjoint_f32":
+        force = torch.from_numpy(W.body_force_field(w)).to(torch.float32).cuda()
+        u0 = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    else:
+        u0 = torch.from_numpy(W.initial_velocity(w)).cuda()
+    st, tmp = lat.new_state(), lat.new_state()
+    lat.init(st, u=u0)
+    st, tmp = lat.step(st, tmp, 10, force)
+    lam_a = lat.new_adjoint().normal_()
+    lam_b = lat.new_adjoint()
+    grad = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda") if force is not None else None
+    for _ in range(warmup):
+        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad)
+        lam_a, lam_b = lam_b, lam_a
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad)
+        lam_a, lam_b = lam_b, lam_a
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    mlups = lat.n / (ms * 1e-3) / 1e6
+    alg = ADJ_BYTES_PER_LUP[kind] * lat.n / (ms * 1e-3) / 1e9
+    del st, tmp, lam_a, lam_b
+    torch.cuda.empty_cache()
+    # one full backward pass of a shortened trajectory (recomputation included)
+    nsteps, every = (100, w.extra["checkpoint"]) if kind == "adjoint_f32" else (100, w.extra["checkpoint"])
+    target = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    uc = u0.clone().requires_grad_(kind == "adjoint_f16")
+    Fc = force.clone().requires_grad_(True) if force is not None else None
+    uT = ADJ.simulate(lat, uc, Fc, nsteps, every)
+    loss = 0.5 * ((uT.to(torch.float64) - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    bwd = time.perf_counter() - t0
+    log(f"[bench] {kind}: {w.nx}x{w.ny}x{w.nz} {storage}: adjoint step {ms:.3f} ms, {mlups:.0f} MLUPS, "
+        f"{alg:.0f} GB/s algorithmic; backward of {nsteps} steps (checkpoint {every}) {bwd:.3f} s "
+        f"= {lat.n * nsteps / bwd / 1e6:.0f} MLUPS incl. recomputation")
+    del lat
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "storage": storage, "mlups": round(mlups, 1), "ms_per_step": round(ms, 4),
+            "hbm_gbs_algorithmic": round(alg, 1), "hbm_frac": round(alg / HBM_PEAK_GBS, 4),
+            "bytes_per_lup": ADJ_BYTES_PER_LUP[kind],
+            "backward_mlups_incl_recompute": round(lat_n(w) * nsteps / bwd / 1e6, 1),
+            "backward_steps": nsteps, "checkpoint_every": every}
+
+
+def lat_n(w):
+    return w.nx * w.ny * w.nz
+
+
 def cpu_baseline(w):
     """FP64 oracle on a 64x64x32 replica of the workload, a few steps, all host cores."""
     import oracle
@@ -167,7 +237,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--variants", default="f32,f16,bf16")
+    ap.add_argument("--variants", default="f32,f16,bf16,adjoint_f32,adjoint_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -190,6 +260,10 @@ def main():
             res[v] = run_forward(w, v, args.steps, args.warmup, u0_dev)
     del u0_dev
     torch.cuda.empty_cache()
+    adj = {}
+    for v in variants:
+        if v in ADJ_BYTES_PER_LUP:
+            adj[v] = run_adjoint(v, max(20, args.steps // 4), 3)
 
     main_v = "f32" if "f32" in res else next(iter(res))
     r = res[main_v]
@@ -204,6 +278,7 @@ def main():
         variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
                            "hbm_gbs_algorithmic": round(ach, 1), "hbm_frac": round(ach / HBM_PEAK_GBS, 4),
                            "bytes_per_lup": BYTES_PER_LUP[v]}
+    variants_out.update(adj)
     if "f32" in res:
         for v in ("f16", "bf16"):
             if v in res:

@@ -1,0 +1,80 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every function include/lbm.h declares, and validates parameters."""
+
+import ctypes
+
+import pytest
+import torch
+
+from paper_2107_14774_amd import _lib
+import paper_2107_14774_amd as P
+
+
+def test_library_exports_every_declared_function():
+    lib = _lib.load()
+    names = _lib.header_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib._SIGNATURES), "binding and header disagree"
+
+
+def test_params_struct_layout_matches_header():
+    # int32 x3, pad, double x6, int32 x4, double, double[3]
+    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 4 + 8 + 24
+
+
+def test_create_sizes_and_padding():
+    h = P.lbm_create(32, 32, 16, r=1.0, s=0.5, omega_nu=1.4, omega_xi=1.2)
+    assert h.n == 32 * 32 * 16
+    assert h.stride >= h.n and h.stride % 256 == 0
+    assert h.state_bytes == 27 * h.stride * 4
+    h16 = P.lbm_create(512, 512, 256, r=1.0, s=0.5, storage="f16")
+    assert h16.stride == 512 * 512 * 256 + 256          # power-of-two pitch moved by 256
+    assert h16.state_bytes == 27 * h16.stride * 2
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=0), "grid sizes"),
+    (dict(omega_nu=2.0), "omega"),
+    (dict(omega_xi=0.0), "omega"),
+    (dict(omega_hi=1.2), "omega_hi"),
+    (dict(r=-1.0), "r and s"),
+    (dict(cs2=0.5, s=0.5), "cs2"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(ny=1, bc_y="bounceback"), "bounce-back"),
+    (dict(force=(float("nan"), 0.0, 0.0)), "non-finite"),
+])
+def test_create_rejects_invalid(kw, msg):
+    args = dict(nx=4, ny=4, nz=4, r=1.0, s=1.0)
+    args.update(kw)
+    with pytest.raises(_lib.LbmError) as e:
+        P.lbm_create(**args)
+    assert e.value.code == _lib.LBM_EINVAL
+    assert msg in str(e.value)
+
+
+def test_default_sound_speed_is_min_over_three():
+    # cs2 <= 0 selects min(r^2, s^2)/3; the derived constants are visible through the state size only,
+    # so check that a cs2 that would give a negative rest weight is rejected while the default is not
+    P.lbm_create(4, 4, 4, r=0.5, s=0.25, cs2=0.0)
+    with pytest.raises(_lib.LbmError):
+        P.lbm_create(4, 4, 4, r=0.5, s=0.25, cs2=0.07)
+
+
+def test_null_handle_and_null_pointers():
+    lib = _lib.load()
+    assert lib.lbm_step(None, 1, None, None, None, None) == _lib.LBM_ESTATE
+    assert b"NULL handle" in lib.lbm_last_error()
+    h = P.lbm_create(4, 4, 4)
+    assert lib.lbm_step(h.raw, 1, None, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step(h.raw, -1, None, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_check_sums(None, None, None) == _lib.LBM_EINVAL
+    # misaligned pointers are rejected before any launch
+    assert lib.lbm_import(h.raw, ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), None) == _lib.LBM_EINVAL
+
+
+def test_binding_rejects_host_tensors():
+    h = P.lbm_create(4, 4, 4)
+    with pytest.raises(ValueError):
+        P.lbm_step(h, 1, torch.empty(h.state_bytes, dtype=torch.uint8), torch.empty(h.state_bytes, dtype=torch.uint8))

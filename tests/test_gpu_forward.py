@@ -171,3 +171,19 @@ def test_duct_replica_matches_oracle():
     err = rel_l2(m.u.cpu(), u)
     _say(f"duct replica 100 steps: rel L2(u) = {err:.3e}")
     assert err <= 1e-5
+
+
+def test_nonfinite_totals_are_reported():
+    """A NaN population makes lbm_check_sums return LBM_ENONFINITE (failure detection)."""
+    from paper_2107_14774_amd import _lib
+    import paper_2107_14774_amd as P
+    p = oracle.Params(8, 6, 4)
+    f0 = fp32_rounded_state(random_state(p, 9), p)
+    f0[3, 1, 2, 3] = float("nan")
+    lat = gpu_lattice(p)
+    st = lat.new_state()
+    lat.import_populations(st, f0.cuda())
+    m = lat.moments(st)
+    with pytest.raises(_lib.LbmError) as e:
+        P.lbm_check_sums(m.sums)
+    assert e.value.code == _lib.LBM_ENONFINITE
