@@ -265,14 +265,19 @@ def main():
         if v in ADJ_BYTES_PER_LUP:
             adj[v] = run_adjoint(v, max(20, args.steps // 4), 3)
 
-    main_v = "f32" if "f32" in res else next(iter(res))
-    r = res[main_v]
-    achieved = BYTES_PER_LUP[main_v] * (w.n) / (r["ms_per_launch"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main_v),
-                "kernel": "k_step<f32, local corrections>", "algorithmic_bytes_per_lup": BYTES_PER_LUP[main_v],
-                "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     variants_out = {}
+    roofline = None
+    r = None
+    main_v = None
+    if res:
+        main_v = "f32" if "f32" in res else next(iter(res))
+        r = res[main_v]
+        achieved = BYTES_PER_LUP[main_v] * (w.n) / (r["ms_per_launch"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main_v),
+                    "kernel": f"k_step<{main_v}, local corrections>",
+                    "algorithmic_bytes_per_lup": BYTES_PER_LUP[main_v],
+                    "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     for v, rv in res.items():
         ach = BYTES_PER_LUP[v] * w.n / (rv["ms_per_launch"] * 1e-3) / 1e9
         variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
@@ -286,12 +291,12 @@ def main():
 
     line = {
         "metric": "MLUPS and % HBM roofline: plain FP32 vs BF16/FP16-storage vs adjoint",
-        "value": round(r["mlups"], 1),
+        "value": round(r["mlups"], 1) if r else None,
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r["wall_s"] / args.steps * 1e3, 4),
+        "ms_per_step": round(r["wall_s"] / args.steps * 1e3, 4) if r else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -299,7 +304,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "r": w.r, "s": w.s,
                    "cs2": w.cs2, "nu": w.nu, "corrections": "local", "boundaries": "periodic",
-                   "storage": main_v},
+                   "storage": main_v or "none"},
         "roofline": roofline,
         "variants": variants_out,
     }

@@ -11,9 +11,14 @@ inside the adjoint step kernel.
 
 Memory: the forward keeps one state every ``checkpoint_every`` steps; the
 backward recomputes one segment at a time from its checkpoint, holding that
-segment's states (at most checkpoint_every of them) while it steps back
-through it.  Peak memory is (nsteps / K + K) states plus two adjoint buffers.
+segment's states while it steps back through it.  A segment longer than
+``max_states`` is split again: its sub-segment starts (about sqrt(K) of
+them) are recomputed and kept, then each sub-segment is recomputed and
+reversed in turn (one extra forward pass per segment).  Peak memory is about
+nsteps/K + min(K, 2 sqrt(K)) states plus two adjoint buffers.
 """
+
+import math
 
 import torch
 
@@ -22,7 +27,7 @@ from . import lbm as L
 
 class _Trajectory(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, force, lat, rho0, nsteps, every):
+    def forward(ctx, u0, force, lat, rho0, nsteps, every, max_states):
         force_t = force if force.numel() else None
         a, b = lat.new_state(), lat.new_state()
         lat.init(a, rho=rho0, u=u0)
@@ -35,7 +40,7 @@ class _Trajectory(torch.autograd.Function):
             if t < nsteps:
                 checkpoints.append(a.clone())
         m = lat.moments(a, force_t, sums=False)
-        ctx.lat, ctx.nsteps, ctx.every = lat, nsteps, every
+        ctx.lat, ctx.nsteps, ctx.every, ctx.max_states = lat, nsteps, every, max_states
         ctx.checkpoints, ctx.final = checkpoints, a
         ctx.force, ctx.rho0 = force_t, rho0
         ctx.save_for_backward(u0)
@@ -56,38 +61,74 @@ class _Trajectory(torch.autograd.Function):
                               grad_force=grad_force)
         ctx.final = None
         nseg = len(ctx.checkpoints)
-        pool = []
-        scratch = lat.new_state()
+        pool = _StatePool(lat)
         for seg in reversed(range(nseg)):
             start = seg * ctx.every
             n = min(ctx.every, ctx.nsteps - start)
-            # states h(start) .. h(start + n - 1) of this segment
-            while len(pool) < n:
-                pool.append(lat.new_state())
-            pool[0].copy_(ctx.checkpoints[seg])
-            for i in range(1, n):
-                L.lbm_step(h, 1, pool[i - 1], scratch, force)
-                pool[i].copy_(scratch)
-            for i in reversed(range(n)):
-                L.lbm_step_adjoint(h, pool[i], lam, lam_next, force, grad_force)
-                lam, lam_next = lam_next, lam
+            lam, lam_next = _reverse_segment(lat, ctx.checkpoints[seg], n, lam, lam_next, force, grad_force,
+                                             ctx.max_states, pool)
             ctx.checkpoints[seg] = None
         g_u0 = torch.empty((3, *lat.shape), dtype=torch.float64, device=lat.device)
         rho0 = None if ctx.rho0 is None else ctx.rho0.to(torch.float64).contiguous()
         L.lbm_init_adjoint(h, lam, rho=rho0, u=u0.contiguous(), g_u=g_u0)
-        return g_u0, grad_force, None, None, None, None
+        return g_u0, grad_force, None, None, None, None, None
 
 
-def simulate(lat, u0, force=None, nsteps=1, checkpoint_every=50, rho0=None):
+class _StatePool:
+    """Reusable state buffers for the recomputation (allocated on first use)."""
+
+    def __init__(self, lat):
+        self.lat, self.free = lat, []
+
+    def get(self):
+        return self.free.pop() if self.free else self.lat.new_state()
+
+    def put(self, *states):
+        self.free.extend(states)
+
+
+def _reverse_segment(lat, start_state, n, lam, lam_next, force, grad_force, max_states, pool):
+    """Apply the adjoint of n steps starting from ``start_state``; returns the swapped adjoint buffers."""
+    h = lat.h
+    if n <= max_states:
+        states = [start_state] + [pool.get() for _ in range(n - 1)]
+        for i in range(1, n):
+            L.lbm_step(h, 1, states[i - 1], states[i], force)
+        for i in reversed(range(n)):
+            L.lbm_step_adjoint(h, states[i], lam, lam_next, force, grad_force)
+            lam, lam_next = lam_next, lam
+        pool.put(*states[1:])
+        return lam, lam_next
+    sub = max(1, math.ceil(math.sqrt(n)))
+    starts = []
+    cur, tmp = pool.get(), pool.get()
+    cur.copy_(start_state)
+    for s0 in range(0, n, sub):
+        keep = pool.get()
+        keep.copy_(cur)
+        starts.append(keep)
+        m = min(sub, n - s0)
+        if s0 + m < n:
+            cur, tmp = lat.step(cur, tmp, m, force)
+    pool.put(cur, tmp)
+    for j in reversed(range(len(starts))):
+        m = min(sub, n - j * sub)
+        lam, lam_next = _reverse_segment(lat, starts[j], m, lam, lam_next, force, grad_force, max_states, pool)
+        pool.put(starts[j])
+    return lam, lam_next
+
+
+def simulate(lat, u0, force=None, nsteps=1, checkpoint_every=50, rho0=None, max_states=128):
     """u(T) after ``nsteps`` steps from f_eq(rho0, u0); differentiable in u0 and force.
 
     lat:   a ``Lattice``
     u0:    (3, nz, ny, nx) float64 on the lattice device
     force: (3, nz, ny, nx) float32 per-node body force, or None for the lattice's uniform force
+    max_states: most states one segment may hold during the backward pass (nesting beyond)
     """
     if force is None:
         force = torch.empty(0, dtype=torch.float32, device=lat.device)
-    return _Trajectory.apply(u0, force, lat, rho0, int(nsteps), int(checkpoint_every))
+    return _Trajectory.apply(u0, force, lat, rho0, int(nsteps), int(checkpoint_every), int(max_states))
 
 
 def uniform_force_gradient(lat, state_t, lam_in, lam_out, force=None):

@@ -12,6 +12,13 @@
 // A1 and dA1/du = 2 A2, which keeps the velocity derivatives short.
 #include "lbm_internal.h"
 
+// Occupancy requested from the register allocator for the adjoint step:
+// 3 waves per SIMD fit the 16-bit variants without spills (measured faster
+// on 384x384x192); the FP32 variants would spill, so they get no bound.
+#ifndef LBM_ADJ_WAVES_16
+#define LBM_ADJ_WAVES_16 3
+#endif
+
 namespace clbm {
 
 // lambda^T dC/d(df, F) at one node: mu = (dC/d df)^T lam, gf = (dC/dF)^T lam.
@@ -232,31 +239,55 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-template <int ST, int CORR>
-__global__ __launch_bounds__(256) void k_step_adjoint(const typename Store<ST>::T* __restrict__ state,
-                                                      const float* __restrict__ adj_in, float* __restrict__ adj_out,
-                                                      const float* __restrict__ force, float* __restrict__ grad_force,
-                                                      double* __restrict__ grad_uniform, Consts k, uint32_t bpr) {
+// Per-direction base pointers of one adjoint step.
+template <typename T>
+struct AdjPtrs {
+  const T* state[27];
+  const float* lin[27];
+  float* lout[27];
+};
+
+template <int A = 0>
+__device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const PeriodicRows& pr,
+                                                 const float (&mu)[27]) {
+  // plain stores: the shifted scatter writes partial lines that L2 merges with the neighbours'
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(dst[A]) + (uint32_t)(periodic_src<A>(pr) * 4u)) = mu[A];
+  if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
+}
+
+template <int ST, int CORR, bool WALLS>
+__global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
+                                                      float* __restrict__ grad_force, double* __restrict__ grad_uniform,
+                                                      Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   float gfx = 0.0f, gfy = 0.0f, gfz = 0.0f;
   if (x < k.nx) {
-    const NodeCoord c = make_coord(x, y, z, k);
-    const int64_t node = ((int64_t)z * k.ny + y) * k.nx + x;
+    const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
     float df[27], lam[27], mu[27];
-    gather_all<ST>(state, c, k, df);
+    PeriodicRows pr;
+    if constexpr (WALLS) {
+      gather_all<ST>(P.state[0], make_coord(x, y, z, k), k, df);
+    } else {
+      periodic_rows(x, y, z, k, pr);
+      gather_periodic<ST>(P.state, pr, k, df);
+    }
 #pragma unroll
-    for (int a = 0; a < 27; ++a) lam[a] = adj_in[a * k.stride + node];
+    for (int a = 0; a < 27; ++a) lam[a] = ld_off(P.lin[a], node);
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
-      fx = force[node];
-      fy = force[k.n + node];
-      fz = force[2 * k.n + node];
+      fx = ld_off(force, node);
+      fy = ld_off(force + k.n, node);
+      fz = ld_off(force + 2 * k.n, node);
     }
     collide_vjp<CORR>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
-    scatter_all(adj_out, c, k, mu);
+    if constexpr (WALLS) {
+      scatter_all(P.lout[0], make_coord(x, y, z, k), k, mu);
+    } else {
+      scatter_periodic(P.lout, pr, mu);
+    }
     if (grad_force != nullptr) {
       grad_force[node] += gfx;
       grad_force[k.n + node] += gfy;
@@ -423,20 +454,22 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  const T* s = (const T*)state;
-  switch (h.p.corr) {
-    case LBM_CORR_OFF:
-      hipLaunchKernelGGL((k_step_adjoint<ST, 0>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
-                         grad_force, grad_uniform, h.k, bpr);
-      break;
-    case LBM_CORR_LOWMACH:
-      hipLaunchKernelGGL((k_step_adjoint<ST, 1>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
-                         grad_force, grad_uniform, h.k, bpr);
-      break;
-    default:
-      hipLaunchKernelGGL((k_step_adjoint<ST, 2>), dim3((unsigned)nb), dim3(block), 0, st, s, adj_in, adj_out, force,
-                         grad_force, grad_uniform, h.k, bpr);
-      break;
+  AdjPtrs<T> P;
+  for (int a = 0; a < 27; ++a) {
+    P.state[a] = (const T*)state + (int64_t)a * h.stride;
+    P.lin[a] = adj_in + (int64_t)a * h.stride;
+    P.lout[a] = adj_out + (int64_t)a * h.stride;
+  }
+  // 32-bit offsets need every (float) adjoint array below 4 GiB
+  const bool walls = h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * 4u >= (1ull << 32);
+  const dim3 grid((unsigned)nb), blk(block);
+  switch (h.p.corr * 2 + (walls ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_step_adjoint<ST, 0, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_step_adjoint<ST, 0, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+    case 2: hipLaunchKernelGGL((k_step_adjoint<ST, 1, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+    case 3: hipLaunchKernelGGL((k_step_adjoint<ST, 1, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+    case 4: hipLaunchKernelGGL((k_step_adjoint<ST, 2, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_step_adjoint<ST, 2, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
   }
   return hipGetLastError();
 }

@@ -359,4 +359,36 @@ struct DirPtrs {
   T* dst[27];
 };
 
+// Source offsets of the periodic fast path: the node x - ebar for every
+// direction is row[ebar_y + 1][ebar_z + 1] + xs[ebar_x + 1] (32-bit node index).
+struct PeriodicRows {
+  uint32_t row[3][3];
+  uint32_t xs[3];
+};
+
+__device__ __forceinline__ void periodic_rows(int x, int y, int z, const Consts& k, PeriodicRows& pr) {
+  pr.xs[0] = (uint32_t)(x == k.nx - 1 ? 0 : x + 1);
+  pr.xs[1] = (uint32_t)x;
+  pr.xs[2] = (uint32_t)(x == 0 ? k.nx - 1 : x - 1);
+  const uint32_t ys[3] = {(uint32_t)(y == k.ny - 1 ? 0 : y + 1), (uint32_t)y, (uint32_t)(y == 0 ? k.ny - 1 : y - 1)};
+  const uint32_t zs[3] = {(uint32_t)(z == k.nz - 1 ? 0 : z + 1), (uint32_t)z, (uint32_t)(z == 0 ? k.nz - 1 : z - 1)};
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) pr.row[j][l] = (zs[l] * (uint32_t)k.ny + ys[j]) * (uint32_t)k.nx;
+}
+
+template <int A>
+__device__ __forceinline__ uint32_t periodic_src(const PeriodicRows& pr) {
+  return pr.row[kEy[A] + 1][kEz[A] + 1] + pr.xs[kEx[A] + 1];
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* const (&src)[27], const PeriodicRows& pr,
+                                                const Consts& k, float (&df)[27]) {
+  const float v = Store<ST>::load_val(ld_off(src[A], periodic_src<A>(pr)));
+  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
+  if constexpr (A + 1 < 27) gather_periodic<ST, A + 1>(src, pr, k, df);
+}
+
 }  // namespace clbm

@@ -11,17 +11,6 @@ namespace clbm {
 // (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
 // base pointer plus a 32-bit node index shared by the three directions of
 // one source row; with walls the general slot rule of gather_slot applies.
-template <int ST, int A = 0>
-__device__ __forceinline__ void gather_periodic(const DirPtrs<typename Store<ST>::T>& P,
-                                                const uint32_t (&row)[3][3], const uint32_t (&xs)[3],
-                                                const Consts& k, float (&df)[27]) {
-  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
-  const uint32_t off = row[ey + 1][ez + 1] + xs[ex + 1];
-  const float v = Store<ST>::load_val(ld_off(P.src[A], off));
-  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
-  if constexpr (A + 1 < 27) gather_periodic<ST, A + 1>(P, row, xs, k, df);
-}
-
 template <int ST, int CORR, bool WALLS>
 __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
                                               const float* __restrict__ force, Consts k, uint32_t bpr) {
@@ -35,16 +24,9 @@ __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
   if constexpr (WALLS) {
     gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
   } else {
-    // source coordinates x - ebar for ebar = -1, 0, +1
-    const uint32_t xs[3] = {(uint32_t)(x == k.nx - 1 ? 0 : x + 1), (uint32_t)x, (uint32_t)(x == 0 ? k.nx - 1 : x - 1)};
-    const uint32_t ys[3] = {(uint32_t)(y == k.ny - 1 ? 0 : y + 1), (uint32_t)y, (uint32_t)(y == 0 ? k.ny - 1 : y - 1)};
-    const uint32_t zs[3] = {(uint32_t)(z == k.nz - 1 ? 0 : z + 1), (uint32_t)z, (uint32_t)(z == 0 ? k.nz - 1 : z - 1)};
-    uint32_t row[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int l = 0; l < 3; ++l) row[j][l] = (zs[l] * (uint32_t)k.ny + ys[j]) * (uint32_t)k.nx;
-    gather_periodic<ST>(P, row, xs, k, df);
+    PeriodicRows pr;
+    periodic_rows(x, y, z, k, pr);
+    gather_periodic<ST>(P.src, pr, k, df);
   }
   float fx = k.fx, fy = k.fy, fz = k.fz;
   if (force != nullptr) {

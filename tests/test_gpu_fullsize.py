@@ -1,0 +1,140 @@
+"""GPU checks at the workloads' full sizes and launch configurations.
+
+* 512x512x256 (r = 1, s = 1/2): one FP32 step of the throughput workload,
+  compared element by element with the FP64 oracle on 64 seeded nodes; the
+  oracle collides the 27 upstream neighbours of each sampled node (from the
+  same generated initial field) and streams them into it.
+* 64x128x32 duct (r = 1, s = 1/4, walls in y and z): 20,000 steps to steady
+  state against the rectangular-duct series.
+* 384x384x192 FP16 adjoint (r = 1/2, s = 1/4): gradient of the final-velocity
+  loss with respect to the initial velocity after 1000 steps (checkpoint every
+  100), FP16 storage against FP32 storage (stated error), and the FP16 path
+  against the FP64 oracle on a small replica (stated error).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import analytic as A
+from oracle import collision as C
+from oracle import equilibrium as EQ
+from oracle import gradient as G
+from oracle import lattice as LT
+import workloads as W
+import paper_2107_14774_amd as P
+from paper_2107_14774_amd import adjoint as ADJ
+from helpers import gpu_lattice, oracle_params, rel_l2
+
+pytestmark = pytest.mark.gpu
+DT = torch.float64
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_throughput_workload_one_step_sampled():
+    w = W.DECAYING_512
+    p = oracle_params(w)
+    _say("generating the 512x512x256 initial field")
+    u0 = W.initial_velocity(w)
+    lat = gpu_lattice(p)
+    a, b = lat.new_state(), lat.new_state()
+    lat.init(a, u=torch.from_numpy(u0).cuda())
+    cur, _ = lat.step(a, b, 1)
+    del a
+    samples = W.sample_indices(64, p.n, 77)
+    zs, ys, xs = np.unravel_index(samples, p.shape)
+    f_gpu = torch.empty((27, len(samples)), dtype=DT)
+    full = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_export(lat.h, cur, full)
+    idx = torch.from_numpy(np.stack([zs, ys, xs])).cuda()
+    f_gpu = full[:, idx[0], idx[1], idx[2]].cpu()
+    del full
+    # oracle: collide every upstream neighbour from f_eq(1, u0) and stream into the sampled node
+    eb = LT.ebar().numpy()
+    nb_z = (zs[None, :] - eb[:, 2:3]) % p.nz
+    nb_y = (ys[None, :] - eb[:, 1:2]) % p.ny
+    nb_x = (xs[None, :] - eb[:, 0:1]) % p.nx
+    u_nb = torch.from_numpy(np.stack([u0[c][nb_z, nb_y, nb_x] for c in range(3)], -1).reshape(-1, 3))
+    f_nb = EQ.feq(torch.ones(u_nb.shape[0], dtype=DT), u_nb, p.r, p.s, p.cs2)
+    ft = C.collide(f_nb, torch.zeros(u_nb.shape[0], 3, dtype=DT), p).reshape(27, len(samples), 27)
+    want = torch.stack([ft[a_, :, a_] for a_ in range(27)])      # f_a(x) = f~_a(x - e_a)
+    err = (f_gpu - want).abs().max().item()
+    _say(f"512x512x256 one step, 64 sampled nodes: max |f_gpu - f_oracle| = {err:.3e}")
+    assert err < 2e-7
+
+
+def test_duct_workload_steady_state_matches_series():
+    w = W.DUCT_64
+    p = oracle_params(w)
+    a_half, b_half = p.ny * p.r / 2, p.nz * p.s / 2
+    fx = A.duct_force_for_centre_velocity(w.extra["u_centre"], a_half, b_half, 1.0, w.nu)
+    lat = gpu_lattice(p, force=(fx, 0.0, 0.0))
+    a, b = lat.new_state(), lat.new_state()
+    lat.init(a)
+    cur, nxt = lat.step(a, b, w.steps - 1000)
+    u_prev = lat.moments(cur).u[0].clone()
+    cur, nxt = lat.step(cur, nxt, 1000)
+    m = lat.moments(cur)
+    u = m.u[0].cpu().to(DT)
+    drift = ((m.u[0] - u_prev).norm() / m.u[0].norm()).item()
+    y = (np.arange(p.ny) + 0.5) * p.r - a_half
+    z = (np.arange(p.nz) + 0.5) * p.s - b_half
+    Z, Y = np.meshgrid(z, y, indexing="ij")
+    ref = torch.from_numpy(A.duct_series(Y, Z, a_half, b_half, fx, 1.0, w.nu))
+    prof = u.mean(-1)                                  # x is homogeneous
+    err = rel_l2(prof, ref)
+    xspread = (u - prof[..., None]).abs().max().item()
+    _say(f"duct 64x128x32, {w.steps} steps: rel L2 vs series {err:.3e}, change over the last 1000 steps "
+         f"{drift:.2e}, centre velocity {prof[p.nz // 2, p.ny // 2].item():.5f} (target "
+         f"{w.extra['u_centre']:.5f}), x-variation {xspread:.1e}")
+    assert err < 0.01
+    assert xspread < 1e-8
+
+
+def test_fp16_initial_velocity_gradient_full_size():
+    w = W.ADJOINT_F16_384
+    p = oracle_params(w)
+    u0 = torch.from_numpy(W.initial_velocity(w)).cuda()
+    target = torch.from_numpy(W.target_velocity(w)).cuda()
+    grads = {}
+    for storage, cap in (("f16", 128), ("f32", 12)):
+        lat = gpu_lattice(p, storage=storage)
+        uc = u0.clone().requires_grad_(True)
+        u = ADJ.simulate(lat, uc, None, w.steps, w.extra["checkpoint"], max_states=cap)
+        loss = 0.5 * ((u.to(DT) - target) ** 2).sum()
+        loss.backward()
+        grads[storage] = uc.grad
+        _say(f"{storage}: loss {loss.item():.6e}, |grad| {uc.grad.norm().item():.6e}")
+        del lat, u, uc
+        torch.cuda.empty_cache()
+    err = rel_l2(grads["f16"].cpu(), grads["f32"].cpu())
+    _say(f"384x384x192, 1000 steps: FP16-storage gradient vs FP32-storage gradient, rel L2 {err:.3e}")
+    assert err < 5e-3
+
+
+def test_fp16_gradient_vs_oracle_replica():
+    w = W.ADJOINT_F16_384
+    p = oracle_params(w, nx=16, ny=16, nz=8)
+    u0 = torch.from_numpy(W.random_modes(p.nx, p.ny, p.nz, p.r, p.s, 2, w.extra["rms"], w.extra["seed"]))
+    target = torch.from_numpy(W.random_modes(p.nx, p.ny, p.nz, p.r, p.s, 2, w.extra["rms"], 50))
+    nsteps = 50
+    _, _, gu_o = G.loss_and_gradients(p, torch.ones(p.shape, dtype=DT), u0, torch.zeros(3, *p.shape, dtype=DT),
+                                      target, nsteps)
+    out = {}
+    for storage in ("f16", "bf16", "f32"):
+        lat = gpu_lattice(p, storage=storage)
+        uc = u0.cuda().requires_grad_(True)
+        u = ADJ.simulate(lat, uc, None, nsteps, 10)
+        (0.5 * ((u.to(DT) - target.cuda()) ** 2).sum()).backward()
+        out[storage] = rel_l2(uc.grad.cpu(), gu_o)
+    _say("replica 16x16x8 (r=1/2, s=1/4), 50 steps, dL/du0 rel L2 vs FP64 oracle: "
+         + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
+    assert out["f32"] < 1e-4
+    assert out["f16"] < 1e-3 and out["bf16"] < 1e-2
