@@ -196,7 +196,7 @@ def run_adjoint(kind, steps, warmup):
     torch.cuda.empty_cache()
     return {"workload": w.name, "storage": storage, "mlups": round(mlups, 1), "ms_per_step": round(ms, 4),
             "hbm_gbs_algorithmic": round(alg, 1), "hbm_frac": round(alg / HBM_PEAK_GBS, 4),
-            "bytes_per_lup": ADJ_BYTES_PER_LUP[kind],
+            "bytes_per_lup": ADJ_BYTES_PER_LUP[kind], "measured_bytes_per_launch": measured_traffic(kind),
             "backward_mlups_incl_recompute": round(lat_n(w) * nsteps / bwd / 1e6, 1),
             "backward_steps": nsteps, "checkpoint_every": every}
 
@@ -282,7 +282,7 @@ def main():
         ach = BYTES_PER_LUP[v] * w.n / (rv["ms_per_launch"] * 1e-3) / 1e9
         variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
                            "hbm_gbs_algorithmic": round(ach, 1), "hbm_frac": round(ach / HBM_PEAK_GBS, 4),
-                           "bytes_per_lup": BYTES_PER_LUP[v]}
+                           "bytes_per_lup": BYTES_PER_LUP[v], "measured_bytes_per_launch": measured_traffic(v)}
     variants_out.update(adj)
     if "f32" in res:
         for v in ("f16", "bf16"):

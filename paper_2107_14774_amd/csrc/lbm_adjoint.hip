@@ -450,7 +450,7 @@ template <int ST>
 static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                         const float* force, float* grad_force, double* grad_uniform, hipStream_t st) {
   using T = typename Store<ST>::T;
-  const int block = 256;
+  const int block = h.block;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;

@@ -71,10 +71,19 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   h->stride = padded_stride(n);
   h->elem = q.storage == LBM_F32 ? 4 : 2;
   h->bytes = (size_t)27 * (size_t)h->stride * h->elem;
+  // threads per block along x: the largest of 256, 192, 128, 64 that leaves the
+  // fewest idle lanes in the last block of a row (e.g. 192 for nx = 384)
   h->block = 256;
+  {
+    int best_waste = 1 << 30;
+    for (int b : {256, 192, 128, 64}) {
+      const int waste = (q.nx + b - 1) / b * b - q.nx;
+      if (waste < best_waste) { best_waste = waste; h->block = b; }
+    }
+  }
   if (const char* env = std::getenv("LBM_BLOCK")) {
     const int b = std::atoi(env);
-    if (b == 64 || b == 128 || b == 256) h->block = b;
+    if (b == 64 || b == 128 || b == 192 || b == 256) h->block = b;
   }
 
   const double c[3] = {1.0, q.r, q.s};
