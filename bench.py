@@ -41,8 +41,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108}
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
 ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
-KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip")
-ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint.hip")
+KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip",
+                  "paper_2107_14774_amd/csrc/lbm_api.hip")
+ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint.hip",
+                   "paper_2107_14774_amd/csrc/lbm_api.hip")
 
 
 def log(*a):
@@ -67,7 +69,7 @@ def measured_traffic(kind):
     entry = rec.get(kind)
     if not entry:
         return None
-    srcs = KERNEL_SOURCES if kind != "adjoint" else ADJOINT_SOURCES
+    srcs = ADJOINT_SOURCES if kind.startswith("adjoint") else KERNEL_SOURCES
     if entry.get("source_sha") != sources_sha(srcs):
         return None
     return entry.get("bytes_per_launch")
