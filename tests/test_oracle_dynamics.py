@@ -9,7 +9,8 @@
 * mass and momentum budgets over many steps (periodic and bounce-back);
 * fully developed rectangular-duct flow against its Fourier series (the
   generalisation of eq. 70);
-* local strain rates (eq. 49) against the derivative of the velocity.
+* local strain rates (eq. 49) against the derivative of the velocity;
+* Galilean invariance: the 3u^2 terms make the decay independent of a carrier velocity.
 """
 
 import math
@@ -236,3 +237,40 @@ def test_strain_rates_match_velocity_gradient():
     assert abs(acc[0] / acc[1] - 1) < 0.03, acc
     assert abs(acc[2] / acc[3] - 1) < 0.03, acc
     assert acc[4] < 0.02 * abs(acc[1])          # no y dependence -> d_y u_y ~ 0
+
+
+def advected_rate_ratio(corr, U0, axis, r=1.0, s=0.5, lam=32.0, omega=1.2, steps=240, amp=1e-4):
+    """Decay rate of an xz-plane Taylor-Green vortex carried by a uniform velocity U0 along ``axis``."""
+    p = oracle.Params(int(lam), 1, int(round(lam / s)), r=r, s=s, omega_nu=omega, omega_xi=omega, corr=corr)
+    k = 2 * math.pi / lam
+    X = _coords(p)
+    sx = (torch.sin(k * X["x"]) * torch.cos(k * X["z"])).expand(p.shape)
+    u = torch.zeros(3, *p.shape, dtype=DT)
+    u[0] = amp * sx
+    u[2] = (-amp * torch.cos(k * X["x"]) * torch.sin(k * X["z"])).expand(p.shape)
+    ia = "xyz".index(axis)
+    u[ia] = u[ia] + U0
+    f = lbm.init_equilibrium(torch.ones(p.shape, dtype=DT), u, p)
+    ts, energy = [], []
+    for t in range(steps + 1):
+        if t >= 40 and t % 10 == 0:
+            _, uu = lbm.observables(f, p)
+            du = uu.clone()
+            du[ia] = du[ia] - U0
+            ts.append(t)
+            energy.append(float((du ** 2).sum()))
+        f = lbm.step(f, p)
+    nu = A.nu_from_omega(omega, p.cs2)
+    return _fit_rate(ts, np.sqrt(energy)) / A.taylor_green_decay_rate(nu, k, k)
+
+
+def test_galilean_invariance_of_the_cubic_velocity_terms():
+    """With the 3u^2 terms (eq. 38-40, App. D) the decay rate does not depend on a uniform
+    carrier velocity; without them (low-Mach form of Sec. 2.4) it does."""
+    base = advected_rate_ratio("local", 0.0, "x")
+    for U0, axis in ((0.1, "x"), (0.05, "z")):
+        q = advected_rate_ratio("local", U0, axis)
+        assert abs(q - base) < 0.003, (U0, axis, q, base)
+    low0 = advected_rate_ratio("lowmach", 0.0, "x")
+    low = advected_rate_ratio("lowmach", 0.1, "x")
+    assert abs(low - low0) > 0.008, (low, low0)
