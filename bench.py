@@ -38,7 +38,12 @@ import torch  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108}
+BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108,
+                 # full corrections, lagged density gradient: + write and read of the density deviation field
+                 "full_f32": 216 + 8, "full_f16": 108 + 8,
+                 # exact density gradient: + a density pass (one more state read, one field write)
+                 "full_f32_exact": 216 + 4 + 108 + 4}
+FULL_VARIANTS = {"full_f32": ("f32", "lagged"), "full_f16": ("f16", "lagged"), "full_f32_exact": ("f32", "exact")}
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
 ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
 KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip",
@@ -75,17 +80,26 @@ def measured_traffic(kind):
     return entry.get("bytes_per_launch")
 
 
-def time_steps(lat, a, b, steps, warmup, force=None):
-    """Warm up, then time exactly `steps` launches; returns (wall s, event ms per launch, a, b)."""
+def time_steps(lat, a, b, steps, warmup, force=None, full_mode=None):
+    """Warm up, then time exactly `steps` launches; returns (wall s, event ms per step, a, b).
+    With ``full_mode`` the full corrections run through lbm_step_full (density fields allocated here)."""
     import paper_2107_14774_amd as P
+    if full_mode is not None:
+        da, db = lat.density(a), lat.field(1)
     if warmup:
-        a, b = lat.step(a, b, warmup, force)
+        if full_mode is None:
+            a, b = lat.step(a, b, warmup, force)
+        else:
+            a, b, da, db = lat.step_full(a, b, warmup, da, db, full_mode, force)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    P.lbm_step(lat.h, steps, a, b, force, stream=stream)
+    if full_mode is None:
+        P.lbm_step(lat.h, steps, a, b, force, stream=stream)
+    else:
+        P.lbm_step_full(lat.h, steps, a, b, da, db, full_mode, force, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -94,24 +108,24 @@ def time_steps(lat, a, b, steps, warmup, force=None):
     return wall, ev0.elapsed_time(ev1) / steps, a, b
 
 
-def run_forward(w, storage, steps, warmup, u0_dev):
+def run_forward(w, variant, steps, warmup, u0_dev):
     import paper_2107_14774_amd as P
+    storage, mode = FULL_VARIANTS.get(variant, (variant, None))
     on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
     lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
-                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local" if mode is None else "full")
     a, b = lat.new_state(), lat.new_state()
     lat.init(a, u=u0_dev)
     torch.cuda.synchronize()
-    log(f"[bench] {storage}: {w.nx}x{w.ny}x{w.nz}, state {lat.h.state_bytes / 2**30:.2f} GiB, "
+    log(f"[bench] {variant}: {w.nx}x{w.ny}x{w.nz}, state {lat.h.state_bytes / 2**30:.2f} GiB, "
         f"{warmup} warmup + {steps} timed steps")
-    wall, ms_launch, a, b = time_steps(lat, a, b, steps, warmup)
+    wall, ms_launch, a, b = time_steps(lat, a, b, steps, warmup, full_mode=mode)
     m = lat.moments(a)
-    import paper_2107_14774_amd as P2
-    sums = P2.lbm_check_sums(m.sums)
+    sums = P.lbm_check_sums(m.sums)
     mlups = lat.n * steps / wall / 1e6
     kernel_mlups = lat.n / (ms_launch * 1e-3) / 1e6
-    log(f"[bench] {storage}: {mlups:.0f} MLUPS wall, {kernel_mlups:.0f} MLUPS per launch "
-        f"({ms_launch:.3f} ms/launch), mass {sums[0]:.6f}, energy {sums[4]:.6e}")
+    log(f"[bench] {variant}: {mlups:.0f} MLUPS wall, {kernel_mlups:.0f} MLUPS per step "
+        f"({ms_launch:.3f} ms/step), mass {sums[0]:.6f}, energy {sums[4]:.6e}")
     del a, b, lat
     torch.cuda.empty_cache()
     return {"mlups": mlups, "wall_s": wall, "ms_per_launch": ms_launch, "kernel_mlups": kernel_mlups,
@@ -239,7 +253,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--variants", default="f32,f16,bf16,adjoint_f32,adjoint_f16")
+    ap.add_argument("--variants", default="f32,f16,bf16,full_f32,full_f16,adjoint_f32,adjoint_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -273,11 +287,12 @@ def main():
     main_v = None
     if res:
         main_v = "f32" if "f32" in res else next(iter(res))
+        main_storage, main_mode = FULL_VARIANTS.get(main_v, (main_v, None))
         r = res[main_v]
         achieved = BYTES_PER_LUP[main_v] * (w.n) / (r["ms_per_launch"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main_v),
-                    "kernel": f"k_step<{main_v}, local corrections>",
+                    "kernel": f"k_step<{main_storage}, {'local' if main_mode is None else 'full'} corrections>",
                     "algorithmic_bytes_per_lup": BYTES_PER_LUP[main_v],
                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     for v, rv in res.items():
@@ -287,7 +302,7 @@ def main():
                            "bytes_per_lup": BYTES_PER_LUP[v], "measured_bytes_per_launch": measured_traffic(v)}
     variants_out.update(adj)
     if "f32" in res:
-        for v in ("f16", "bf16"):
+        for v in ("f16", "bf16", "full_f32", "full_f16", "full_f32_exact"):
             if v in res:
                 variants_out[v]["speedup_vs_f32"] = round(res[v]["mlups"] / res["f32"]["mlups"], 3)
 

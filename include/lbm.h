@@ -68,8 +68,15 @@ enum lbm_storage { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
  * OFF:     plain central-moment collision on the cuboid lattice;
  * LOWMACH: theta without the 3u^2 terms (last remark of Sec. 2.4);
  * LOCAL:   theta with the 3u^2 terms; the density-gradient (lambda) terms,
- *          which need a non-local finite difference, are left out. */
-enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2 };
+ *          which need a non-local finite difference, are left out;
+ * FULL:    LOCAL plus the lambda terms of eq. 38-40 and the e_rho terms of
+ *          the strain-rate system (App. D), with the density gradient from a
+ *          density field: only lbm_step_full runs it (lbm_step and
+ *          lbm_step_adjoint reject it). */
+enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2, LBM_CORR_FULL = 3 };
+
+/* Time level of the density gradient of the full corrections (lbm_step_full). */
+enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1 };
 
 typedef struct lbm_params {
   int32_t nx, ny, nz;   /* grid nodes; each >= 1; ny, nz >= 2 on a bounce-back axis */
@@ -129,6 +136,36 @@ int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream);
 int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
              const float* force, void* hip_stream);
 
+/* Density deviation rho - rho0 of every node of a state (the sum of its 27
+ * gathered populations minus rho0, eq. 12), in FP32, bit-identical to the
+ * density the step computes for that node.
+ *   drho: device float[n_nodes], written. */
+int lbm_density(lbm_handle* h, const void* state, float* drho, void* hip_stream);
+
+/* Advance nsteps >= 0 steps with the full corrections (p->corr must be
+ * LBM_CORR_FULL; LBM_EINVAL otherwise).  App. D takes the density gradient
+ * from an isotropic second-order finite difference; the library uses the
+ * lattice-weighted stencil grad rho (x) = (1/cs2) sum_a w_a e_a rho(x + ebar_a)
+ * (w_a the rest weights, e_a the cuboid velocities), with periodic wrap and,
+ * across a bounce-back wall, the boundary node's own value (its mirror
+ * image).  States behave as in lbm_step.  The density fields hold rho - rho0:
+ *   mode LBM_GRAD_EXACT:  before each step the density of its input state is
+ *       written to drho_a and the gradient is taken from it (gradient and
+ *       collision at the same time level; one more read of the state per
+ *       step).  drho_b is not used and may be NULL.
+ *   mode LBM_GRAD_LAGGED: drho_a holds on entry the field the first step
+ *       takes its gradient from (normally lbm_density of state_a, which makes
+ *       the first step exact).  Each step writes the density of its own input
+ *       state into the other buffer, and the next step takes its gradient from
+ *       there, one step behind.  On return the field the next call starts from
+ *       is in drho_a when nsteps is even and in drho_b when it is odd, so a
+ *       run split over several calls equals one call.  drho_b must differ
+ *       from drho_a.
+ *   drho_a, drho_b: device float[n_nodes]. */
+int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
+                  const float* force, float* drho_a, float* drho_b, int32_t mode,
+                  void* hip_stream);
+
 /* Observables of a state (eq. 12 / the last bullet of Sec. 3.2):
  * rho = sum f, u = (sum f e + F/2) / rho.
  *   rho:  device float[n_nodes] or NULL
@@ -159,7 +196,8 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *   grad_force: device float[3][n_nodes] or NULL: += (dh(t+1)/dF)^T lambda(t+1)
  *               for a per-node force field
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
- *               nodes (gradient with respect to the uniform force). */
+ *               nodes (gradient with respect to the uniform force).
+ * Not implemented for the full corrections (LBM_EINVAL). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);

@@ -50,37 +50,48 @@ def init_equilibrium(rho, u, p: Params):
 
 
 def density_gradient(rho, p: Params):
-    """Second-order central differences of rho with spacings (1, r, s).
+    """Isotropic second-order density gradient on the cuboid lattice (App. D).
 
-    Only the "full" correction variant uses it.  Periodic axes wrap; at a
-    bounce-back wall the first/last node uses the one-sided second-order
-    difference.  The paper names an isotropic second-order stencil without
-    fixing it: parity unpinned.
+    App. D takes d_x rho, d_y rho, d_z rho from an isotropic second-order
+    finite-difference stencil without printing it.  The stencil here is the
+    lattice-weighted one,
+        grad rho (x) = (1 / cs2) sum_a w_a e_a rho(x + ebar_a),
+    with the rest weights w_a and the cuboid velocities e_a = (ebar_x, r ebar_y,
+    s ebar_z); because sum_a w_a e_a e_a = cs2 I, it is exact for fields of
+    degree <= 2 and its leading error is isotropic.  Periodic axes wrap; across
+    a halfway bounce-back wall the neighbour is the mirror image of the node
+    across the wall, i.e. the boundary node itself (the index is clamped).
+    Returns (3, nz, ny, nx): d/dx, d/dy, d/dz.
     """
-    out = []
-    for axis, h, bc in ((2, 1.0, "periodic"), (1, p.r, p.bc_y), (0, p.s, p.bc_z)):
-        n = rho.shape[axis]
-        g = (torch.roll(rho, -1, axis) - torch.roll(rho, 1, axis)) / (2 * h)
-        if bc == "bounceback" and n >= 3:
-            idx = torch.arange(n)
-            first = (-3 * rho.index_select(axis, idx[0:1]) + 4 * rho.index_select(axis, idx[1:2])
-                     - rho.index_select(axis, idx[2:3])) / (2 * h)
-            last = (3 * rho.index_select(axis, idx[-1:]) - 4 * rho.index_select(axis, idx[-2:-1])
-                    + rho.index_select(axis, idx[-3:-2])) / (2 * h)
-            g = g.clone()
-            g.index_copy_(axis, idx[0:1], first)
-            g.index_copy_(axis, idx[-1:], last)
-        out.append(g)
-    return torch.stack(out)  # (3, nz, ny, nx): d/dx, d/dy, d/dz
+    rho = torch.as_tensor(rho, dtype=DT)
+    w = EQ.rest_weights(p.r, p.s, p.cs2)
+    e = L.velocities(p.r, p.s)
+    ebar = L.velocities(1.0, 1.0).round().to(torch.int64)
+    idx = []
+    for n, bc in ((p.nz, p.bc_z), (p.ny, p.bc_y), (p.nx, "periodic")):
+        base = torch.arange(n)
+        idx.append({d: (torch.clamp(base + d, 0, n - 1) if bc == "bounceback" else (base + d) % n)
+                    for d in (-1, 0, 1)})
+    out = torch.zeros((3, *rho.shape), dtype=DT)
+    for a in range(L.Q27):
+        ex, ey, ez = (int(v) for v in ebar[a])
+        nb = rho.index_select(0, idx[0][ez]).index_select(1, idx[1][ey]).index_select(2, idx[2][ex])
+        for d in range(3):
+            out[d] += w[a] * e[a, d] * nb
+    return out / p.cs2
 
 
-def collide_field(f, p: Params, force=None):
-    """Collision on every node of a (27, nz, ny, nx) field."""
+def collide_field(f, p: Params, force=None, grad_from=None):
+    """Collision on every node of a (27, nz, ny, nx) field.
+
+    With the "full" corrections the density gradient is taken from
+    ``grad_from`` (a density field) when given, else from the density of ``f``.
+    """
     fn = to_nodes(f)
     Fn = force_nodes(force, p)
     grad = None
     if p.corr == "full":
-        rho = f.sum(0)
+        rho = f.sum(0) if grad_from is None else torch.as_tensor(grad_from, dtype=DT)
         grad = density_gradient(rho, p).reshape(3, -1).T
     out = []
     for i in range(0, p.n, CHUNK):
@@ -89,14 +100,20 @@ def collide_field(f, p: Params, force=None):
     return from_nodes(torch.cat(out), p)
 
 
-def step(f, p: Params, force=None):
+def step(f, p: Params, force=None, grad_from=None):
     """One collide-and-stream step: f(t) -> f(t + 1)."""
-    return ST.stream(collide_field(f, p, force), p)
+    return ST.stream(collide_field(f, p, force, grad_from), p)
 
 
-def run(f, p: Params, nsteps, force=None):
+def run(f, p: Params, nsteps, force=None, lagged=False):
+    """nsteps steps.  ``lagged`` (full corrections only): the first step takes its
+    density gradient from the density of its own input, every later step from the
+    density of the previous step's input (one step behind)."""
+    prev = None
     for _ in range(nsteps):
-        f = step(f, p, force)
+        now = f.sum(0) if (lagged and p.corr == "full") else None
+        f = step(f, p, force, prev if lagged else None)
+        prev = now
     return f
 
 

@@ -15,7 +15,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4
 BC = {"periodic": 0, "bounceback": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
-CORR = {"off": 0, "lowmach": 1, "local": 2}
+CORR = {"off": 0, "lowmach": 1, "local": 2, "full": 3}
+GRAD_MODE = {"exact": 0, "lagged": 1}
 
 
 class LbmParams(ctypes.Structure):
@@ -49,6 +50,8 @@ _SIGNATURES = {
     "lbm_import": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbm_export": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "lbm_density": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbm_step_full": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "lbm_check_sums": (ctypes.c_int, [_P, _P, _P]),
     "lbm_step_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),

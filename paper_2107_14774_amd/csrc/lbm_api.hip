@@ -59,7 +59,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     return fail(LBM_EINVAL, "lbm_create: omega_nu and omega_xi must lie in (0, 2)");
   if (q.omega_hi != 1.0) return fail(LBM_EINVAL, "lbm_create: only omega_hi = 1 is implemented");
   if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
-  if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_LOCAL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
+  if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
   if (!(q.rho0 > 0.0)) return fail(LBM_EINVAL, "lbm_create: rho0 must be > 0");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(q.force[d])) return fail(LBM_EINVAL, "lbm_create: non-finite force");
@@ -173,10 +173,56 @@ int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const 
   CHECK_REQ(state_b, "lbm_step", "state_b");
   CHECK_PTR(force, "lbm_step", "force");
   if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step: state_a and state_b must differ");
+  if (h->p.corr == LBM_CORR_FULL)
+    return fail(LBM_EINVAL, "lbm_step: the full corrections need a density field (use lbm_step_full)");
   void* bufs[2] = {state_a, state_b};
   for (int32_t t = 0; t < nsteps; ++t) {
-    hipError_t e = clbm::launch_step(*h, bufs[t & 1], bufs[(t + 1) & 1], force, (hipStream_t)hip_stream);
+    hipError_t e = clbm::launch_step(*h, bufs[t & 1], bufs[(t + 1) & 1], force, nullptr, nullptr,
+                                     (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
+  }
+  return LBM_OK;
+}
+
+int lbm_density(lbm_handle* h, const void* state, float* drho, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_density");
+  CHECK_REQ(state, "lbm_density", "state");
+  CHECK_REQ(drho, "lbm_density", "drho");
+  hipError_t e = clbm::launch_density(*h, state, drho, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_density");
+}
+
+int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const float* force,
+                  float* drho_a, float* drho_b, int32_t mode, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_step_full");
+  if (h->p.corr != LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_step_full: the handle's corr is not LBM_CORR_FULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "lbm_step_full: nsteps < 0");
+  if (mode != LBM_GRAD_EXACT && mode != LBM_GRAD_LAGGED) return fail(LBM_EINVAL, "lbm_step_full: unknown mode");
+  CHECK_REQ(state_a, "lbm_step_full", "state_a");
+  CHECK_REQ(state_b, "lbm_step_full", "state_b");
+  CHECK_PTR(force, "lbm_step_full", "force");
+  CHECK_REQ(drho_a, "lbm_step_full", "drho_a");
+  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step_full: state_a and state_b must differ");
+  if (mode == LBM_GRAD_LAGGED) {
+    CHECK_REQ(drho_b, "lbm_step_full", "drho_b");
+    if (drho_a == drho_b) return fail(LBM_EINVAL, "lbm_step_full: drho_a and drho_b must differ");
+  } else {
+    CHECK_PTR(drho_b, "lbm_step_full", "drho_b");
+  }
+  const hipStream_t st = (hipStream_t)hip_stream;
+  void* bufs[2] = {state_a, state_b};
+  float* rho[2] = {drho_a, drho_b};
+  for (int32_t t = 0; t < nsteps; ++t) {
+    void* src = bufs[t & 1];
+    void* dst = bufs[(t + 1) & 1];
+    hipError_t e;
+    if (mode == LBM_GRAD_EXACT) {
+      e = clbm::launch_density(*h, src, drho_a, st);
+      if (e == hipSuccess) e = clbm::launch_step(*h, src, dst, force, drho_a, nullptr, st);
+    } else {
+      e = clbm::launch_step(*h, src, dst, force, rho[t & 1], rho[(t + 1) & 1], st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "lbm_step_full");
   }
   return LBM_OK;
 }
@@ -215,6 +261,8 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   CHECK_PTR(grad_force, "lbm_step_adjoint", "grad_force");
   CHECK_PTR(grad_force_uniform, "lbm_step_adjoint", "grad_force_uniform");
   if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, "lbm_step_adjoint: adj_in == adj_out");
+  if (h->p.corr == LBM_CORR_FULL)
+    return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the full corrections");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
                                            grad_force_uniform, (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");

@@ -203,9 +203,12 @@ __device__ __forceinline__ AxisVec axis_vectors(float u, int d, const Consts& k)
 //                 + sum over the first/second-order non-equilibrium central
 //                   moments Delta_mnp of Delta_mnp A_m(x)A_n(x)A_p,
 // which equals P^-1 S^-1 F(-u) applied to the post-collision central moments.
+// CORR: 0 none, 1 low-Mach theta, 2 theta with the 3u^2 terms, 3 as 2 plus the
+// density-gradient terms (gx, gy, gz = grad rho, used only when CORR == 3).
 template <int CORR>
 __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, float fy, float fz,
-                                             const Consts& k, float (&out)[27]) {
+                                             const Consts& k, float (&out)[27],
+                                             float grx = 0.0f, float gry = 0.0f, float grz = 0.0f) {
   const LowMoments M = low_moments(df);
   const float r = k.r, s = k.s, cs2 = k.cs2, rho0 = k.rho0;
   const float drho = M.m000;
@@ -234,24 +237,34 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   float c2d1 = 0.0f, c2d2 = 0.0f, c2s = 0.0f;
   if constexpr (CORR != 0) {
     // strain-rate system of App. D divided by rho: C/rho . (rho du) = R
-    const float g = (CORR == 2) ? 1.5f : 0.0f;
+    const float g = (CORR >= 2) ? 1.5f : 0.0f;
     const float inw = 2.0f * cs2 / wn, inx = 2.0f * cs2 / wx;
     const float ax = 0.5f * (3.0f * cs2 - 1.0f), ay = 0.5f * (3.0f * cs2 - k.c2[1]), az = 0.5f * (3.0f * cs2 - k.c2[2]);
     const float csx = -inw + ax + g * uxx, cbx = -inx + ax + g * uxx;
     const float csy = inw - ay - g * uyy, cby = -inx + ay + g * uyy;
     const float csz = inw - az - g * uzz, cbz = -inx + az + g * uzz;
     const float det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
+    // density-gradient terms e_sr1, e_sr2, e_br of App. D (A, B, C = a_d u_d)
+    float es1 = 0.0f, es2 = 0.0f, eb = 0.0f;
+    if constexpr (CORR == 3) {
+      const float tA = ax * ux * grx, tB = ay * uy * gry, tC = az * uz * grz;
+      es1 = tB - tA;
+      es2 = tC - tA;
+      eb = -(tA + tB + tC);
+    }
+    const float Rs1e = Rs1 + es1, Rs2e = Rs2 + es2, Rbe = Rb + eb;
     // closed-form solution of eq. 49 (the corrections only need a few digits of it)
-    const float gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) * __builtin_amdgcn_rcpf(det);
-    const float gy = (Rs1 - csx * gx) * __builtin_amdgcn_rcpf(csy);
-    const float gz = (Rs2 - csx * gx) * __builtin_amdgcn_rcpf(csz);
+    const float gx = (-csz * cby * Rs1e - csy * (cbz * Rs2e - csz * Rbe)) * __builtin_amdgcn_rcpf(det);
+    const float gy = (Rs1e - csx * gx) * __builtin_amdgcn_rcpf(csy);
+    const float gz = (Rs2e - csx * gx) * __builtin_amdgcn_rcpf(csz);
     // theta / rho of eq. 38-40 (App. D), times rho du
     const float hn = 1.0f / wn - 0.5f, hx = 1.0f / wx - 0.5f;
-    const float g3 = (CORR == 2) ? 3.0f : 0.0f;
+    const float g3 = (CORR >= 2) ? 3.0f : 0.0f;
     const float tx = -(g3 * uxx + 2.0f * ax), ty = -(g3 * uyy + 2.0f * ay), tz = -(g3 * uzz + 2.0f * az);
-    c2d1 = hn * (tx * gx - ty * gy);
-    c2d2 = hn * (tx * gx - tz * gz);
-    c2s = hx * (tx * gx + ty * gy + tz * gz);
+    // lambda . grad rho of eq. 38-40 equals 2 (1/omega - 1/2) times the e terms above
+    c2d1 = hn * (tx * gx - ty * gy + 2.0f * es1);
+    c2d2 = hn * (tx * gx - tz * gz + 2.0f * es2);
+    c2s = hx * (tx * gx + ty * gy + tz * gz + 2.0f * eb);
   }
   // relaxation of the combined moments, then segregation (B^-1 of App. D)
   const float D2s = (1.0f - wx) * Rb + wx * c2s;
@@ -323,6 +336,54 @@ __device__ __forceinline__ void conserve(const float (&df)[27], float fx, float 
   out[4] -= 0.5f * ry;
   out[5] += 0.5f * rz;
   out[6] -= 0.5f * rz;
+}
+
+// Density gradient of the full corrections (App. D: an isotropic second-order
+// finite difference) from a field of density deviations:
+//   grad rho (x) = (1/cs2) sum_a w_a e_a rho(x + ebar_a),
+// which with the product weights w_a = Wx Wy Wz is a central difference along
+// each axis averaged over the 3 x 3 transverse neighbourhood with the 1D
+// weights of the other two axes.  Periodic axes wrap; across a bounce-back
+// wall the neighbour is the boundary node itself (its mirror image).
+__device__ __forceinline__ void density_gradient(const float* __restrict__ drho, int x, int y, int z,
+                                                 const Consts& k, float& gx, float& gy, float& gz) {
+  const int xs[3] = {x == 0 ? k.nx - 1 : x - 1, x, x == k.nx - 1 ? 0 : x + 1};
+  int ys[3], zs[3];
+  if (k.bb_y) {
+    ys[0] = y == 0 ? 0 : y - 1; ys[2] = y == k.ny - 1 ? y : y + 1;
+  } else {
+    ys[0] = y == 0 ? k.ny - 1 : y - 1; ys[2] = y == k.ny - 1 ? 0 : y + 1;
+  }
+  if (k.bb_z) {
+    zs[0] = z == 0 ? 0 : z - 1; zs[2] = z == k.nz - 1 ? z : z + 1;
+  } else {
+    zs[0] = z == 0 ? k.nz - 1 : z - 1; zs[2] = z == k.nz - 1 ? 0 : z + 1;
+  }
+  ys[1] = y;
+  zs[1] = z;
+  float v[3][3][3];  // [z offset][y offset][x offset]; the centre is not needed
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const uint32_t row = ((uint32_t)zs[l] * (uint32_t)k.ny + (uint32_t)ys[j]) * (uint32_t)k.nx;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (i != 1 || j != 1 || l != 1) v[l][j][i] = drho[row + (uint32_t)xs[i]];
+    }
+  const float W[3][3] = {{k.w0s[0], k.w0c[0], k.w0s[0]}, {k.w0s[1], k.w0c[1], k.w0s[1]}, {k.w0s[2], k.w0c[2], k.w0s[2]}};
+  float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      sx += W[1][a] * W[2][b] * (v[b][a][2] - v[b][a][0]);
+      sy += W[0][a] * W[2][b] * (v[b][2][a] - v[b][0][a]);
+      sz += W[0][a] * W[1][b] * (v[2][b][a] - v[0][b][a]);
+    }
+  gx = 0.5f * sx;
+  gy = 0.5f * k.ic[1] * sy;
+  gz = 0.5f * k.ic[2] * sz;
 }
 
 // XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs

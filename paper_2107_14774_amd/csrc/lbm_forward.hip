@@ -11,16 +11,12 @@ namespace clbm {
 // (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
 // base pointer plus a 32-bit node index shared by the three directions of
 // one source row; with walls the general slot rule of gather_slot applies.
-template <int ST, int CORR, bool WALLS>
-__global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
-                                              const float* __restrict__ force, Consts k, uint32_t bpr) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
-  if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-  float df[27];
+// With the full corrections (CORR 3) the density gradient comes from the
+// density-deviation field grad_src, and drho_out (if not NULL) receives the
+// node's own density deviation.
+template <int ST, bool WALLS>
+__device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
+                                            const Consts& k, float (&df)[27]) {
   if constexpr (WALLS) {
     gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
   } else {
@@ -28,6 +24,21 @@ __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
     periodic_rows(x, y, z, k, pr);
     gather_periodic<ST>(P.src, pr, k, df);
   }
+}
+
+template <int ST, int CORR, bool WALLS>
+__global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
+                                              const float* __restrict__ force,
+                                              const float* __restrict__ grad_src, float* __restrict__ drho_out,
+                                              Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  if (x >= k.nx) return;
+  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  float df[27];
+  gather_node<ST, WALLS>(P, x, y, z, k, df);
   float fx = k.fx, fy = k.fy, fz = k.fz;
   if (force != nullptr) {
     fx = ld_off(force, node);
@@ -35,11 +46,34 @@ __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
     fz = ld_off(force + 2 * k.n, node);
   }
   float out[27];
-  collide_node<CORR>(df, fx, fy, fz, k, out);
+  if constexpr (CORR == 3) {
+    float grx, gry, grz;
+    density_gradient(grad_src, x, y, z, k, grx, gry, grz);
+    collide_node<CORR>(df, fx, fy, fz, k, out, grx, gry, grz);
+    if (drho_out != nullptr) drho_out[node] = low_moments(df).m000;
+  } else {
+    collide_node<CORR>(df, fx, fy, fz, k, out);
+  }
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
 #pragma unroll
   for (int a = 0; a < 27; ++a)
     st_off_nt(P.dst[a], node, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]));
+}
+
+// Density deviation of every node of a state: the same gather and the same
+// FP32 sum as the step, so the value is bit-identical to the step's.
+template <int ST, bool WALLS>
+__global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> P, float* __restrict__ drho,
+                                                 Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  if (x >= k.nx) return;
+  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  float df[27];
+  gather_node<ST, WALLS>(P, x, y, z, k, df);
+  drho[node] = low_moments(df).m000;
 }
 
 // ------------------------------------------------------------------ init / import / export
@@ -201,6 +235,11 @@ __global__ __launch_bounds__(256) void k_moments(const typename Store<ST>::T* __
 }
 
 // ------------------------------------------------------------------ launchers
+// The 32-bit addressing of the periodic path needs every byte offset below 4 GiB.
+static bool use_general_gather(const lbm_handle& h) {
+  return h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * h.elem >= (1ull << 32);
+}
+
 static int grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -209,7 +248,8 @@ static int grid_for(int64_t n, int block, int64_t cap) {
 }
 
 template <int ST>
-static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst, const float* force,
+                                const float* grad_src, float* drho_out, hipStream_t st) {
   using T = typename Store<ST>::T;
   const int block = h.block;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
@@ -220,25 +260,58 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
     P.src[a] = (const T*)src + (int64_t)a * h.stride;
     P.dst[a] = (T*)dst + (int64_t)a * h.stride;
   }
-  // the 32-bit addressing of the periodic path needs every byte offset below 4 GiB
-  const bool walls = h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * sizeof(T) >= (1ull << 32);
+  const bool walls = use_general_gather(h);
   const dim3 grid((unsigned)nb), blk(block);
+#define CLBM_STEP(C, W) \
+  hipLaunchKernelGGL((k_step<ST, C, W>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
   switch (h.p.corr * 2 + (walls ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((k_step<ST, 0, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
-    case 1: hipLaunchKernelGGL((k_step<ST, 0, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
-    case 2: hipLaunchKernelGGL((k_step<ST, 1, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
-    case 3: hipLaunchKernelGGL((k_step<ST, 1, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
-    case 4: hipLaunchKernelGGL((k_step<ST, 2, false>), grid, blk, 0, st, P, force, h.k, bpr); break;
-    default: hipLaunchKernelGGL((k_step<ST, 2, true>), grid, blk, 0, st, P, force, h.k, bpr); break;
+    case 0: CLBM_STEP(0, false); break;
+    case 1: CLBM_STEP(0, true); break;
+    case 2: CLBM_STEP(1, false); break;
+    case 3: CLBM_STEP(1, true); break;
+    case 4: CLBM_STEP(2, false); break;
+    case 5: CLBM_STEP(2, true); break;
+    case 6: CLBM_STEP(3, false); break;
+    default: CLBM_STEP(3, true); break;
   }
+#undef CLBM_STEP
   return hipGetLastError();
 }
 
-hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st) {
+template <int ST>
+static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
+  using T = typename Store<ST>::T;
+  const int block = h.block;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  DirPtrs<T> P;
+  for (int a = 0; a < 27; ++a) {
+    P.src[a] = (const T*)src + (int64_t)a * h.stride;
+    P.dst[a] = nullptr;
+  }
+  const dim3 grid((unsigned)nb), blk(block);
+  if (use_general_gather(h))
+    hipLaunchKernelGGL((k_density<ST, true>), grid, blk, 0, st, P, drho, h.k, bpr);
+  else
+    hipLaunchKernelGGL((k_density<ST, false>), grid, blk, 0, st, P, drho, h.k, bpr);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force,
+                       const float* grad_src, float* drho_out, hipStream_t st) {
   switch (h.p.storage) {
-    case LBM_F32: return launch_step_t<0>(h, src, dst, force, st);
-    case LBM_F16: return launch_step_t<1>(h, src, dst, force, st);
-    default: return launch_step_t<2>(h, src, dst, force, st);
+    case LBM_F32: return launch_step_t<0>(h, src, dst, force, grad_src, drho_out, st);
+    case LBM_F16: return launch_step_t<1>(h, src, dst, force, grad_src, drho_out, st);
+    default: return launch_step_t<2>(h, src, dst, force, grad_src, drho_out, st);
+  }
+}
+
+hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
+  switch (h.p.storage) {
+    case LBM_F32: return launch_density_t<0>(h, src, drho, st);
+    case LBM_F16: return launch_density_t<1>(h, src, drho, st);
+    default: return launch_density_t<2>(h, src, drho, st);
   }
 }
 

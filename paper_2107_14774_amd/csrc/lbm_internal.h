@@ -20,7 +20,9 @@ struct lbm_handle {
 
 namespace clbm {
 
-hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force, hipStream_t st);
+hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force,
+                       const float* grad_src, float* drho_out, hipStream_t st);
+hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
 hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
                        const double* perturb, hipStream_t st);
 hipError_t launch_import(const lbm_handle& h, void* dst, const double* f, hipStream_t st);

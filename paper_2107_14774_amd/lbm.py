@@ -114,6 +114,22 @@ def lbm_step(h, nsteps, state_a, state_b, force=None, stream=None):
                                     _lib.stream_ptr(stream)))
 
 
+def lbm_density(h, state, drho, stream=None):
+    _require(drho, _ABI_F32, h.n, "drho")
+    _lib.check(_lib.load().lbm_density(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(drho), _lib.stream_ptr(stream)))
+
+
+def lbm_step_full(h, nsteps, state_a, state_b, drho_a, drho_b=None, mode="lagged", force=None, stream=None):
+    """Steps with the full corrections; ``mode`` is "exact" or "lagged" (see include/lbm.h)."""
+    _require(force, _ABI_F32, 3 * h.n, "force")
+    _require(drho_a, _ABI_F32, h.n, "drho_a")
+    _require(drho_b, _ABI_F32, h.n, "drho_b")
+    _lib.check(_lib.load().lbm_step_full(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
+                                         _lib.ptr(_state(h, state_b, "state_b")), _lib.ptr(force),
+                                         _lib.ptr(drho_a), _lib.ptr(drho_b), _lib.GRAD_MODE[mode],
+                                         _lib.stream_ptr(stream)))
+
+
 def lbm_moments(h, state, force=None, rho=None, u=None, sums=None, stream=None):
     n = h.n
     _require(force, _ABI_F32, 3 * n, "force")
@@ -233,6 +249,19 @@ class Lattice:
         """Advance; returns (current, scratch) after nsteps."""
         lbm_step(self.h, nsteps, a, b, force)
         return (a, b) if nsteps % 2 == 0 else (b, a)
+
+    def step_full(self, a, b, nsteps, drho_a, drho_b=None, mode="lagged", force=None):
+        """Full corrections; returns (current, scratch, current density field, other density field)."""
+        lbm_step_full(self.h, nsteps, a, b, drho_a, drho_b, mode, force)
+        if nsteps % 2 == 0 or mode == "exact":
+            return ((a, b) if nsteps % 2 == 0 else (b, a)) + (drho_a, drho_b)
+        return b, a, drho_b, drho_a
+
+    def density(self, state):
+        """rho - rho0 (FP32 field) of a state."""
+        d = self.field(1)
+        lbm_density(self.h, state, d)
+        return d
 
     def moments(self, state, force=None, sums=True):
         rho = self.field(1)

@@ -78,3 +78,21 @@ def test_binding_rejects_host_tensors():
     h = P.lbm_create(4, 4, 4)
     with pytest.raises(ValueError):
         P.lbm_step(h, 1, torch.empty(h.state_bytes, dtype=torch.uint8), torch.empty(h.state_bytes, dtype=torch.uint8))
+
+
+def test_full_corrections_need_the_density_field_entry_point():
+    lib = _lib.load()
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    hf = P.lbm_create(4, 4, 4, corr="full")
+    assert lib.lbm_step(hf.raw, 1, a, b, None, None) == _lib.LBM_EINVAL
+    assert b"lbm_step_full" in lib.lbm_last_error()
+    assert lib.lbm_step_adjoint(hf.raw, a, b, ctypes.c_void_p(0x30000), None, None, None, None) == _lib.LBM_EINVAL
+    d1, d2 = ctypes.c_void_p(0x40000), ctypes.c_void_p(0x50000)
+    assert lib.lbm_step_full(hf.raw, 1, a, b, None, d1, d1, 1, None) == _lib.LBM_EINVAL      # same density buffers
+    assert lib.lbm_step_full(hf.raw, 1, a, b, None, d1, None, 1, None) == _lib.LBM_EINVAL    # lagged needs drho_b
+    assert lib.lbm_step_full(hf.raw, 1, a, b, None, d1, d2, 7, None) == _lib.LBM_EINVAL      # unknown mode
+    assert lib.lbm_step_full(hf.raw, 1, a, b, None, None, d2, 0, None) == _lib.LBM_EINVAL    # no drho_a
+    assert lib.lbm_step_full(hf.raw, 0, a, b, None, d1, None, 0, None) == _lib.LBM_OK        # zero steps: nothing runs
+    hl = P.lbm_create(4, 4, 4, corr="local")
+    assert lib.lbm_step_full(hl.raw, 1, a, b, None, d1, d2, 1, None) == _lib.LBM_EINVAL
+    assert b"LBM_CORR_FULL" in lib.lbm_last_error()

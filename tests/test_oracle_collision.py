@@ -7,6 +7,8 @@ the independent central-moment route (eq. 3a + dense solve), the closed-form
 strain-rate solution of eq. 65, and the first-order source identity of App. D.
 """
 
+import math
+
 import pytest
 import torch
 
@@ -201,3 +203,58 @@ def test_strain_rate_closed_form():
     dyuy = (R_s1 - C_sx * dxux) / C_sy
     dzuz = (R_s2 - C_sx * dxux) / C_sz
     assert torch.allclose(info["du"], torch.stack([dxux, dyuy, dzuz], -1), atol=1e-14, rtol=1e-10)
+
+
+# ------------------------------------------------------------------ density gradient of the full corrections
+
+def _tensor_weights(r, s, cs2):
+    """1D weights per axis (ebar = -1, 0, +1) with speed c: side cs2/(2c^2), centre 1 - cs2/c^2."""
+    return [(cs2 / (2 * c * c), 1 - cs2 / (c * c), cs2 / (2 * c * c)) for c in (1.0, r, s)]
+
+
+@pytest.mark.parametrize("r,s", [(1.0, 0.5), (0.5, 0.25), (1.3, 0.8)])
+def test_isotropic_density_gradient_fourier_symbol(r, s):
+    """On rho = cos(phase) the lattice-weighted stencil has the closed-form symbol
+    d_x -> -sin(th_x) T_y T_z sin(phase), d_y -> -sin(th_y)/r T_x T_z sin(phase), ...
+    with T_d = 1 - (cs2/c_d^2)(1 - cos th_d), th_d the phase step per node along d."""
+    from oracle import lbm as OL
+    nx, ny, nz = 9, 7, 6
+    p = oracle.Params(nx, ny, nz, r=r, s=s, corr="full")
+    z, y, x = torch.meshgrid(torch.arange(nz, dtype=DT), torch.arange(ny, dtype=DT),
+                             torch.arange(nx, dtype=DT), indexing="ij")
+    for kx, ky, kz, ph in ((1, 2, 1, 0.3), (4, 1, 2, 1.1), (0, 3, 5, -0.7)):
+        th = (2 * math.pi * kx / nx, 2 * math.pi * ky / ny, 2 * math.pi * kz / nz)
+        phase = th[0] * x + th[1] * y + th[2] * z + ph
+        g = OL.density_gradient(torch.cos(phase), p)
+        T = [1 - (p.cs2 / c ** 2) * (1 - math.cos(t)) for c, t in zip((1.0, r, s), th)]
+        want = [-math.sin(th[0]) * T[1] * T[2] * torch.sin(phase),
+                 -math.sin(th[1]) / r * T[0] * T[2] * torch.sin(phase),
+                 -math.sin(th[2]) / s * T[0] * T[1] * torch.sin(phase)]
+        for d in range(3):
+            assert torch.allclose(g[d], want[d], atol=1e-14), (kx, ky, kz, d)
+
+
+def test_density_gradient_exact_for_quadratics_and_mirrored_at_walls():
+    from oracle import lbm as OL
+    r, s = 0.5, 0.25
+    # (a) second order: exact on a quadratic field away from the walls (interior nodes)
+    p = oracle.Params(8, 7, 6, r=r, s=s, corr="full", bc_y="bounceback", bc_z="bounceback")
+    z, y, x = torch.meshgrid(torch.arange(6, dtype=DT) * s, torch.arange(7, dtype=DT) * r,
+                             torch.arange(8, dtype=DT), indexing="ij")
+    # x is periodic, so the x-dependence is a single Fourier mode scaled by its known symbol
+    rho = 1 + 0.1 * y - 0.2 * z + 0.05 * y * y + 0.03 * y * z - 0.07 * z * z
+    g = OL.density_gradient(rho, p)
+    inner = (slice(1, -1), slice(1, -1), slice(None))
+    assert torch.allclose(g[0][inner], torch.zeros_like(g[0][inner]), atol=1e-14)
+    assert torch.allclose(g[1][inner], (0.1 + 0.1 * y + 0.03 * z)[inner], atol=1e-13)
+    assert torch.allclose(g[2][inner], (-0.2 + 0.03 * y - 0.14 * z)[inner], atol=1e-13)
+    # (b) walls: the stencil equals the periodic one on the domain doubled by reflection about each wall
+    n_y, n_z = 5, 4
+    pw = oracle.Params(6, n_y, n_z, r=r, s=s, corr="full", bc_y="bounceback", bc_z="bounceback")
+    pp = oracle.Params(6, 2 * n_y, 2 * n_z, r=r, s=s, corr="full")
+    g0 = torch.Generator().manual_seed(3)
+    base = torch.rand((n_z, n_y, 6), generator=g0, dtype=DT)
+    big = torch.cat([base, base.flip(1)], 1)
+    big = torch.cat([big, big.flip(0)], 0)
+    want = OL.density_gradient(big, pp)[:, :n_z, :n_y]
+    assert torch.allclose(OL.density_gradient(base, pw), want, atol=1e-14)
