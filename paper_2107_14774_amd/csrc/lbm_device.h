@@ -340,14 +340,25 @@ __device__ __forceinline__ void conserve(const float (&df)[27], float fx, float 
 
 // Density gradient of the full corrections (App. D: an isotropic second-order
 // finite difference) from a field of density deviations:
-//   grad rho (x) = (1/cs2) sum_a w_a e_a rho(x + ebar_a),
-// which with the product weights w_a = Wx Wy Wz is a central difference along
-// each axis averaged over the 3 x 3 transverse neighbourhood with the 1D
-// weights of the other two axes.  Periodic axes wrap; across a bounce-back
-// wall the neighbour is the boundary node itself (its mirror image).
-__device__ __forceinline__ void density_gradient(const float* __restrict__ drho, int x, int y, int z,
-                                                 const Consts& k, float& gx, float& gy, float& gz) {
-  const int xs[3] = {x == 0 ? k.nx - 1 : x - 1, x, x == k.nx - 1 ? 0 : x + 1};
+//   grad rho (x) = (1/cs2) sum_a w_a e_a rho(x + ebar_a).
+// With the product weights w_a = Wx Wy Wz it factorises over the 3 x 3
+// transverse neighbourhood of each column x' in {x-1, x, x+1}:
+//   T(x') = sum_jl Wy_j Wz_l rho(x', y+j-1, z+l-1)
+//   U(x') = sum_l  Wz_l [rho(x', y+1, z+l-1) - rho(x', y-1, z+l-1)]
+//   V(x') = sum_j  Wy_j [rho(x', y+j-1, z+1) - rho(x', y+j-1, z-1)]
+//   d_x rho = (T(x+1) - T(x-1)) / 2
+//   d_y rho = sum_i Wx_i U(x+i-1) / (2 r),   d_z rho = sum_i Wx_i V(x+i-1) / (2 s).
+// Periodic axes wrap; across a bounce-back wall the neighbour is the
+// boundary node itself (its mirror image).
+struct ColumnSums {
+  float T, U, V;
+};
+
+struct TransverseRows {
+  uint32_t row[3][3];  // [y offset][z offset] -> (z' ny + y') nx
+};
+
+__device__ __forceinline__ TransverseRows transverse_rows(int y, int z, const Consts& k) {
   int ys[3], zs[3];
   if (k.bb_y) {
     ys[0] = y == 0 ? 0 : y - 1; ys[2] = y == k.ny - 1 ? y : y + 1;
@@ -361,29 +372,63 @@ __device__ __forceinline__ void density_gradient(const float* __restrict__ drho,
   }
   ys[1] = y;
   zs[1] = z;
-  float v[3][3][3];  // [z offset][y offset][x offset]; the centre is not needed
+  TransverseRows t;
 #pragma unroll
-  for (int l = 0; l < 3; ++l)
+  for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const uint32_t row = ((uint32_t)zs[l] * (uint32_t)k.ny + (uint32_t)ys[j]) * (uint32_t)k.nx;
+    for (int l = 0; l < 3; ++l) t.row[j][l] = ((uint32_t)zs[l] * (uint32_t)k.ny + (uint32_t)ys[j]) * (uint32_t)k.nx;
+  return t;
+}
+
+__device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho, const TransverseRows& t,
+                                                  int xc, const Consts& k) {
+  float v[3][3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        if (i != 1 || j != 1 || l != 1) v[l][j][i] = drho[row + (uint32_t)xs[i]];
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) v[j][l] = drho[t.row[j][l] + (uint32_t)xc];
+  const float wy[3] = {k.w0s[1], k.w0c[1], k.w0s[1]};
+  const float wz[3] = {k.w0s[2], k.w0c[2], k.w0s[2]};
+  ColumnSums c{0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c.U += wz[a] * (v[2][a] - v[0][a]);
+    c.V += wy[a] * (v[a][2] - v[a][0]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) c.T += wy[a] * wz[b] * v[a][b];
+  }
+  return c;
+}
+
+// Block-cooperative gradient for the nodes of one row segment (blockDim.x
+// consecutive x, one y, z): each thread reduces its own column, two threads
+// reduce the halo columns x0 - 1 and x_last + 1 (periodic in x), the x
+// neighbours are exchanged through LDS.  Every thread of the block must call
+// it (it contains a barrier); threads with x >= nx pass active = false.
+__device__ __forceinline__ void density_gradient_block(const float* __restrict__ drho, int x, int y, int z,
+                                                       bool active, const Consts& k, float (&lds)[3][258],
+                                                       float& gx, float& gy, float& gz) {
+  const int t = (int)threadIdx.x;
+  const TransverseRows rows = transverse_rows(y, z, k);
+  if (active) {
+    const ColumnSums c = column_sums(drho, rows, x, k);
+    lds[0][t + 1] = c.T; lds[1][t + 1] = c.U; lds[2][t + 1] = c.V;
+    if (t == 0) {
+      const ColumnSums h = column_sums(drho, rows, x == 0 ? k.nx - 1 : x - 1, k);
+      lds[0][0] = h.T; lds[1][0] = h.U; lds[2][0] = h.V;
     }
-  const float W[3][3] = {{k.w0s[0], k.w0c[0], k.w0s[0]}, {k.w0s[1], k.w0c[1], k.w0s[1]}, {k.w0s[2], k.w0c[2], k.w0s[2]}};
-  float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      sx += W[1][a] * W[2][b] * (v[b][a][2] - v[b][a][0]);
-      sy += W[0][a] * W[2][b] * (v[b][2][a] - v[b][0][a]);
-      sz += W[0][a] * W[1][b] * (v[2][b][a] - v[0][b][a]);
+    if (t == (int)blockDim.x - 1 || x == k.nx - 1) {
+      const ColumnSums h = column_sums(drho, rows, x == k.nx - 1 ? 0 : x + 1, k);
+      lds[0][t + 2] = h.T; lds[1][t + 2] = h.U; lds[2][t + 2] = h.V;
     }
-  gx = 0.5f * sx;
-  gy = 0.5f * k.ic[1] * sy;
-  gz = 0.5f * k.ic[2] * sz;
+  }
+  __syncthreads();
+  if (active) {
+    const float wc = k.w0c[0], ws = k.w0s[0];
+    gx = 0.5f * (lds[0][t + 2] - lds[0][t]);
+    gy = 0.5f * k.ic[1] * (ws * lds[1][t] + wc * lds[1][t + 1] + ws * lds[1][t + 2]);
+    gz = 0.5f * k.ic[2] * (ws * lds[2][t] + wc * lds[2][t + 1] + ws * lds[2][t + 2]);
+  }
 }
 
 // XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs

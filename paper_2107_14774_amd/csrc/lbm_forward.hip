@@ -26,8 +26,26 @@ __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>
   }
 }
 
+// Minimum waves per SIMD the compiler must fit (1 = no register limit).
+#ifndef LBM_STEP_WAVES_F32
+#define LBM_STEP_WAVES_F32 1
+#endif
+#ifndef LBM_STEP_WAVES_F16
+#define LBM_STEP_WAVES_F16 1
+#endif
+#ifndef LBM_FULL_WAVES_F32
+#define LBM_FULL_WAVES_F32 1
+#endif
+#ifndef LBM_FULL_WAVES_F16
+#define LBM_FULL_WAVES_F16 1
+#endif
+constexpr int step_waves(int st, int corr) {
+  return corr == 3 ? (st == 0 ? LBM_FULL_WAVES_F32 : LBM_FULL_WAVES_F16)
+                   : (st == 0 ? LBM_STEP_WAVES_F32 : LBM_STEP_WAVES_F16);
+}
+
 template <int ST, int CORR, bool WALLS>
-__global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
+__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<typename Store<ST>::T> P,
                                               const float* __restrict__ force,
                                               const float* __restrict__ grad_src, float* __restrict__ drho_out,
                                               Consts k, uint32_t bpr) {
@@ -35,6 +53,12 @@ __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  // the density gradient first (block-wide, with a barrier), while no population is live
+  float grx = 0.0f, gry = 0.0f, grz = 0.0f;
+  if constexpr (CORR == 3) {
+    __shared__ float lds[3][258];
+    density_gradient_block(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
+  }
   if (x >= k.nx) return;
   const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
   float df[27];
@@ -47,8 +71,6 @@ __global__ __launch_bounds__(256) void k_step(DirPtrs<typename Store<ST>::T> P,
   }
   float out[27];
   if constexpr (CORR == 3) {
-    float grx, gry, grz;
-    density_gradient(grad_src, x, y, z, k, grx, gry, grz);
     collide_node<CORR>(df, fx, fy, fz, k, out, grx, gry, grz);
     if (drho_out != nullptr) drho_out[node] = low_moments(df).m000;
   } else {

@@ -31,6 +31,9 @@ CASES = [
     ("aniso_walls_z", (20, 9, 14), 0.5, 0.25, "periodic", "bounceback", "uniform"),
     ("two_node_walls", (5, 2, 3), 1.3, 0.8, "bounceback", "periodic", "none"),
     ("single_node_axes", (1, 1, 1), 1.0, 0.5, "periodic", "periodic", "field"),
+    # 192-wide blocks, three per row, the last one ragged; 256-wide blocks that fill the row
+    ("blocks_192_ragged", (520, 3, 4), 1.0, 0.5, "bounceback", "periodic", "none"),
+    ("blocks_256_full", (256, 4, 3), 0.5, 0.25, "periodic", "periodic", "uniform"),
 ]
 
 
