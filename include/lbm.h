@@ -11,8 +11,9 @@
  * corrections cancel the grid-anisotropy and non-Galilean-invariant errors
  * (Sec. 2.4, eq. 38-40) with strain rates from the local system of App. D
  * (eq. 44-49), adds the body force through eq. 11c, and maps back (App. E-G).
- * Streaming is periodic along x and periodic or halfway bounce-back (Sec. 4
- * with a stationary wall) along y and z.
+ * Streaming is periodic or halfway bounce-back along each axis; bounce-back
+ * faces may move tangentially (momentum-augmented bounce-back, Sec. 4,
+ * eq. 69).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -78,18 +79,32 @@ enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2, LBM_
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
 enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1 };
 
+/* Walls.  On a bounce-back axis the walls sit half a cell outside the first
+ * and last node.  A population whose upstream node lies beyond a wall is the
+ * node's own outgoing population of the opposite direction, plus, for a
+ * moving wall, the momentum term of Sec. 4:
+ *   f_a(x, t+1) = f~_abar(x, t) - [f_eq_abar - f_eq_a](rho(x, t), u_w),
+ * f_eq the product-form equilibrium (eq. 9 mapped to populations), rho the
+ * fluid node's density (the paper's rho_w = rho_f) and u_w the face velocity;
+ * a lid moving along x gives exactly the coefficients of eq. 69.  A link that
+ * leaves through two or three faces at an edge or corner takes the mean
+ * velocity of the moving faces among them (zero if none moves), so a lid
+ * meets the side walls without a mass source.  Faces are numbered
+ * 0..5 = x-, x+, y-, y+, z-, z+. */
 typedef struct lbm_params {
-  int32_t nx, ny, nz;   /* grid nodes; each >= 1; ny, nz >= 2 on a bounce-back axis */
+  int32_t nx, ny, nz;   /* grid nodes; each >= 1; >= 2 on a bounce-back axis */
   double r, s;          /* grid aspect ratios dy/dx and dz/dx (Sec. 2.1), > 0 */
   double cs2;           /* squared sound speed; <= 0 selects min(r^2, s^2)/3 (end of Sec. 2.5) */
   double omega_nu;      /* shear rate, 0 < omega_nu < 2: nu = cs2 (1/omega_nu - 1/2) (eq. 53) */
   double omega_xi;      /* bulk rate, 0 < omega_xi < 2: xi = (2 cs2/3)(1/omega_xi - 1/2) */
   double omega_hi;      /* rate of every third- and higher-order moment; must be 1 (App. D) */
-  int32_t bc_y, bc_z;   /* enum lbm_bc; x is always periodic */
+  int32_t bc_x, bc_y, bc_z; /* enum lbm_bc per axis */
   int32_t storage;      /* enum lbm_storage */
   int32_t corr;         /* enum lbm_corr */
   double rho0;          /* reference density of the stored deviations, > 0 (usually 1) */
   double force[3];      /* uniform body force used when no force field is passed */
+  double wall_velocity[6][3]; /* velocity of each face (x-, x+, y-, y+, z-, z+); must be
+                                 zero on periodic axes and along the face normal */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -98,7 +113,8 @@ typedef struct lbm_handle lbm_handle;
  * Rejects (LBM_EINVAL): a size < 1 (or < 2 on a bounce-back axis), more than
  * 2^31 - 1 nodes, r or s <= 0, a rate outside (0, 2), omega_hi != 1, a sound
  * speed that makes a rest weight <= 0 (cs2 >= min(1, r^2, s^2)), unknown enum
- * values, rho0 <= 0. */
+ * values, rho0 <= 0, a non-finite force or wall velocity, a wall velocity on
+ * a periodic axis or with a component along its face normal. */
 int lbm_create(const lbm_params* p, lbm_handle** out);
 void lbm_destroy(lbm_handle* h);
 
@@ -197,7 +213,7 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *               for a per-node force field
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
- * Not implemented for the full corrections (LBM_EINVAL). */
+ * Not implemented for the full corrections or moving walls (LBM_EINVAL). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);

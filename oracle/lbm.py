@@ -68,7 +68,7 @@ def density_gradient(rho, p: Params):
     e = L.velocities(p.r, p.s)
     ebar = L.velocities(1.0, 1.0).round().to(torch.int64)
     idx = []
-    for n, bc in ((p.nz, p.bc_z), (p.ny, p.bc_y), (p.nx, "periodic")):
+    for n, bc in ((p.nz, p.bc_z), (p.ny, p.bc_y), (p.nx, p.bc_x)):
         base = torch.arange(n)
         idx.append({d: (torch.clamp(base + d, 0, n - 1) if bc == "bounceback" else (base + d) % n)
                     for d in (-1, 0, 1)})

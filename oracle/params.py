@@ -26,10 +26,19 @@ class Params:
     corr: str = "local"
     bc_y: str = "periodic"
     bc_z: str = "periodic"
+    bc_x: str = "periodic"
+    # tangential velocity of each wall face, in the order x-, x+, y-, y+, z-, z+
+    # (used on bounce-back axes only; Sec. 4, momentum-augmented bounce-back)
+    wall_velocity: tuple = ((0.0, 0.0, 0.0),) * 6
 
     def __post_init__(self):
         assert self.corr in CORRECTIONS, self.corr
-        assert self.bc_y in BOUNDARIES and self.bc_z in BOUNDARIES
+        assert self.bc_x in BOUNDARIES and self.bc_y in BOUNDARIES and self.bc_z in BOUNDARIES
+        wv = tuple(tuple(float(c) for c in v) for v in self.wall_velocity)
+        assert len(wv) == 6 and all(len(v) == 3 for v in wv)
+        for face, v in enumerate(wv):
+            assert v[face // 2] == 0.0, "a wall moves only tangentially"
+        object.__setattr__(self, "wall_velocity", wv)
         if self.cs2 <= 0.0:
             object.__setattr__(self, "cs2", min(self.r ** 2, self.s ** 2) / 3.0)
 

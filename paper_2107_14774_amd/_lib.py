@@ -24,9 +24,10 @@ class LbmParams(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("r", ctypes.c_double), ("s", ctypes.c_double), ("cs2", ctypes.c_double),
         ("omega_nu", ctypes.c_double), ("omega_xi", ctypes.c_double), ("omega_hi", ctypes.c_double),
-        ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("corr", ctypes.c_int32),
         ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
+        ("wall_velocity", (ctypes.c_double * 3) * 6),
     ]
 
 

@@ -461,7 +461,7 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
     P.lout[a] = adj_out + (int64_t)a * h.stride;
   }
   // 32-bit offsets need every (float) adjoint array below 4 GiB
-  const bool walls = h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * 4u >= (1ull << 32);
+  const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * 4u >= (1ull << 32);
   const dim3 grid((unsigned)nb), blk(block);
   switch (h.p.corr * 2 + (walls ? 1 : 0)) {
     case 0: hipLaunchKernelGGL((k_step_adjoint<ST, 0, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;

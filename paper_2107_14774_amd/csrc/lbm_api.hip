@@ -45,10 +45,24 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   *out = nullptr;
   lbm_params q = *p;
   if (q.nx < 1 || q.ny < 1 || q.nz < 1) return fail(LBM_EINVAL, "lbm_create: grid sizes must be >= 1");
-  if ((q.bc_y != LBM_PERIODIC && q.bc_y != LBM_BOUNCEBACK) || (q.bc_z != LBM_PERIODIC && q.bc_z != LBM_BOUNCEBACK))
-    return fail(LBM_EINVAL, "lbm_create: unknown boundary type");
-  if ((q.bc_y == LBM_BOUNCEBACK && q.ny < 2) || (q.bc_z == LBM_BOUNCEBACK && q.nz < 2))
-    return fail(LBM_EINVAL, "lbm_create: a bounce-back axis needs at least 2 nodes");
+  const int32_t bcs[3] = {q.bc_x, q.bc_y, q.bc_z};
+  const int32_t sizes[3] = {q.nx, q.ny, q.nz};
+  for (int d = 0; d < 3; ++d) {
+    if (bcs[d] != LBM_PERIODIC && bcs[d] != LBM_BOUNCEBACK) return fail(LBM_EINVAL, "lbm_create: unknown boundary type");
+    if (bcs[d] == LBM_BOUNCEBACK && sizes[d] < 2)
+      return fail(LBM_EINVAL, "lbm_create: a bounce-back axis needs at least 2 nodes");
+  }
+  int moving = 0;  // bit f: face f moves
+  for (int f = 0; f < 6; ++f) {
+    for (int c = 0; c < 3; ++c) {
+      const double v = q.wall_velocity[f][c];
+      if (!std::isfinite(v)) return fail(LBM_EINVAL, "lbm_create: non-finite wall velocity");
+      if (v == 0.0) continue;
+      if (bcs[f / 2] != LBM_BOUNCEBACK) return fail(LBM_EINVAL, "lbm_create: wall velocity on a periodic axis");
+      if (c == f / 2) return fail(LBM_EINVAL, "lbm_create: wall velocity along the face normal");
+      moving |= 1 << f;
+    }
+  }
   const int64_t n = (int64_t)q.nx * q.ny * q.nz;
   if (n > 0x7fffffffLL) return fail(LBM_EINVAL, "lbm_create: more than 2^31-1 nodes");
   if (!(q.r > 0.0) || !(q.s > 0.0)) return fail(LBM_EINVAL, "lbm_create: r and s must be > 0");
@@ -90,8 +104,12 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   clbm::Consts& k = h->k;
   clbm::ConstsD& kd = h->kd;
   k.nx = q.nx; k.ny = q.ny; k.nz = q.nz;
+  k.bb_x = q.bc_x == LBM_BOUNCEBACK;
   k.bb_y = q.bc_y == LBM_BOUNCEBACK;
   k.bb_z = q.bc_z == LBM_BOUNCEBACK;
+  k.moving = moving;
+  for (int f = 0; f < 6; ++f)
+    for (int c = 0; c < 3; ++c) k.wall_u[f][c] = (float)q.wall_velocity[f][c];
   k.stride = h->stride;
   k.n = n;
   k.rho0 = (float)q.rho0; k.cs2 = (float)q.cs2; k.r = (float)q.r; k.s = (float)q.s;
@@ -263,6 +281,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, "lbm_step_adjoint: adj_in == adj_out");
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the full corrections");
+  if (h->k.moving) return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for moving walls");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
                                            grad_force_uniform, (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");

@@ -37,7 +37,9 @@ constexpr int dir_of(int i, int j, int k) {
 // Per-launch constants, passed by value as a kernel argument.
 struct Consts {
   int nx, ny, nz;
-  int bb_y, bb_z;          // 1 = halfway bounce-back walls on that axis
+  int bb_x, bb_y, bb_z;    // 1 = halfway bounce-back walls on that axis
+  int moving;              // bit f set = face f moves (momentum-augmented bounce-back)
+  float wall_u[6][3];      // face velocities, faces x-, x+, y-, y+, z-, z+
   int64_t stride;          // elements between direction arrays
   int64_t n;               // nodes
   float rho0, cs2, r, s;
@@ -109,6 +111,7 @@ __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts&
   const int ys = ey == 0 ? c.y : (ey > 0 ? c.ym : c.yp);
   const int zs = ez == 0 ? c.z : (ez > 0 ? c.zm : c.zp);
   bool wall = false;
+  if (ex != 0) wall |= k.bb_x && (ex > 0 ? c.x == 0 : c.x == k.nx - 1);
   if (ey != 0) wall |= k.bb_y && (ey > 0 ? c.y == 0 : c.y == k.ny - 1);
   if (ez != 0) wall |= k.bb_z && (ez > 0 ? c.z == 0 : c.z == k.nz - 1);
   const int64_t node = ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;
@@ -304,6 +307,45 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   }
 }
 
+// Momentum-augmented bounce-back (Sec. 4) applied where the populations are
+// stored: the slot (alpha, x) of a population that leaves the fluid through a
+// wall is read only by the bounce-back gather of node x itself, so the
+// colliding node writes f~_alpha - [f_eq_alpha - f_eq_alphabar](rho, u_w)
+// there, rho being its own density (the fluid density the paper assigns to
+// the wall) and u_w the face velocity (an edge or corner link takes the mean
+// over the moving faces it crosses, so a lid meets the side walls without a
+// mass source).  f_eq is the product-form equilibrium; for a lid moving along
+// x the bracket is the coefficient list of eq. 69.
+__device__ __forceinline__ float weq1(int e, float u, int d, const Consts& k) {
+  const float q = (k.cs2 + u * u) * k.ic2[d];
+  return e == 0 ? 1.0f - q : 0.5f * q + 0.5f * (float)e * u * k.ic[d];
+}
+
+template <int A = 0>
+__device__ __forceinline__ void moving_wall_terms(int x, int y, int z, float rho, const Consts& k, float (&out)[27]) {
+  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
+  int cnt = 0;
+  float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+  auto cross = [&](int f) {
+    if (!((k.moving >> f) & 1)) return;
+    ++cnt;
+    ux += k.wall_u[f][0];
+    uy += k.wall_u[f][1];
+    uz += k.wall_u[f][2];
+  };
+  if (ex != 0 && k.bb_x && (ex > 0 ? x == k.nx - 1 : x == 0)) cross(ex > 0 ? 1 : 0);
+  if (ey != 0 && k.bb_y && (ey > 0 ? y == k.ny - 1 : y == 0)) cross(ey > 0 ? 3 : 2);
+  if (ez != 0 && k.bb_z && (ez > 0 ? z == k.nz - 1 : z == 0)) cross(ez > 0 ? 5 : 4);
+  if (cnt != 0) {
+    const float inv = cnt == 1 ? 1.0f : (cnt == 2 ? 0.5f : 1.0f / 3.0f);
+    ux *= inv; uy *= inv; uz *= inv;
+    const float d = weq1(ex, ux, 0, k) * weq1(ey, uy, 1, k) * weq1(ez, uz, 2, k)
+                  - weq1(-ex, ux, 0, k) * weq1(-ey, uy, 1, k) * weq1(-ez, uz, 2, k);
+    out[A] -= rho * d;
+  }
+  if constexpr (A + 1 < 27) moving_wall_terms<A + 1>(x, y, z, rho, k, out);
+}
+
 // Exact local conservation for FP32 storage.  In exact arithmetic the
 // collision keeps the mass and adds F to the momentum; in FP32 the rounding
 // of the 27 outputs leaves a residual of a few 1e-9 per node that repeats
@@ -402,7 +444,7 @@ __device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho
 
 // Block-cooperative gradient for the nodes of one row segment (blockDim.x
 // consecutive x, one y, z): each thread reduces its own column, two threads
-// reduce the halo columns x0 - 1 and x_last + 1 (periodic in x), the x
+// reduce the halo columns x0 - 1 and x_last + 1 (wrapped or mirrored), the x
 // neighbours are exchanged through LDS.  Every thread of the block must call
 // it (it contains a barrier); threads with x >= nx pass active = false.
 __device__ __forceinline__ void density_gradient_block(const float* __restrict__ drho, int x, int y, int z,
@@ -414,11 +456,11 @@ __device__ __forceinline__ void density_gradient_block(const float* __restrict__
     const ColumnSums c = column_sums(drho, rows, x, k);
     lds[0][t + 1] = c.T; lds[1][t + 1] = c.U; lds[2][t + 1] = c.V;
     if (t == 0) {
-      const ColumnSums h = column_sums(drho, rows, x == 0 ? k.nx - 1 : x - 1, k);
+      const ColumnSums h = column_sums(drho, rows, x == 0 ? (k.bb_x ? 0 : k.nx - 1) : x - 1, k);
       lds[0][0] = h.T; lds[1][0] = h.U; lds[2][0] = h.V;
     }
     if (t == (int)blockDim.x - 1 || x == k.nx - 1) {
-      const ColumnSums h = column_sums(drho, rows, x == k.nx - 1 ? 0 : x + 1, k);
+      const ColumnSums h = column_sums(drho, rows, x == k.nx - 1 ? (k.bb_x ? x : 0) : x + 1, k);
       lds[0][t + 2] = h.T; lds[1][t + 2] = h.U; lds[2][t + 2] = h.V;
     }
   }

@@ -77,6 +77,9 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
     collide_node<CORR>(df, fx, fy, fz, k, out);
   }
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
+  if constexpr (WALLS) {
+    if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
+  }
 #pragma unroll
   for (int a = 0; a < 27; ++a)
     st_off_nt(P.dst[a], node, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]));
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(256) void k_moments(const typename Store<ST>::T* __
 // ------------------------------------------------------------------ launchers
 // The 32-bit addressing of the periodic path needs every byte offset below 4 GiB.
 static bool use_general_gather(const lbm_handle& h) {
-  return h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * h.elem >= (1ull << 32);
+  return h.k.bb_x || h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * h.elem >= (1ull << 32);
 }
 
 static int grid_for(int64_t n, int block, int64_t cap) {

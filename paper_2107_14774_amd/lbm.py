@@ -72,17 +72,24 @@ def _state(h, t, name="state"):
 
 def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, omega_hi=1.0,
                bc_y="periodic", bc_z="periodic", storage="f32", corr="local", rho0=1.0,
-               force=(0.0, 0.0, 0.0)):
+               force=(0.0, 0.0, 0.0), bc_x="periodic", wall_velocity=None):
+    """wall_velocity: None or six 3-vectors, faces x-, x+, y-, y+, z-, z+."""
     lib = _lib.load()
     p = _lib.LbmParams()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.r, p.s, p.cs2 = r, s, cs2
     p.omega_nu, p.omega_xi, p.omega_hi = omega_nu, omega_xi, omega_hi
-    p.bc_y, p.bc_z = _lib.BC[bc_y], _lib.BC[bc_z]
+    p.bc_x, p.bc_y, p.bc_z = _lib.BC[bc_x], _lib.BC[bc_y], _lib.BC[bc_z]
     p.storage, p.corr = _lib.STORAGE[storage], _lib.CORR[corr]
     p.rho0 = rho0
     for d in range(3):
         p.force[d] = float(force[d])
+    if wall_velocity is not None:
+        if len(wall_velocity) != 6:
+            raise ValueError("wall_velocity: six faces (x-, x+, y-, y+, z-, z+)")
+        for f, v in enumerate(wall_velocity):
+            for d in range(3):
+                p.wall_velocity[f][d] = float(v[d])
     raw = _lib.ctypes.c_void_p()
     _lib.check(lib.lbm_create(_lib.ctypes.byref(p), _lib.ctypes.byref(raw)))
     return Handle(raw, p)

@@ -20,8 +20,9 @@ def test_library_exports_every_declared_function():
 
 
 def test_params_struct_layout_matches_header():
-    # int32 x3, pad, double x6, int32 x4, double, double[3]
-    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 4 + 8 + 24
+    # int32 x3, pad, double x6, int32 x5, pad, double, double[3], double[6][3]
+    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 + 24 + 144
+    assert _lib.LbmParams.wall_velocity.offset == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 + 24
 
 
 def test_create_sizes_and_padding():
@@ -44,6 +45,10 @@ def test_create_sizes_and_padding():
     (dict(rho0=0.0), "rho0"),
     (dict(ny=1, bc_y="bounceback"), "bounce-back"),
     (dict(force=(float("nan"), 0.0, 0.0)), "non-finite"),
+    (dict(nx=1, bc_x="bounceback"), "bounce-back"),
+    (dict(wall_velocity=[(0, 0, 0), (0, 0, 0), (0, 0, 0), (0.1, 0, 0), (0, 0, 0), (0, 0, 0)]), "periodic axis"),
+    (dict(bc_y="bounceback", wall_velocity=[(0, 0, 0)] * 3 + [(0, 0.1, 0)] + [(0, 0, 0)] * 2), "normal"),
+    (dict(bc_y="bounceback", wall_velocity=[(0, 0, 0)] * 3 + [(float("inf"), 0, 0)] + [(0, 0, 0)] * 2), "non-finite"),
 ])
 def test_create_rejects_invalid(kw, msg):
     args = dict(nx=4, ny=4, nz=4, r=1.0, s=1.0)

@@ -30,14 +30,16 @@ ADJ_CASES = [
     ("duct_walls_local", (19, 10, 8), 1.0, 0.25, "bounceback", "bounceback", "local"),
     ("aniso_lowmach", (16, 9, 12), 0.5, 0.25, "periodic", "bounceback", "lowmach"),
     ("walls_off", (12, 7, 6), 0.8, 1.2, "bounceback", "periodic", "off"),
+    ("x_walls_local", (11, 6, 5), 0.5, 1.0, "bounceback", "bounceback", "local", "bounceback"),
 ]
 
 
 @pytest.mark.parametrize("case", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
 def test_step_adjoint_matches_oracle_vjp(case):
-    name, (nx, ny, nz), r, s, by, bz, corr = case
+    name, (nx, ny, nz), r, s, by, bz, corr = case[:7]
+    bx = case[7] if len(case) > 7 else "periodic"
     _say("case", name)
-    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_y=by, bc_z=bz)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_y=by, bc_z=bz, bc_x=bx)
     f0 = fp32_rounded_state(random_state(p, 21), p)
     g = np.random.Generator(np.random.PCG64(22))
     force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32)
