@@ -76,6 +76,14 @@ enum lbm_storage { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
  *          lbm_step_adjoint reject it). */
 enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2, LBM_CORR_FULL = 3 };
 
+/* Moments the collision relaxes.  CENTRAL: the 3DCCM-LBM (Sec. 3.2).  RAW:
+ * the raw-moment scheme of Sec. 7 (3DCRM-LBM): the same steps without the
+ * frame transformation around the collision, with raw equilibria (eq. 10),
+ * the same corrections, and the raw image F(-u) Phi^c of the central source
+ * (eq. 11c); the strain rates of the corrections come from the same
+ * non-equilibrium moments.  Forward steps only (the adjoint rejects RAW). */
+enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
+
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
 enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1 };
 
@@ -101,6 +109,7 @@ typedef struct lbm_params {
   int32_t bc_x, bc_y, bc_z; /* enum lbm_bc per axis */
   int32_t storage;      /* enum lbm_storage */
   int32_t corr;         /* enum lbm_corr */
+  int32_t moments;      /* enum lbm_moments_basis */
   double rho0;          /* reference density of the stored deviations, > 0 (usually 1) */
   double force[3];      /* uniform body force used when no force field is passed */
   double wall_velocity[6][3]; /* velocity of each face (x-, x+, y-, y+, z-, z+); must be
@@ -213,7 +222,8 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *               for a per-node force field
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
- * Not implemented for the full corrections or moving walls (LBM_EINVAL). */
+ * Not implemented for the full corrections, moving walls or the raw-moment
+ * scheme (LBM_EINVAL). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);

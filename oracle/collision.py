@@ -12,6 +12,8 @@ Follows the bullet list of Sec. 3.2 in order, with explicit 27x27 matrices:
   f~ = P^-1 m~                    (App. G)
 
 The velocity is the force-shifted one of eq. 12: rho u = sum f e + F/2.
+With ``moments="raw"`` the relaxation acts on the raw moments instead (the
+raw-moment scheme of Sec. 7; ``relax_raw``).
 Readings where the paper is silent or garbled (see the design notes):
 * the non-equilibrium moments of the strain-rate solve are the pre-collision
   central moments minus the *uncorrected* equilibria (eq. 45-46);
@@ -151,6 +153,36 @@ def relax_central(mc, rho, u, force, p: Params, grad_rho):
     return n_post @ Binv.T, du
 
 
+def relax_raw(m, mc, rho, u, force, p: Params, grad_rho):
+    """Post-collision raw moments of the raw-moment scheme (3DCRM-LBM, Sec. 7).
+
+    The relaxation of the combined moments (App. D) acts on raw moments: the
+    raw equilibria are F(-u) applied to the central ones (eq. 10), the
+    corrections enter the same combined second-order equilibria, and the
+    source is the raw image F(-u) Phi^c of the central source of eq. 11c.
+    The strain rates of the corrections are taken from the central moments
+    ``mc`` exactly as in the central scheme.  Returns (m~, strain rates).
+    """
+    n_nodes = m.shape[0]
+    B, Binv = L.B_matrix(), L.B_inverse()
+    Finv = L.frame_matrix_inverse(u)
+    if p.corr == "off":
+        du = torch.zeros(n_nodes, 3, dtype=m.dtype)
+    else:
+        du = strain_rates(mc @ B.T, rho, u, p, grad_rho)
+    m_eq = torch.einsum("nab,nb->na", Finv, EQ.central_equilibrium(rho, p.cs2))
+    n_eq = (m_eq @ B.T).clone()
+    corr = correction_terms(rho, u, du, p, grad_rho)
+    n_eq[:, L.N_2D1] = n_eq[:, L.N_2D1] + corr[:, 0]
+    n_eq[:, L.N_2D2] = n_eq[:, L.N_2D2] + corr[:, 1]
+    n_eq[:, L.N_2S] = n_eq[:, L.N_2S] + corr[:, 2]
+    phi = torch.einsum("nab,nb->na", Finv, EQ.central_source(force)) @ B.T
+    lam = relaxation_diag(p)
+    nvec = m @ B.T
+    n_post = nvec + lam * (n_eq - nvec) + (1.0 - 0.5 * lam) * phi
+    return n_post @ Binv.T, du
+
+
 def collide(f, force, p: Params, grad_rho=None, return_info=False):
     """Post-collision populations f~ for populations ``f`` (N, 27) and force (N, 3)."""
     n_nodes = f.shape[0]
@@ -169,11 +201,17 @@ def collide(f, force, p: Params, grad_rho=None, return_info=False):
     # pre-collision central moments
     mc = torch.einsum("nab,nb->na", L.frame_matrix(u), m)
 
-    # relaxation in central-moment space (B, strain rates, extended equilibria, B^-1)
-    mc_post, du = relax_central(mc, rho, u, force, p, grad_rho)
+    if p.moments == "raw":
+        # relaxation of raw moments (no frame transformation around the collision)
+        m_post, du = relax_raw(m, mc, rho, u, force, p, grad_rho)
+        mc_post = torch.einsum("nab,nb->na", L.frame_matrix(u), m_post)
+    else:
+        # relaxation in central-moment space (B, strain rates, extended equilibria, B^-1)
+        mc_post, du = relax_central(mc, rho, u, force, p, grad_rho)
+        # back to raw moments
+        m_post = torch.einsum("nab,nb->na", L.frame_matrix_inverse(u), mc_post)
 
-    # back to raw moments, unscale, back to populations
-    m_post = torch.einsum("nab,nb->na", L.frame_matrix_inverse(u), mc_post)
+    # unscale, back to populations
     m_post = m_post / S
     f_post = m_post @ Pinv.T
     if return_info:

@@ -9,6 +9,9 @@ from dataclasses import dataclass
 #   "full"    -- theta and lambda; needs the density gradient from a finite-difference stencil
 CORRECTIONS = ("off", "lowmach", "local", "full")
 BOUNDARIES = ("periodic", "bounceback")
+# Moments relaxed by the collision: "central" (3DCCM-LBM, Sec. 3.2) or "raw"
+# (3DCRM-LBM: the same steps without the frame transformations, Sec. 3.1 and Sec. 7)
+MOMENT_BASES = ("central", "raw")
 
 
 @dataclass(frozen=True)
@@ -30,9 +33,11 @@ class Params:
     # tangential velocity of each wall face, in the order x-, x+, y-, y+, z-, z+
     # (used on bounce-back axes only; Sec. 4, momentum-augmented bounce-back)
     wall_velocity: tuple = ((0.0, 0.0, 0.0),) * 6
+    moments: str = "central"
 
     def __post_init__(self):
         assert self.corr in CORRECTIONS, self.corr
+        assert self.moments in MOMENT_BASES, self.moments
         assert self.bc_x in BOUNDARIES and self.bc_y in BOUNDARIES and self.bc_z in BOUNDARIES
         wv = tuple(tuple(float(c) for c in v) for v in self.wall_velocity)
         assert len(wv) == 6 and all(len(v) == 3 for v in wv)

@@ -74,6 +74,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   if (q.omega_hi != 1.0) return fail(LBM_EINVAL, "lbm_create: only omega_hi = 1 is implemented");
   if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
   if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
+  if (q.moments != LBM_CENTRAL && q.moments != LBM_RAW) return fail(LBM_EINVAL, "lbm_create: unknown moment basis");
   if (!(q.rho0 > 0.0)) return fail(LBM_EINVAL, "lbm_create: rho0 must be > 0");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(q.force[d])) return fail(LBM_EINVAL, "lbm_create: non-finite force");
@@ -282,6 +283,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the full corrections");
   if (h->k.moving) return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for moving walls");
+  if (h->p.moments == LBM_RAW) return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the raw-moment scheme");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
                                            grad_force_uniform, (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");

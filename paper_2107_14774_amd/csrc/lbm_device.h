@@ -208,7 +208,13 @@ __device__ __forceinline__ AxisVec axis_vectors(float u, int d, const Consts& k)
 // which equals P^-1 S^-1 F(-u) applied to the post-collision central moments.
 // CORR: 0 none, 1 low-Mach theta, 2 theta with the 3u^2 terms, 3 as 2 plus the
 // density-gradient terms (gx, gy, gz = grad rho, used only when CORR == 3).
-template <int CORR>
+// RAW: relax raw instead of central moments (the raw-moment scheme of Sec. 7).
+// With unit higher-order rates the two schemes share every post-collision
+// moment of order <= 2; the raw scheme sets the higher raw moments to their
+// equilibria plus half the source, so its relaxed second-order
+// non-equilibrium parts Delta map back through the per-axis basis at u = 0
+// (A0 = (0, 1, 0), A1 = (-1, 0, 1)/(2c), A2 unchanged) instead of at u.
+template <int CORR, bool RAW = false>
 __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, float fy, float fz,
                                              const Consts& k, float (&out)[27],
                                              float grx = 0.0f, float gry = 0.0f, float grz = 0.0f) {
@@ -283,26 +289,59 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   const AxisVec X = axis_vectors(ux, 0, k);
   const AxisVec Y = axis_vectors(uy, 1, k);
   const AxisVec Z = axis_vectors(uz, 2, k);
+  if constexpr (!RAW) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const float eE = drho * X.E[i] + rho0 * X.D[i];
-    const float eW = rho0 * X.W0[i];
-    const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
-    const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
-    const float a2 = Dyy * X.A0[i];
-    const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
-    const float b1 = Dyz * X.A0[i];
-    const float c0 = Dzz * X.A0[i];
+    for (int i = 0; i < 3; ++i) {
+      const float eE = drho * X.E[i] + rho0 * X.D[i];
+      const float eW = rho0 * X.W0[i];
+      const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
+      const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
+      const float a2 = Dyy * X.A0[i];
+      const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
+      const float b1 = Dyz * X.A0[i];
+      const float c0 = Dzz * X.A0[i];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const float QE = eE * Y.E[j] + eW * Y.D[j];
-      const float QW = eW * Y.W0[j];
-      const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j] + a2 * Y.A2[j];
-      const float Q1 = b0 * Y.A0[j] + b1 * Y.A1[j];
-      const float Q2 = c0 * Y.A0[j];
+      for (int j = 0; j < 3; ++j) {
+        const float QE = eE * Y.E[j] + eW * Y.D[j];
+        const float QW = eW * Y.W0[j];
+        const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j] + a2 * Y.A2[j];
+        const float Q1 = b0 * Y.A0[j] + b1 * Y.A1[j];
+        const float Q2 = c0 * Y.A0[j];
 #pragma unroll
-      for (int l = 0; l < 3; ++l)
-        out[dir_of(i, j, l)] = QE * Z.E[l] + QW * Z.D[l] + Q0 * Z.A0[l] + Q1 * Z.A1[l] + Q2 * Z.A2[l];
+        for (int l = 0; l < 3; ++l)
+          out[dir_of(i, j, l)] = QE * Z.E[l] + QW * Z.D[l] + Q0 * Z.A0[l] + Q1 * Z.A1[l] + Q2 * Z.A2[l];
+      }
+    }
+  } else {
+    // equilibrium and first-order source through the basis at u, second order through the basis at 0
+    const float hx = 0.5f * k.ic[0], hy = 0.5f * k.ic[1], hz = 0.5f * k.ic[2];
+    const float cxy = Dxy * hx * hy, cxz = Dxz * hx * hz, cyz = Dyz * hy * hz;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float eE = drho * X.E[i] + rho0 * X.D[i];
+      const float eW = rho0 * X.W0[i];
+      const float a0 = Dx * X.A1[i];
+      const float a1 = Dy * X.A0[i];
+      const float b0 = Dz * X.A0[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float QE = eE * Y.E[j] + eW * Y.D[j];
+        const float QW = eW * Y.W0[j];
+        const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j];
+        const float Q1 = b0 * Y.A0[j];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          float v = QE * Z.E[l] + QW * Z.D[l] + Q0 * Z.A0[l] + Q1 * Z.A1[l];
+          // second-order Delta_mnp A_m(0) A_n(0) A_p(0): most products vanish at compile time
+          if (j == 1 && l == 1) v += Dxx * X.A2[i];
+          if (i == 1 && l == 1) v += Dyy * Y.A2[j];
+          if (i == 1 && j == 1) v += Dzz * Z.A2[l];
+          if (l == 1) v += cxy * (float)((i - 1) * (j - 1));
+          if (j == 1) v += cxz * (float)((i - 1) * (l - 1));
+          if (i == 1) v += cyz * (float)((j - 1) * (l - 1));
+          out[dir_of(i, j, l)] = v;
+        }
+      }
     }
   }
 }

@@ -44,7 +44,7 @@ constexpr int step_waves(int st, int corr) {
                    : (st == 0 ? LBM_STEP_WAVES_F32 : LBM_STEP_WAVES_F16);
 }
 
-template <int ST, int CORR, bool WALLS>
+template <int ST, int CORR, bool WALLS, bool RAW>
 __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<typename Store<ST>::T> P,
                                               const float* __restrict__ force,
                                               const float* __restrict__ grad_src, float* __restrict__ drho_out,
@@ -71,10 +71,10 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
   }
   float out[27];
   if constexpr (CORR == 3) {
-    collide_node<CORR>(df, fx, fy, fz, k, out, grx, gry, grz);
+    collide_node<CORR, RAW>(df, fx, fy, fz, k, out, grx, gry, grz);
     if (drho_out != nullptr) drho_out[node] = low_moments(df).m000;
   } else {
-    collide_node<CORR>(df, fx, fy, fz, k, out);
+    collide_node<CORR, RAW>(df, fx, fy, fz, k, out);
   }
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
   if constexpr (WALLS) {
@@ -287,18 +287,22 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
   }
   const bool walls = use_general_gather(h);
   const dim3 grid((unsigned)nb), blk(block);
-#define CLBM_STEP(C, W) \
-  hipLaunchKernelGGL((k_step<ST, C, W>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
-  switch (h.p.corr * 2 + (walls ? 1 : 0)) {
-    case 0: CLBM_STEP(0, false); break;
-    case 1: CLBM_STEP(0, true); break;
-    case 2: CLBM_STEP(1, false); break;
-    case 3: CLBM_STEP(1, true); break;
-    case 4: CLBM_STEP(2, false); break;
-    case 5: CLBM_STEP(2, true); break;
-    case 6: CLBM_STEP(3, false); break;
-    default: CLBM_STEP(3, true); break;
+#define CLBM_STEP(C, W, R) \
+  hipLaunchKernelGGL((k_step<ST, C, W, R>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
+#define CLBM_STEP_CORR(W, R)                   \
+  switch (h.p.corr) {                          \
+    case 0: CLBM_STEP(0, W, R); break;         \
+    case 1: CLBM_STEP(1, W, R); break;         \
+    case 2: CLBM_STEP(2, W, R); break;         \
+    default: CLBM_STEP(3, W, R); break;        \
   }
+  const bool raw = h.p.moments == LBM_RAW;
+  if (walls) {
+    if (raw) { CLBM_STEP_CORR(true, true) } else { CLBM_STEP_CORR(true, false) }
+  } else {
+    if (raw) { CLBM_STEP_CORR(false, true) } else { CLBM_STEP_CORR(false, false) }
+  }
+#undef CLBM_STEP_CORR
 #undef CLBM_STEP
   return hipGetLastError();
 }

@@ -72,7 +72,7 @@ def _state(h, t, name="state"):
 
 def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, omega_hi=1.0,
                bc_y="periodic", bc_z="periodic", storage="f32", corr="local", rho0=1.0,
-               force=(0.0, 0.0, 0.0), bc_x="periodic", wall_velocity=None):
+               force=(0.0, 0.0, 0.0), bc_x="periodic", wall_velocity=None, moments="central"):
     """wall_velocity: None or six 3-vectors, faces x-, x+, y-, y+, z-, z+."""
     lib = _lib.load()
     p = _lib.LbmParams()
@@ -81,6 +81,7 @@ def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, om
     p.omega_nu, p.omega_xi, p.omega_hi = omega_nu, omega_xi, omega_hi
     p.bc_x, p.bc_y, p.bc_z = _lib.BC[bc_x], _lib.BC[bc_y], _lib.BC[bc_z]
     p.storage, p.corr = _lib.STORAGE[storage], _lib.CORR[corr]
+    p.moments = _lib.MOMENTS[moments]
     p.rho0 = rho0
     for d in range(3):
         p.force[d] = float(force[d])

@@ -20,9 +20,10 @@ def test_library_exports_every_declared_function():
 
 
 def test_params_struct_layout_matches_header():
-    # int32 x3, pad, double x6, int32 x5, pad, double, double[3], double[6][3]
-    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 + 24 + 144
-    assert _lib.LbmParams.wall_velocity.offset == 4 * 3 + 4 + 8 * 6 + 4 * 5 + 4 + 8 + 24
+    # int32 x3, pad, double x6, int32 x6, double, double[3], double[6][3]
+    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 6 + 8 + 24 + 144
+    assert _lib.LbmParams.rho0.offset == 4 * 3 + 4 + 8 * 6 + 4 * 6
+    assert _lib.LbmParams.wall_velocity.offset == 4 * 3 + 4 + 8 * 6 + 4 * 6 + 8 + 24
 
 
 def test_create_sizes_and_padding():
@@ -101,3 +102,18 @@ def test_full_corrections_need_the_density_field_entry_point():
     hl = P.lbm_create(4, 4, 4, corr="local")
     assert lib.lbm_step_full(hl.raw, 1, a, b, None, d1, d2, 1, None) == _lib.LBM_EINVAL
     assert b"LBM_CORR_FULL" in lib.lbm_last_error()
+
+
+def test_adjoint_rejects_what_it_does_not_differentiate():
+    lib = _lib.load()
+    a, b, c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    for kw in (dict(moments="raw"), dict(bc_y="bounceback", wall_velocity=[(0, 0, 0)] * 3 + [(0.1, 0, 0)] + [(0, 0, 0)] * 2)):
+        h = P.lbm_create(4, 4, 4, **kw)
+        assert lib.lbm_step_adjoint(h.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
+    prm = _lib.LbmParams()
+    prm.nx = prm.ny = prm.nz = 4
+    prm.r = prm.s = prm.omega_nu = prm.omega_xi = prm.omega_hi = prm.rho0 = 1.0
+    prm.moments = 7
+    raw = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(prm), ctypes.byref(raw)) == _lib.LBM_EINVAL
+    assert b"moment basis" in lib.lbm_last_error()

@@ -258,3 +258,57 @@ def test_density_gradient_exact_for_quadratics_and_mirrored_at_walls():
     big = torch.cat([big, big.flip(0)], 0)
     want = OL.density_gradient(big, pp)[:, :n_z, :n_y]
     assert torch.allclose(OL.density_gradient(base, pw), want, atol=1e-14)
+
+
+# ------------------------------------------------------------------ raw-moment scheme (Sec. 7)
+
+def _orders(mask_fn):
+    return torch.tensor([mask_fn(sum(mn)) for mn in L.MOMENTS])
+
+
+@pytest.mark.parametrize("corr", ["off", "lowmach", "local", "full"])
+@pytest.mark.parametrize("r,s", [(1.0, 0.5), (0.5, 0.25)])
+def test_raw_scheme_equals_central_up_to_second_order(corr, r, s):
+    """Relaxing raw or central moments gives the same post-collision moments of order <= 2
+    (the non-equilibrium second-order parts and the source images agree, Sec. 2.4) and
+    different higher-order moments (the central frame carries u x non-equilibrium terms)."""
+    cs2 = min(r * r, s * s) / 3
+    kw = dict(r=r, s=s, omega_nu=1.45, omega_xi=1.2, corr=corr)
+    pc, pr = oracle.Params(1, 1, 1, **kw), oracle.Params(1, 1, 1, moments="raw", **kw)
+    f, g = _rand_state(30, 31, r, s, cs2, amp_u=0.04)
+    force = 1e-3 * (torch.rand(30, 3, generator=g, dtype=DT) - 0.5)
+    grad = 1e-2 * (torch.rand(30, 3, generator=g, dtype=DT) - 0.5)
+    Q = L.P_matrix() * L.S_diag(r, s)[:, None]
+    mc = C.collide(f, force, pc, grad_rho=grad) @ Q.T
+    mr = C.collide(f, force, pr, grad_rho=grad) @ Q.T
+    low = _orders(lambda o: o <= 2)
+    assert torch.allclose(mc[:, low], mr[:, low], atol=1e-14)
+    assert (mc[:, ~low] - mr[:, ~low]).abs().max() > 1e-8
+
+
+def test_raw_scheme_higher_moments_are_equilibrium_plus_half_source():
+    """With unit higher-order rates the raw scheme sets every raw moment of order >= 3 to its
+    equilibrium (eq. 10) plus half the raw image of the central source (eq. 11c)."""
+    r, s = 0.7, 0.4
+    cs2 = min(r * r, s * s) / 3
+    p = oracle.Params(1, 1, 1, r=r, s=s, omega_nu=1.3, omega_xi=1.1, corr="local", moments="raw")
+    f, g = _rand_state(20, 32, r, s, cs2, amp_u=0.04)
+    force = 1e-3 * (torch.rand(20, 3, generator=g, dtype=DT) - 0.5)
+    rho, u = C.macroscopic(f, force, p)
+    Q = L.P_matrix() * L.S_diag(r, s)[:, None]
+    m = C.collide(f, force, p) @ Q.T
+    Finv = L.frame_matrix_inverse(u)
+    want = torch.einsum("nab,nb->na", Finv, EQ.central_equilibrium(rho, cs2) + 0.5 * EQ.central_source(force))
+    hi = _orders(lambda o: o >= 3)
+    assert torch.allclose(m[:, hi], want[:, hi], atol=1e-15)
+
+
+def test_raw_scheme_without_corrections_at_unit_rates_is_the_central_scheme():
+    r, s = 0.5, 0.25
+    cs2 = min(r * r, s * s) / 3
+    kw = dict(r=r, s=s, omega_nu=1.0, omega_xi=1.0, corr="off")
+    f, g = _rand_state(20, 33, r, s, cs2)
+    force = 1e-3 * (torch.rand(20, 3, generator=g, dtype=DT) - 0.5)
+    a = C.collide(f, force, oracle.Params(1, 1, 1, **kw))
+    b = C.collide(f, force, oracle.Params(1, 1, 1, moments="raw", **kw))
+    assert torch.allclose(a, b, atol=1e-15)
