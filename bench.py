@@ -248,6 +248,108 @@ def cpu_baseline(w):
                       f"(r={rep.r}, s={rep.s}, same viscosity), {dt:.1f} s"}
 
 
+# ---------------------------------------------------------------------- rocprofv3 summaries
+PROFILE_KERNELS = {
+    "f32": "k_step<0, 2, false, false>", "f16": "k_step<1, 2, false, false>", "bf16": "k_step<2, 2, false, false>",
+    "full_f32": "k_step<0, 3, false, false>", "full_f16": "k_step<1, 3, false, false>",
+    "adjoint_f32": "k_step_adjoint<0, 2, true>", "adjoint_f16": "k_step_adjoint<1, 2, false>",
+}
+PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
+    "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),
+    "bf16": (512, 512, 256, "512x512x256"), "full_f32": (512, 512, 256, "512x512x256"),
+    "full_f16": (512, 512, 256, "512x512x256"), "adjoint_f32": (128, 128, 64, "128x128x64 duct"),
+    "adjoint_f16": (384, 384, 192, "384x384x192"),
+}
+TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_step -o step --output-format csv -- "
+             "python3 bench.py --steps 30 --warmup 5 --no-cpu-baseline")
+PMC_CMD = ("timeout -s KILL 240 rocprofv3 --pmc {c} -d gpurun_out/pmc_{d} -o {d} --output-format csv -- "
+           "python3 bench.py --steps 4 --warmup 1 --no-cpu-baseline")
+SUMMARY_CMD = "python3 bench.py --summarize-rocprof gpurun_out"
+TRACE_SUMMARY = "profiles/k_step_and_adjoint_kernel_trace.txt"
+TRAFFIC_SUMMARY = "profiles/k_step_and_adjoint_hbm_traffic.txt"
+
+
+def _launch_grid(nx, ny, nz):
+    """Total threads of a node-kernel launch (the library's block-width rule)."""
+    best, waste = 256, 1 << 30
+    for b in (256, 192, 128, 64):
+        w = (nx + b - 1) // b * b - nx
+        if w < waste:
+            best, waste = b, w
+    return str((nx + best - 1) // best * best * ny * nz)
+
+
+def summarize_rocprof(out_dir):
+    """Write the kernel-trace and HBM-traffic summaries (and traffic.json) under profiles/ from the
+    CSVs of the three rocprofv3 runs named in TRACE_CMD and PMC_CMD, found under ``out_dir``."""
+    import csv
+    import statistics
+    alg = dict(BYTES_PER_LUP, **ADJ_BYTES_PER_LUP)
+    trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
+    lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
+             "# corrections) and its adjoint (128x128x64 duct with force field; 384x384x192, r=1/2, s=1/4, FP16)",
+             "", "commands (repo root, one MI355X, TMPDIR=/tmp):", "  " + TRACE_CMD, "  " + SUMMARY_CMD, "",
+             "kernel                         variant      workload         calls  avg_ms   min_ms   max_ms   "
+             "MLUPS(avg)  alg_B/LUP  alg_GB/s  frac_of_8TB/s"]
+    for v, key in PROFILE_KERNELS.items():
+        nx, ny, nz, label = PROFILE_WORKLOADS[v]
+        grid = _launch_grid(nx, ny, nz)
+        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+             if key in r["Kernel_Name"] and r["Grid_Size_X"] == grid]
+        if not d:
+            continue
+        n = nx * ny * nz
+        avg = statistics.mean(d) / 1e6
+        b = alg[v]
+        lines.append(f"{key:30s} {v:12s} {label:16s} {len(d):5d}  {avg:.4f}  {min(d) / 1e6:.4f}  {max(d) / 1e6:.4f}"
+                     f"  {n / avg / 1e3:10.0f}  {b:9d}  {b * n / avg / 1e6:8.0f}  {b * n / avg / 1e6 / HBM_PEAK_GBS:.3f}")
+    lines += ["", "(kernels grouped by name and grid size; the adjoint calls include the backward passes of bench.py)"]
+    with open(os.path.join(ROOT, TRACE_SUMMARY), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def rows(kind):
+        return list(csv.DictReader(open(os.path.join(out_dir, f"pmc_{kind}", f"{kind}_counter_collection.csv"))))
+    fe, wr = rows("fetch"), rows("write")
+    copy_bytes = 4 << 30
+    # the 4 GiB copies of copy_bandwidth() (11 per run) are the largest copy kernels of the run
+    cf = sorted(float(r["Counter_Value"]) for r in fe if "copyBuffer" in r["Kernel_Name"])[-11:]
+    cw = sorted(float(r["Counter_Value"]) for r in wr if "copyBuffer" in r["Kernel_Name"])[-11:]
+    kf = (copy_bytes / 1024) / statistics.mean(cf)
+    kw = (copy_bytes / 1024) / statistics.mean(cw)
+    lines = ["# HBM traffic of the step kernels (512x512x256, r=1, s=1/2) and the adjoint from rocprofv3 counters",
+             "", "commands (repo root, one MI355X, TMPDIR=/tmp), one counter per pass:",
+             "  " + PMC_CMD.format(c="FETCH_SIZE", d="fetch"), "  " + PMC_CMD.format(c="WRITE_SIZE", d="write"),
+             "  " + SUMMARY_CMD, "",
+             "calibration: the 4 GiB device-to-device copy in the same runs (hipMemcpy kernel __amd_rocclr_copyBuffer,",
+             f"reads and writes exactly {copy_bytes} bytes): mean FETCH_SIZE {statistics.mean(cf):.1f} KiB -> scale "
+             f"{kf:.4f};", f"mean WRITE_SIZE {statistics.mean(cw):.1f} KiB -> scale {kw:.4f}", "",
+             "kernel                         variant      FETCH_KiB(raw)  WRITE_KiB(raw)  read_B/LUP  write_B/LUP  "
+             "total_B/LUP  algorithmic_B/LUP"]
+    traffic = {}
+    for v, key in PROFILE_KERNELS.items():
+        nx, ny, nz, _ = PROFILE_WORKLOADS[v]
+        grid = _launch_grid(nx, ny, nz)
+        fv = [float(r["Counter_Value"]) for r in fe if key in r["Kernel_Name"] and r["Grid_Size"] == grid]
+        wv = [float(r["Counter_Value"]) for r in wr if key in r["Kernel_Name"] and r["Grid_Size"] == grid]
+        if not fv or not wv:
+            continue
+        n = nx * ny * nz
+        rb = statistics.mean(fv) * 1024 * kf / n
+        wb = statistics.mean(wv) * 1024 * kw / n
+        lines.append(f"{key:30s} {v:12s} {statistics.mean(fv):14.1f}  {statistics.mean(wv):14.1f}  {rb:10.2f}  "
+                     f"{wb:11.2f}  {rb + wb:11.2f}  {alg[v]:17d}")
+        traffic[v] = {"kernel": key, "bytes_per_launch": round((rb + wb) * n), "bytes_per_lup": round(rb + wb, 3),
+                      "read_bytes_per_lup": round(rb, 3), "write_bytes_per_lup": round(wb, 3),
+                      "source_sha": sources_sha(ADJOINT_SOURCES if v.startswith("adjoint") else KERNEL_SOURCES),
+                      "summary": TRAFFIC_SUMMARY}
+    with open(os.path.join(ROOT, TRAFFIC_SUMMARY), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    print(open(os.path.join(ROOT, TRACE_SUMMARY)).read())
+    print(open(os.path.join(ROOT, TRAFFIC_SUMMARY)).read())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +357,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--variants", default="f32,f16,bf16,full_f32,full_f16,adjoint_f32,adjoint_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-rocprof", metavar="DIR", default=None,
+                    help="write the profiles/ summaries from rocprofv3 CSVs under DIR (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        summarize_rocprof(args.summarize_rocprof)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU z-slab decomposition is a design note, not built)", file=sys.stderr)

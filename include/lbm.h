@@ -81,7 +81,7 @@ enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2, LBM_
  * frame transformation around the collision, with raw equilibria (eq. 10),
  * the same corrections, and the raw image F(-u) Phi^c of the central source
  * (eq. 11c); the strain rates of the corrections come from the same
- * non-equilibrium moments.  Forward steps only (the adjoint rejects RAW). */
+ * non-equilibrium moments. */
 enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
 
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
@@ -161,6 +161,22 @@ int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream);
 int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
              const float* force, void* hip_stream);
 
+/* Replace the handle's uniform body force (p->force), used by every later call
+ * that is given no force field.  Host-side only (no GPU work); must not run
+ * concurrently with other calls on the same handle.  LBM_EINVAL if a
+ * component is not finite. */
+int lbm_set_force(lbm_handle* h, const double force[3]);
+
+/* Advance nsteps >= 0 steps like lbm_step, step t using the uniform body force
+ * forces[3 t .. 3 t + 2] instead of p->force (a time-dependent forcing such as
+ * the pulsatile duct of Sec. 5.2, F_x = F_m cos(omega t)).
+ *   forces: HOST double[nsteps][3], read before the call returns (it may be
+ *           freed afterwards); LBM_EINVAL if NULL or not finite.
+ * p->force is left unchanged; pass the force of the current time to
+ * lbm_set_force before lbm_moments to read eq. 12's velocity at that time. */
+int lbm_step_forcing(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
+                     const double* forces, void* hip_stream);
+
 /* Density deviation rho - rho0 of every node of a state (the sum of its 27
  * gathered populations minus rho0, eq. 12), in FP32, bit-identical to the
  * density the step computes for that node.
@@ -222,8 +238,8 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *               for a per-node force field
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
- * Not implemented for the full corrections, moving walls or the raw-moment
- * scheme (LBM_EINVAL). */
+ * Moving walls (their terms depend on the node's density) and the raw-moment
+ * scheme are included.  Not implemented for the full corrections (LBM_EINVAL). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);

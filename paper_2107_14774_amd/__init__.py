@@ -7,5 +7,5 @@ autograd wrapper with checkpointing.
 """
 
 from .lbm import (Lattice, Handle, relaxation_rates, lbm_create, lbm_init, lbm_import, lbm_export,  # noqa: F401
-                  lbm_step, lbm_density, lbm_step_full, lbm_moments, lbm_check_sums, lbm_step_adjoint, lbm_moments_adjoint,
+                  lbm_step, lbm_set_force, lbm_step_forcing, lbm_density, lbm_step_full, lbm_moments, lbm_check_sums, lbm_step_adjoint, lbm_moments_adjoint,
                   lbm_init_adjoint, lbm_adjoint_to_natural, lbm_adjoint_from_natural)

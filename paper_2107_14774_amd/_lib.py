@@ -53,6 +53,8 @@ _SIGNATURES = {
     "lbm_export": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "lbm_density": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbm_set_force": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_step_forcing": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "lbm_step_full": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "lbm_check_sums": (ctypes.c_int, [_P, _P, _P]),

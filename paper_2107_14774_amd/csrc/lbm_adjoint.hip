@@ -22,7 +22,10 @@
 namespace clbm {
 
 // lambda^T dC/d(df, F) at one node: mu = (dC/d df)^T lam, gf = (dC/dF)^T lam.
-template <int CORR>
+// RAW: the raw-moment scheme, whose relaxed second-order non-equilibrium parts
+// map back through the per-axis basis at u = 0 (collide_node): those terms
+// carry no velocity dependence and their cotangents come from lam directly.
+template <int CORR, bool RAW = false>
 __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, float fy, float fz, const Consts& k,
                                             const float (&lam)[27], float (&mu)[27], float& gfx, float& gfy,
                                             float& gfz) {
@@ -80,16 +83,19 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
   // ---------------------------------------------------------------- reverse: output tensor products
   float bux = 0.0f, buy = 0.0f, buz = 0.0f, bdrho = 0.0f;
   float bDx = 0.0f, bDy = 0.0f, bDz = 0.0f, bDxx = 0.0f, bDyy = 0.0f, bDzz = 0.0f, bDxy = 0.0f, bDxz = 0.0f, bDyz = 0.0f;
+  // second-order parts inside the basis at u (central scheme only)
+  const float Exx = RAW ? 0.0f : Dxx, Eyy = RAW ? 0.0f : Dyy, Ezz = RAW ? 0.0f : Dzz;
+  const float Exy = RAW ? 0.0f : Dxy, Exz = RAW ? 0.0f : Dxz, Eyz = RAW ? 0.0f : Dyz;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const float eE = drho * X.E[i] + rho0 * X.D[i];
     const float eW = rho0 * X.W0[i];
-    const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
-    const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
-    const float a2 = Dyy * X.A0[i];
-    const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
-    const float b1 = Dyz * X.A0[i];
-    const float c0 = Dzz * X.A0[i];
+    const float a0 = Dx * X.A1[i] + Exx * X.A2[i];
+    const float a1 = Dy * X.A0[i] + Exy * X.A1[i];
+    const float a2 = Eyy * X.A0[i];
+    const float b0 = Dz * X.A0[i] + Exz * X.A1[i];
+    const float b1 = Eyz * X.A0[i];
+    const float c0 = Ezz * X.A0[i];
     float eEb = 0.0f, a0b = 0.0f, a1b = 0.0f, a2b = 0.0f, b0b = 0.0f, b1b = 0.0f, c0b = 0.0f;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -125,20 +131,41 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
     bdrho += eEb * X.E[i];
     bux += eEb * rho * X.A1[i];
     bDx += a0b * X.A1[i];
-    bDxx += a0b * X.A2[i];
     bux += 2.0f * a0b * Dx * X.A2[i];
     bDy += a1b * X.A0[i];
-    bDxy += a1b * X.A1[i];
-    bux += a1b * (Dy * X.A1[i] + 2.0f * Dxy * X.A2[i]);
-    bDyy += a2b * X.A0[i];
-    bux += a2b * Dyy * X.A1[i];
+    bux += a1b * Dy * X.A1[i];
     bDz += b0b * X.A0[i];
-    bDxz += b0b * X.A1[i];
-    bux += b0b * (Dz * X.A1[i] + 2.0f * Dxz * X.A2[i]);
-    bDyz += b1b * X.A0[i];
-    bux += b1b * Dyz * X.A1[i];
-    bDzz += c0b * X.A0[i];
-    bux += c0b * Dzz * X.A1[i];
+    bux += b0b * Dz * X.A1[i];
+    if constexpr (!RAW) {
+      bDxx += a0b * X.A2[i];
+      bDxy += a1b * X.A1[i];
+      bux += a1b * 2.0f * Dxy * X.A2[i];
+      bDyy += a2b * X.A0[i];
+      bux += a2b * Dyy * X.A1[i];
+      bDxz += b0b * X.A1[i];
+      bux += b0b * 2.0f * Dxz * X.A2[i];
+      bDyz += b1b * X.A0[i];
+      bux += b1b * Dyz * X.A1[i];
+      bDzz += c0b * X.A0[i];
+      bux += c0b * Dzz * X.A1[i];
+    }
+  }
+  if constexpr (RAW) {
+    // second-order parts through the basis at u = 0: A0 = e_1, A1 = (-1, 0, 1)/(2c), A2 as at u
+    const float hx2 = 0.5f * k.ic[0], hy2 = 0.5f * k.ic[1], hz2 = 0.5f * k.ic[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      bDxx += lam[dir_of(i, 1, 1)] * X.A2[i];
+      bDyy += lam[dir_of(1, i, 1)] * Y.A2[i];
+      bDzz += lam[dir_of(1, 1, i)] * Z.A2[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float sgn = (float)((i - 1) * (j - 1));
+        bDxy += sgn * hx2 * hy2 * lam[dir_of(i, j, 1)];
+        bDxz += sgn * hx2 * hz2 * lam[dir_of(i, 1, j)];
+        bDyz += sgn * hy2 * hz2 * lam[dir_of(1, i, j)];
+      }
+    }
   }
   float bfx = 0.5f * bDx, bfy = 0.5f * bDy, bfz = 0.5f * bDz;
   const float bkxy = (1.0f - wn) * bDxy, bkxz = (1.0f - wn) * bDxz, bkyz = (1.0f - wn) * bDyz;
@@ -255,7 +282,7 @@ __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const 
   if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
 }
 
-template <int ST, int CORR, bool WALLS>
+template <int ST, int CORR, bool WALLS, bool RAW>
 __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
                                                       float* __restrict__ grad_force, double* __restrict__ grad_uniform,
                                                       Consts k, uint32_t bpr) {
@@ -282,7 +309,7 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
       fy = ld_off(force + k.n, node);
       fz = ld_off(force + 2 * k.n, node);
     }
-    collide_vjp<CORR>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
+    collide_vjp<CORR, RAW>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
     if constexpr (WALLS) {
       scatter_all(P.lout[0], make_coord(x, y, z, k), k, mu);
     } else {
@@ -305,6 +332,36 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
       for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) v += part[threadIdx.x][w];
       atomicAdd(&grad_uniform[threadIdx.x], v);
     }
+  }
+}
+
+// Transpose of the moving-wall terms of the forward store, -rho d_A with rho
+// the sum of the node's gathered populations: every slot the node gathered
+// gains -sum_A lam_A d_A.  A separate pass after k_step_adjoint (it touches
+// only nodes on a moving face; each slot belongs to one node, so no races),
+// which keeps the main adjoint kernel's registers unchanged.
+template <int A = 0>
+__device__ __forceinline__ void add_to_gathered(float* __restrict__ dst, const NodeCoord& c, const Consts& k, float v) {
+  dst[gather_slot<A>(c, k)] += v;
+  if constexpr (A + 1 < 27) add_to_gathered<A + 1>(dst, c, k, v);
+}
+
+__global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __restrict__ adj_in, float* __restrict__ adj_out,
+                                                             Consts k) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(node % k.nx);
+    const int64_t t = node / k.nx;
+    const int y = (int)(t % k.ny), z = (int)(t / k.ny);
+    const bool on_moving = (k.bb_x && (((k.moving & 1) && x == 0) || ((k.moving & 2) && x == k.nx - 1))) ||
+                           (k.bb_y && (((k.moving & 4) && y == 0) || ((k.moving & 8) && y == k.ny - 1))) ||
+                           (k.bb_z && (((k.moving & 16) && z == 0) || ((k.moving & 32) && z == k.nz - 1)));
+    if (!on_moving) continue;
+    float lam[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) lam[a] = adj_in[(int64_t)a * k.stride + node];
+    const float c = moving_wall_vjp(x, y, z, k, lam);
+    add_to_gathered(adj_out, make_coord(x, y, z, k), k, -c);
   }
 }
 
@@ -463,24 +520,38 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
   // 32-bit offsets need every (float) adjoint array below 4 GiB
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * 4u >= (1ull << 32);
   const dim3 grid((unsigned)nb), blk(block);
-  switch (h.p.corr * 2 + (walls ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((k_step_adjoint<ST, 0, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
-    case 1: hipLaunchKernelGGL((k_step_adjoint<ST, 0, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
-    case 2: hipLaunchKernelGGL((k_step_adjoint<ST, 1, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
-    case 3: hipLaunchKernelGGL((k_step_adjoint<ST, 1, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
-    case 4: hipLaunchKernelGGL((k_step_adjoint<ST, 2, false>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
-    default: hipLaunchKernelGGL((k_step_adjoint<ST, 2, true>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr); break;
+#define CLBM_ADJ(C, W, R)                                                                              \
+  hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr)
+#define CLBM_ADJ_CORR(W, R)                  \
+  switch (h.p.corr) {                        \
+    case 0: CLBM_ADJ(0, W, R); break;        \
+    case 1: CLBM_ADJ(1, W, R); break;        \
+    default: CLBM_ADJ(2, W, R); break;       \
   }
+  const bool raw = h.p.moments == LBM_RAW;
+  if (walls) {
+    if (raw) { CLBM_ADJ_CORR(true, true) } else { CLBM_ADJ_CORR(true, false) }
+  } else {
+    if (raw) { CLBM_ADJ_CORR(false, true) } else { CLBM_ADJ_CORR(false, false) }
+  }
+#undef CLBM_ADJ_CORR
+#undef CLBM_ADJ
   return hipGetLastError();
 }
 
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                const float* force, float* grad_force, double* grad_force_uniform, hipStream_t st) {
+  hipError_t e;
   switch (h.p.storage) {
-    case LBM_F32: return launch_step_adjoint_t<0>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
-    case LBM_F16: return launch_step_adjoint_t<1>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
-    default: return launch_step_adjoint_t<2>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st);
+    case LBM_F32: e = launch_step_adjoint_t<0>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
+    case LBM_F16: e = launch_step_adjoint_t<1>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
+    default: e = launch_step_adjoint_t<2>(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
   }
+  if (e != hipSuccess || !h.k.moving) return e;
+  int64_t g = (h.n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_moving_wall_adjoint, (unsigned)g, 256, 0, st, adj_in, adj_out, h.k);
+  return hipGetLastError();
 }
 
 hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force, const float* g_rho,

@@ -203,6 +203,40 @@ int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const 
   return LBM_OK;
 }
 
+int lbm_set_force(lbm_handle* h, const double force[3]) {
+  CHECK_HANDLE(h, "lbm_set_force");
+  if (force == nullptr) return fail(LBM_EINVAL, "lbm_set_force: NULL force");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(force[d])) return fail(LBM_EINVAL, "lbm_set_force: non-finite force");
+  for (int d = 0; d < 3; ++d) h->p.force[d] = force[d];
+  h->k.fx = (float)force[0];
+  h->k.fy = (float)force[1];
+  h->k.fz = (float)force[2];
+  return LBM_OK;
+}
+
+int lbm_step_forcing(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const double* forces,
+                     void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_step_forcing");
+  if (nsteps < 0) return fail(LBM_EINVAL, "lbm_step_forcing: nsteps < 0");
+  CHECK_REQ(state_a, "lbm_step_forcing", "state_a");
+  CHECK_REQ(state_b, "lbm_step_forcing", "state_b");
+  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step_forcing: state_a and state_b must differ");
+  if (h->p.corr == LBM_CORR_FULL)
+    return fail(LBM_EINVAL, "lbm_step_forcing: the full corrections need a density field (use lbm_step_full)");
+  if (nsteps > 0 && forces == nullptr) return fail(LBM_EINVAL, "lbm_step_forcing: NULL forces");
+  for (int64_t i = 0; i < 3 * (int64_t)nsteps; ++i)
+    if (!std::isfinite(forces[i])) return fail(LBM_EINVAL, "lbm_step_forcing: non-finite force");
+  void* bufs[2] = {state_a, state_b};
+  for (int32_t t = 0; t < nsteps; ++t) {
+    hipError_t e = clbm::launch_step_uniform(*h, bufs[t & 1], bufs[(t + 1) & 1], (float)forces[3 * t],
+                                             (float)forces[3 * t + 1], (float)forces[3 * t + 2],
+                                             (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step_forcing");
+  }
+  return LBM_OK;
+}
+
 int lbm_density(lbm_handle* h, const void* state, float* drho, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_density");
   CHECK_REQ(state, "lbm_density", "state");
@@ -282,8 +316,6 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, "lbm_step_adjoint: adj_in == adj_out");
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the full corrections");
-  if (h->k.moving) return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for moving walls");
-  if (h->p.moments == LBM_RAW) return fail(LBM_EINVAL, "lbm_step_adjoint: not implemented for the raw-moment scheme");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
                                            grad_force_uniform, (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");

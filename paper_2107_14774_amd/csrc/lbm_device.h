@@ -360,8 +360,11 @@ __device__ __forceinline__ float weq1(int e, float u, int d, const Consts& k) {
   return e == 0 ? 1.0f - q : 0.5f * q + 0.5f * (float)e * u * k.ic[d];
 }
 
-template <int A = 0>
-__device__ __forceinline__ void moving_wall_terms(int x, int y, int z, float rho, const Consts& k, float (&out)[27]) {
+// Wall coefficient of the outgoing direction A at node (x, y, z):
+// f_eq_A - f_eq_Abar per unit density at the link's wall velocity, or 0 when
+// the link does not leave through a moving face.
+template <int A>
+__device__ __forceinline__ float moving_wall_coef(int x, int y, int z, const Consts& k) {
   constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
   int cnt = 0;
   float ux = 0.0f, uy = 0.0f, uz = 0.0f;
@@ -375,14 +378,26 @@ __device__ __forceinline__ void moving_wall_terms(int x, int y, int z, float rho
   if (ex != 0 && k.bb_x && (ex > 0 ? x == k.nx - 1 : x == 0)) cross(ex > 0 ? 1 : 0);
   if (ey != 0 && k.bb_y && (ey > 0 ? y == k.ny - 1 : y == 0)) cross(ey > 0 ? 3 : 2);
   if (ez != 0 && k.bb_z && (ez > 0 ? z == k.nz - 1 : z == 0)) cross(ez > 0 ? 5 : 4);
-  if (cnt != 0) {
-    const float inv = cnt == 1 ? 1.0f : (cnt == 2 ? 0.5f : 1.0f / 3.0f);
-    ux *= inv; uy *= inv; uz *= inv;
-    const float d = weq1(ex, ux, 0, k) * weq1(ey, uy, 1, k) * weq1(ez, uz, 2, k)
-                  - weq1(-ex, ux, 0, k) * weq1(-ey, uy, 1, k) * weq1(-ez, uz, 2, k);
-    out[A] -= rho * d;
-  }
+  if (cnt == 0) return 0.0f;
+  const float inv = cnt == 1 ? 1.0f : (cnt == 2 ? 0.5f : 1.0f / 3.0f);
+  ux *= inv; uy *= inv; uz *= inv;
+  return weq1(ex, ux, 0, k) * weq1(ey, uy, 1, k) * weq1(ez, uz, 2, k)
+       - weq1(-ex, ux, 0, k) * weq1(-ey, uy, 1, k) * weq1(-ez, uz, 2, k);
+}
+
+template <int A = 0>
+__device__ __forceinline__ void moving_wall_terms(int x, int y, int z, float rho, const Consts& k, float (&out)[27]) {
+  out[A] -= rho * moving_wall_coef<A>(x, y, z, k);
   if constexpr (A + 1 < 27) moving_wall_terms<A + 1>(x, y, z, rho, k, out);
+}
+
+// Transpose of moving_wall_terms: the wall terms are -rho d_A with rho the sum of
+// the gathered populations, so every population's cotangent gains -sum_A lam_A d_A.
+template <int A = 0>
+__device__ __forceinline__ float moving_wall_vjp(int x, int y, int z, const Consts& k, const float (&lam)[27]) {
+  const float c = lam[A] * moving_wall_coef<A>(x, y, z, k);
+  if constexpr (A + 1 < 27) return c + moving_wall_vjp<A + 1>(x, y, z, k, lam);
+  return c;
 }
 
 // Exact local conservation for FP32 storage.  In exact arithmetic the

@@ -336,6 +336,15 @@ hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const fl
   }
 }
 
+hipError_t launch_step_uniform(const lbm_handle& h, const void* src, void* dst, float fx, float fy, float fz,
+                               hipStream_t st) {
+  lbm_handle hv = h;  // host copy: the constants travel by value in the kernel arguments
+  hv.k.fx = fx;
+  hv.k.fy = fy;
+  hv.k.fz = fz;
+  return launch_step(hv, src, dst, nullptr, nullptr, nullptr, st);
+}
+
 hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
   switch (h.p.storage) {
     case LBM_F32: return launch_density_t<0>(h, src, drho, st);

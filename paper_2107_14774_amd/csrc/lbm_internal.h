@@ -22,6 +22,9 @@ namespace clbm {
 
 hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force,
                        const float* grad_src, float* drho_out, hipStream_t st);
+// Same with the uniform force replaced for this launch only.
+hipError_t launch_step_uniform(const lbm_handle& h, const void* src, void* dst, float fx, float fy, float fz,
+                               hipStream_t st);
 hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
 hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
                        const double* perturb, hipStream_t st);

@@ -122,6 +122,23 @@ def lbm_step(h, nsteps, state_a, state_b, force=None, stream=None):
                                     _lib.stream_ptr(stream)))
 
 
+def lbm_set_force(h, force):
+    arr = (_lib.ctypes.c_double * 3)(*(float(v) for v in force))
+    _lib.check(_lib.load().lbm_set_force(h.raw, arr))
+
+
+def lbm_step_forcing(h, nsteps, state_a, state_b, forces, stream=None):
+    """``forces``: host sequence or array of nsteps uniform forces (nsteps x 3)."""
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(forces, dtype=np.float64).reshape(-1))
+    if arr.size != 3 * int(nsteps):
+        raise ValueError(f"forces: need {nsteps} x 3 values, got {arr.size}")
+    ptr = arr.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_double))
+    _lib.check(_lib.load().lbm_step_forcing(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
+                                            _lib.ptr(_state(h, state_b, "state_b")), ptr,
+                                            _lib.stream_ptr(stream)))
+
+
 def lbm_density(h, state, drho, stream=None):
     _require(drho, _ABI_F32, h.n, "drho")
     _lib.check(_lib.load().lbm_density(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(drho), _lib.stream_ptr(stream)))
@@ -264,6 +281,15 @@ class Lattice:
         if nsteps % 2 == 0 or mode == "exact":
             return ((a, b) if nsteps % 2 == 0 else (b, a)) + (drho_a, drho_b)
         return b, a, drho_b, drho_a
+
+    def step_forcing(self, a, b, forces):
+        """Advance len(forces) steps, step t under the uniform force forces[t]; returns (current, scratch)."""
+        n = len(forces)
+        lbm_step_forcing(self.h, n, a, b, forces)
+        return (a, b) if n % 2 == 0 else (b, a)
+
+    def set_force(self, force):
+        lbm_set_force(self.h, force)
 
     def density(self, state):
         """rho - rho0 (FP32 field) of a state."""

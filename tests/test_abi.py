@@ -107,7 +107,7 @@ def test_full_corrections_need_the_density_field_entry_point():
 def test_adjoint_rejects_what_it_does_not_differentiate():
     lib = _lib.load()
     a, b, c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
-    for kw in (dict(moments="raw"), dict(bc_y="bounceback", wall_velocity=[(0, 0, 0)] * 3 + [(0.1, 0, 0)] + [(0, 0, 0)] * 2)):
+    for kw in (dict(corr="full"),):
         h = P.lbm_create(4, 4, 4, **kw)
         assert lib.lbm_step_adjoint(h.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
     prm = _lib.LbmParams()
@@ -117,3 +117,17 @@ def test_adjoint_rejects_what_it_does_not_differentiate():
     raw = ctypes.c_void_p()
     assert lib.lbm_create(ctypes.byref(prm), ctypes.byref(raw)) == _lib.LBM_EINVAL
     assert b"moment basis" in lib.lbm_last_error()
+
+
+def test_set_force_and_step_forcing_validate_on_the_host():
+    lib = _lib.load()
+    h = P.lbm_create(4, 4, 4)
+    bad = (ctypes.c_double * 3)(0.0, float("nan"), 0.0)
+    assert lib.lbm_set_force(h.raw, bad) == _lib.LBM_EINVAL
+    good = (ctypes.c_double * 3)(1e-5, 0.0, 0.0)
+    assert lib.lbm_set_force(h.raw, good) == _lib.LBM_OK
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    assert lib.lbm_step_forcing(h.raw, 2, a, b, None, None) == _lib.LBM_EINVAL
+    f = (ctypes.c_double * 6)(0, 0, 0, float("inf"), 0, 0)
+    assert lib.lbm_step_forcing(h.raw, 2, a, b, f, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_forcing(h.raw, 0, a, b, None, None) == _lib.LBM_OK

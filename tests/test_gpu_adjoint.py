@@ -31,6 +31,12 @@ ADJ_CASES = [
     ("aniso_lowmach", (16, 9, 12), 0.5, 0.25, "periodic", "bounceback", "lowmach"),
     ("walls_off", (12, 7, 6), 0.8, 1.2, "bounceback", "periodic", "off"),
     ("x_walls_local", (11, 6, 5), 0.5, 1.0, "bounceback", "bounceback", "local", "bounceback"),
+    ("cavity_moving_faces", (9, 8, 7), 0.5, 1.0, "bounceback", "bounceback", "local", "bounceback",
+     ((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0.02), (0.03, 0.01, 0), (0, 0, 0))),
+    ("raw_periodic_local", (70, 5, 4), 1.0, 0.5, "periodic", "periodic", "local", "periodic",
+     ((0, 0, 0),) * 6, "raw"),
+    ("raw_duct_lowmach", (13, 9, 8), 0.5, 0.25, "bounceback", "bounceback", "lowmach", "periodic",
+     ((0, 0, 0),) * 6, "raw"),
 ]
 
 
@@ -38,8 +44,11 @@ ADJ_CASES = [
 def test_step_adjoint_matches_oracle_vjp(case):
     name, (nx, ny, nz), r, s, by, bz, corr = case[:7]
     bx = case[7] if len(case) > 7 else "periodic"
+    wv = case[8] if len(case) > 8 else ((0, 0, 0),) * 6
+    moments = case[9] if len(case) > 9 else "central"
     _say("case", name)
-    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_y=by, bc_z=bz, bc_x=bx)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_y=by, bc_z=bz, bc_x=bx,
+                      wall_velocity=wv, moments=moments)
     f0 = fp32_rounded_state(random_state(p, 21), p)
     g = np.random.Generator(np.random.PCG64(22))
     force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32)
