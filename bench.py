@@ -252,7 +252,7 @@ def cpu_baseline(w):
 PROFILE_KERNELS = {
     "f32": "k_step<0, 2, false, false>", "f16": "k_step<1, 2, false, false>", "bf16": "k_step<2, 2, false, false>",
     "full_f32": "k_step<0, 3, false, false>", "full_f16": "k_step<1, 3, false, false>",
-    "adjoint_f32": "k_step_adjoint<0, 2, true>", "adjoint_f16": "k_step_adjoint<1, 2, false>",
+    "adjoint_f32": "k_step_adjoint<0, 2, 1, false>", "adjoint_f16": "k_step_adjoint<1, 2, 0, false>",
 }
 PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),

@@ -253,11 +253,11 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
 }
 
 // ------------------------------------------------------------------ adjoint step
-template <int A = 0>
+template <bool WX, int A = 0>
 __device__ __forceinline__ void scatter_all(float* __restrict__ dst, const NodeCoord& c, const Consts& k,
                                             const float (&mu)[27]) {
-  dst[gather_slot<A>(c, k)] = mu[A];
-  if constexpr (A + 1 < 27) scatter_all<A + 1>(dst, c, k, mu);
+  dst[gather_slot<A, WX>(c, k)] = mu[A];
+  if constexpr (A + 1 < 27) scatter_all<WX, A + 1>(dst, c, k, mu);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -282,7 +282,8 @@ __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const 
   if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
 }
 
-template <int ST, int CORR, bool WALLS, bool RAW>
+// WALLS: 0 periodic (fast addressing), 1 walls on y and z only, 2 walls on any axis.
+template <int ST, int CORR, int WALLS, bool RAW>
 __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
                                                       float* __restrict__ grad_force, double* __restrict__ grad_uniform,
                                                       Consts k, uint32_t bpr) {
@@ -295,8 +296,8 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
     const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
     float df[27], lam[27], mu[27];
     PeriodicRows pr;
-    if constexpr (WALLS) {
-      gather_all<ST>(P.state[0], make_coord(x, y, z, k), k, df);
+    if constexpr (WALLS != 0) {
+      gather_all<ST, 0, WALLS == 2>(P.state[0], make_coord(x, y, z, k), k, df);
     } else {
       periodic_rows(x, y, z, k, pr);
       gather_periodic<ST>(P.state, pr, k, df);
@@ -310,8 +311,8 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
       fz = ld_off(force + 2 * k.n, node);
     }
     collide_vjp<CORR, RAW>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
-    if constexpr (WALLS) {
-      scatter_all(P.lout[0], make_coord(x, y, z, k), k, mu);
+    if constexpr (WALLS != 0) {
+      scatter_all<WALLS == 2>(P.lout[0], make_coord(x, y, z, k), k, mu);
     } else {
       scatter_periodic(P.lout, pr, mu);
     }
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(256) void k_moments_adjoint(const typename Store<ST
       if (kEz[a] != 0) v += kEz[a] * bj[2];
       mu[a] = v;
     }
-    scatter_all(adj, c, k, mu);
+    scatter_all<true>(adj, c, k, mu);
     if (grad_force != nullptr) {
       grad_force[node] += 0.5f * gx * irho;
       grad_force[k.n + node] += 0.5f * gy * irho;
@@ -529,10 +530,12 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
     default: CLBM_ADJ(2, W, R); break;       \
   }
   const bool raw = h.p.moments == LBM_RAW;
-  if (walls) {
-    if (raw) { CLBM_ADJ_CORR(true, true) } else { CLBM_ADJ_CORR(true, false) }
+  if (walls && h.k.bb_x) {
+    if (raw) { CLBM_ADJ_CORR(2, true) } else { CLBM_ADJ_CORR(2, false) }
+  } else if (walls) {
+    if (raw) { CLBM_ADJ_CORR(1, true) } else { CLBM_ADJ_CORR(1, false) }
   } else {
-    if (raw) { CLBM_ADJ_CORR(false, true) } else { CLBM_ADJ_CORR(false, false) }
+    if (raw) { CLBM_ADJ_CORR(0, true) } else { CLBM_ADJ_CORR(0, false) }
   }
 #undef CLBM_ADJ_CORR
 #undef CLBM_ADJ

@@ -109,6 +109,13 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   k.bb_y = q.bc_y == LBM_BOUNCEBACK;
   k.bb_z = q.bc_z == LBM_BOUNCEBACK;
   k.moving = moving;
+  k.ytile = 1;
+  for (int t : {32, 16, 8, 4, 2})
+    if (q.ny % t == 0) { k.ytile = t; break; }
+  if (const char* env = std::getenv("LBM_FULL_YTILE")) {  // tuning: any divisor of ny (ny = plain row order)
+    const int t = std::atoi(env);
+    if (t >= 1 && q.ny % t == 0) k.ytile = t;
+  }
   for (int f = 0; f < 6; ++f)
     for (int c = 0; c < 3; ++c) k.wall_u[f][c] = (float)q.wall_velocity[f][c];
   k.stride = h->stride;

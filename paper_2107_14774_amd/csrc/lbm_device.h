@@ -39,6 +39,7 @@ struct Consts {
   int nx, ny, nz;
   int bb_x, bb_y, bb_z;    // 1 = halfway bounce-back walls on that axis
   int moving;              // bit f set = face f moves (momentum-augmented bounce-back)
+  int ytile;               // rows per y-tile of the full-correction step's row order (divides ny)
   float wall_u[6][3];      // face velocities, faces x-, x+, y-, y+, z-, z+
   int64_t stride;          // elements between direction arrays
   int64_t n;               // nodes
@@ -103,7 +104,8 @@ __device__ __forceinline__ NodeCoord make_coord(int x, int y, int z, const Const
 }
 
 // Slot from which the node gathers f_a: (a, x - ebar_a) or, across a wall, (opp(a), x).
-template <int A>
+// WX = false compiles the x-wall test away (for callers that know x is periodic).
+template <int A, bool WX = true>
 __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts& k) {
   constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
   constexpr int opp = opposite_of(A);
@@ -111,7 +113,7 @@ __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts&
   const int ys = ey == 0 ? c.y : (ey > 0 ? c.ym : c.yp);
   const int zs = ez == 0 ? c.z : (ez > 0 ? c.zm : c.zp);
   bool wall = false;
-  if (ex != 0) wall |= k.bb_x && (ex > 0 ? c.x == 0 : c.x == k.nx - 1);
+  if (WX && ex != 0) wall |= k.bb_x && (ex > 0 ? c.x == 0 : c.x == k.nx - 1);
   if (ey != 0) wall |= k.bb_y && (ey > 0 ? c.y == 0 : c.y == k.ny - 1);
   if (ez != 0) wall |= k.bb_z && (ez > 0 ? c.z == 0 : c.z == k.nz - 1);
   const int64_t node = ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;
@@ -119,18 +121,18 @@ __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts&
   return wall ? (int64_t)opp * k.stride + node : (int64_t)A * k.stride + src;
 }
 
-template <int A, int ST>
+template <int A, int ST, bool WX = true>
 __device__ __forceinline__ float gather_dev(const typename Store<ST>::T* __restrict__ src,
                                             const NodeCoord& c, const Consts& k) {
-  const float v = Store<ST>::load(src + gather_slot<A>(c, k));
+  const float v = Store<ST>::load(src + gather_slot<A, WX>(c, k));
   return ST == 0 ? v : v * k.inv_sigma[A];
 }
 
-template <int ST, int A = 0>
+template <int ST, int A = 0, bool WX = true>
 __device__ __forceinline__ void gather_all(const typename Store<ST>::T* __restrict__ src,
                                            const NodeCoord& c, const Consts& k, float (&df)[27]) {
-  df[A] = gather_dev<A, ST>(src, c, k);
-  if constexpr (A + 1 < 27) gather_all<ST, A + 1>(src, c, k, df);
+  df[A] = gather_dev<A, ST, WX>(src, c, k);
+  if constexpr (A + 1 < 27) gather_all<ST, A + 1, WX>(src, c, k, df);
 }
 
 // ----------------------------------------------------------------- moments

@@ -51,7 +51,18 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
                                               Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  int y, z;
+  if constexpr (CORR == 3) {
+    // rows in y-tiles of k.ytile, z-major inside a tile: the density rows of z - 1 and
+    // z + 1 are then read a few rows apart (an L2 hit) instead of a whole plane apart
+    const uint32_t ty = (uint32_t)k.ytile, per_tile = ty * (uint32_t)k.nz;
+    const uint32_t tile = rowid / per_tile, rem = rowid % per_tile;
+    z = (int)(rem / ty);
+    y = (int)(tile * ty + rem % ty);
+  } else {
+    y = (int)(rowid % (uint32_t)k.ny);
+    z = (int)(rowid / (uint32_t)k.ny);
+  }
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   // the density gradient first (block-wide, with a barrier), while no population is live
   float grx = 0.0f, gry = 0.0f, grz = 0.0f;
