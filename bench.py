@@ -260,11 +260,12 @@ PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "full_f16": (512, 512, 256, "512x512x256"), "adjoint_f32": (128, 128, 64, "128x128x64 duct"),
     "adjoint_f16": (384, 384, 192, "384x384x192"),
 }
-TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof_step -o step --output-format csv -- "
+# $OUT is any output directory (the three runs write their CSVs under it)
+TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_step -o step --output-format csv -- "
              "python3 bench.py --steps 30 --warmup 5 --no-cpu-baseline")
-PMC_CMD = ("timeout -s KILL 240 rocprofv3 --pmc {c} -d gpurun_out/pmc_{d} -o {d} --output-format csv -- "
+PMC_CMD = ("timeout -s KILL 240 rocprofv3 --pmc {c} -d $OUT/pmc_{d} -o {d} --output-format csv -- "
            "python3 bench.py --steps 4 --warmup 1 --no-cpu-baseline")
-SUMMARY_CMD = "python3 bench.py --summarize-rocprof gpurun_out"
+SUMMARY_CMD = "python3 bench.py --summarize-rocprof $OUT"
 TRACE_SUMMARY = "profiles/k_step_and_adjoint_kernel_trace.txt"
 TRAFFIC_SUMMARY = "profiles/k_step_and_adjoint_hbm_traffic.txt"
 
@@ -288,7 +289,8 @@ def summarize_rocprof(out_dir):
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
              "# corrections) and its adjoint (128x128x64 duct with force field; 384x384x192, r=1/2, s=1/4, FP16)",
-             "", "commands (repo root, one MI355X, TMPDIR=/tmp):", "  " + TRACE_CMD, "  " + SUMMARY_CMD, "",
+             "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):", "  " + TRACE_CMD,
+             "  " + SUMMARY_CMD, "",
              "kernel                         variant      workload         calls  avg_ms   min_ms   max_ms   "
              "MLUPS(avg)  alg_B/LUP  alg_GB/s  frac_of_8TB/s"]
     for v, key in PROFILE_KERNELS.items():
@@ -317,7 +319,7 @@ def summarize_rocprof(out_dir):
     kf = (copy_bytes / 1024) / statistics.mean(cf)
     kw = (copy_bytes / 1024) / statistics.mean(cw)
     lines = ["# HBM traffic of the step kernels (512x512x256, r=1, s=1/2) and the adjoint from rocprofv3 counters",
-             "", "commands (repo root, one MI355X, TMPDIR=/tmp), one counter per pass:",
+             "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory), one counter per pass:",
              "  " + PMC_CMD.format(c="FETCH_SIZE", d="fetch"), "  " + PMC_CMD.format(c="WRITE_SIZE", d="write"),
              "  " + SUMMARY_CMD, "",
              "calibration: the 4 GiB device-to-device copy in the same runs (hipMemcpy kernel __amd_rocclr_copyBuffer,",
