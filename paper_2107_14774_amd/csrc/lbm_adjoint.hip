@@ -275,6 +275,13 @@ struct AdjPtrs {
 };
 
 template <int A = 0>
+__device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const PeriodicRows& pr, uint32_t node,
+                                                const WallFlags& w, const Consts& k, const float (&mu)[27]) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (uint32_t)(wall_slot32<A>(pr, node, w, k) * 4u)) = mu[A];
+  if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, pr, node, w, k, mu);
+}
+
+template <int A = 0>
 __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const PeriodicRows& pr,
                                                  const float (&mu)[27]) {
   // plain stores: the shifted scatter writes partial lines that L2 merges with the neighbours'
@@ -282,7 +289,8 @@ __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const 
   if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
 }
 
-// WALLS: 0 periodic (fast addressing), 1 walls on y and z only, 2 walls on any axis.
+// WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit offsets
+// across the whole state and adjoint (both below 4 GiB), 2 walls with 64-bit slots.
 template <int ST, int CORR, int WALLS, bool RAW>
 __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
                                                       float* __restrict__ grad_force, double* __restrict__ grad_uniform,
@@ -296,11 +304,17 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
     const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
     float df[27], lam[27], mu[27];
     PeriodicRows pr;
-    if constexpr (WALLS != 0) {
-      gather_all<ST, 0, WALLS == 2>(P.state[0], make_coord(x, y, z, k), k, df);
+    WallFlags w;
+    if constexpr (WALLS == 2) {
+      gather_all<ST>(P.state[0], make_coord(x, y, z, k), k, df);
     } else {
       periodic_rows(x, y, z, k, pr);
-      gather_periodic<ST>(P.state, pr, k, df);
+      if constexpr (WALLS == 1) {
+        w = wall_flags(x, y, z, k);
+        gather_walls32<ST>(P.state[0], pr, node, w, k, df);
+      } else {
+        gather_periodic<ST>(P.state, pr, k, df);
+      }
     }
 #pragma unroll
     for (int a = 0; a < 27; ++a) lam[a] = ld_off(P.lin[a], node);
@@ -311,8 +325,10 @@ __global__ __launch_bounds__(256, ST == 0 ? 1 : LBM_ADJ_WAVES_16) void k_step_ad
       fz = ld_off(force + 2 * k.n, node);
     }
     collide_vjp<CORR, RAW>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
-    if constexpr (WALLS != 0) {
-      scatter_all<WALLS == 2>(P.lout[0], make_coord(x, y, z, k), k, mu);
+    if constexpr (WALLS == 2) {
+      scatter_all<true>(P.lout[0], make_coord(x, y, z, k), k, mu);
+    } else if constexpr (WALLS == 1) {
+      scatter_walls32(P.lout[0], pr, node, w, k, mu);
     } else {
       scatter_periodic(P.lout, pr, mu);
     }
@@ -518,8 +534,11 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
     P.lin[a] = adj_in + (int64_t)a * h.stride;
     P.lout[a] = adj_out + (int64_t)a * h.stride;
   }
-  // 32-bit offsets need every (float) adjoint array below 4 GiB
-  const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * 4u >= (1ull << 32);
+  // 32-bit offsets: per direction array (periodic) or across all 27 (walls), for the
+  // state and the float adjoint arrays alike
+  const bool any_wall = h.k.bb_x || h.k.bb_y || h.k.bb_z;
+  const int kind = (!any_wall && (uint64_t)h.stride * 4u < (1ull << 32)) ? 0
+                   : (27ull * (uint64_t)h.stride * 4u < (1ull << 32) ? 1 : 2);
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_ADJ(C, W, R)                                                                              \
   hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr)
@@ -530,9 +549,9 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
     default: CLBM_ADJ(2, W, R); break;       \
   }
   const bool raw = h.p.moments == LBM_RAW;
-  if (walls && h.k.bb_x) {
+  if (kind == 2) {
     if (raw) { CLBM_ADJ_CORR(2, true) } else { CLBM_ADJ_CORR(2, false) }
-  } else if (walls) {
+  } else if (kind == 1) {
     if (raw) { CLBM_ADJ_CORR(1, true) } else { CLBM_ADJ_CORR(1, false) }
   } else {
     if (raw) { CLBM_ADJ_CORR(0, true) } else { CLBM_ADJ_CORR(0, false) }

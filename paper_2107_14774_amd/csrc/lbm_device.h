@@ -587,6 +587,49 @@ __device__ __forceinline__ uint32_t periodic_src(const PeriodicRows& pr) {
   return pr.row[kEy[A] + 1][kEz[A] + 1] + pr.xs[kEx[A] + 1];
 }
 
+// Walls with 32-bit offsets (the whole state below 4 GiB): the slot of f_A is
+// (A, x - ebar_A) from the periodic row offsets, or (opp(A), x) across a wall,
+// written as one 32-bit element offset from direction 0's array; a wall costs
+// a compare and a select instead of 64-bit index arithmetic.
+struct WallFlags {
+  bool lx, hx, ly, hy, lz, hz;  // upstream node beyond the wall at the low / high end of an axis
+};
+
+__device__ __forceinline__ WallFlags wall_flags(int x, int y, int z, const Consts& k) {
+  WallFlags w;
+  w.lx = k.bb_x && x == 0;
+  w.hx = k.bb_x && x == k.nx - 1;
+  w.ly = k.bb_y && y == 0;
+  w.hy = k.bb_y && y == k.ny - 1;
+  w.lz = k.bb_z && z == 0;
+  w.hz = k.bb_z && z == k.nz - 1;
+  return w;
+}
+
+template <int A>
+__device__ __forceinline__ uint32_t wall_slot32(const PeriodicRows& pr, uint32_t node, const WallFlags& w,
+                                                const Consts& k) {
+  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
+  constexpr int opp = opposite_of(A);
+  bool wall = false;
+  if (ex > 0) wall |= w.lx;
+  if (ex < 0) wall |= w.hx;
+  if (ey > 0) wall |= w.ly;
+  if (ey < 0) wall |= w.hy;
+  if (ez > 0) wall |= w.lz;
+  if (ez < 0) wall |= w.hz;
+  const uint32_t stride = (uint32_t)k.stride;
+  return wall ? (uint32_t)opp * stride + node : (uint32_t)A * stride + periodic_src<A>(pr);
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const PeriodicRows& pr,
+                                               uint32_t node, const WallFlags& w, const Consts& k, float (&df)[27]) {
+  const float v = Store<ST>::load_val(ld_off(base, wall_slot32<A>(pr, node, w, k)));
+  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
+  if constexpr (A + 1 < 27) gather_walls32<ST, A + 1>(base, pr, node, w, k, df);
+}
+
 template <int ST, int A = 0>
 __device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* const (&src)[27], const PeriodicRows& pr,
                                                 const Consts& k, float (&df)[27]) {

@@ -14,15 +14,22 @@ namespace clbm {
 // With the full corrections (CORR 3) the density gradient comes from the
 // density-deviation field grad_src, and drho_out (if not NULL) receives the
 // node's own density deviation.
-template <int ST, bool WALLS>
+// WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
+// offsets from direction 0's array (state below 4 GiB), 2 walls, 64-bit slots.
+template <int ST, int WALLS>
 __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
                                             const Consts& k, float (&df)[27]) {
-  if constexpr (WALLS) {
+  if constexpr (WALLS == 2) {
     gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
   } else {
     PeriodicRows pr;
     periodic_rows(x, y, z, k, pr);
-    gather_periodic<ST>(P.src, pr, k, df);
+    if constexpr (WALLS == 1) {
+      const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+      gather_walls32<ST>(P.src[0], pr, node, wall_flags(x, y, z, k), k, df);
+    } else {
+      gather_periodic<ST>(P.src, pr, k, df);
+    }
   }
 }
 
@@ -44,7 +51,7 @@ constexpr int step_waves(int st, int corr) {
                    : (st == 0 ? LBM_STEP_WAVES_F32 : LBM_STEP_WAVES_F16);
 }
 
-template <int ST, int CORR, bool WALLS, bool RAW>
+template <int ST, int CORR, int WALLS, bool RAW>
 __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<typename Store<ST>::T> P,
                                               const float* __restrict__ force,
                                               const float* __restrict__ grad_src, float* __restrict__ drho_out,
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
     collide_node<CORR, RAW>(df, fx, fy, fz, k, out);
   }
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
-  if constexpr (WALLS) {
+  if constexpr (WALLS != 0) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
 #pragma unroll
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
 
 // Density deviation of every node of a state: the same gather and the same
 // FP32 sum as the step, so the value is bit-identical to the step's.
-template <int ST, bool WALLS>
+template <int ST, int WALLS>
 __global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> P, float* __restrict__ drho,
                                                  Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -271,9 +278,13 @@ __global__ __launch_bounds__(256) void k_moments(const typename Store<ST>::T* __
 }
 
 // ------------------------------------------------------------------ launchers
-// The 32-bit addressing of the periodic path needs every byte offset below 4 GiB.
-static bool use_general_gather(const lbm_handle& h) {
-  return h.k.bb_x || h.k.bb_y || h.k.bb_z || (uint64_t)h.stride * h.elem >= (1ull << 32);
+// Gather path: 0 periodic (32-bit offsets per direction array), 1 walls with
+// 32-bit offsets across the whole state, 2 walls with 64-bit slots.
+static int gather_kind(const lbm_handle& h) {
+  const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
+  if (!walls && (uint64_t)h.stride * h.elem < (1ull << 32)) return 0;
+  if (27ull * (uint64_t)h.stride * h.elem < (1ull << 32)) return 1;
+  return 2;
 }
 
 static int grid_for(int64_t n, int block, int64_t cap) {
@@ -296,7 +307,7 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
     P.src[a] = (const T*)src + (int64_t)a * h.stride;
     P.dst[a] = (T*)dst + (int64_t)a * h.stride;
   }
-  const bool walls = use_general_gather(h);
+  const int kind = gather_kind(h);
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_STEP(C, W, R) \
   hipLaunchKernelGGL((k_step<ST, C, W, R>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
@@ -307,12 +318,16 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
     case 2: CLBM_STEP(2, W, R); break;         \
     default: CLBM_STEP(3, W, R); break;        \
   }
-  const bool raw = h.p.moments == LBM_RAW;
-  if (walls) {
-    if (raw) { CLBM_STEP_CORR(true, true) } else { CLBM_STEP_CORR(true, false) }
+#define CLBM_STEP_RAW(W)                                           \
+  if (h.p.moments == LBM_RAW) { CLBM_STEP_CORR(W, true) } else { CLBM_STEP_CORR(W, false) }
+  if (kind == 0) {
+    CLBM_STEP_RAW(0)
+  } else if (kind == 1) {
+    CLBM_STEP_RAW(1)
   } else {
-    if (raw) { CLBM_STEP_CORR(false, true) } else { CLBM_STEP_CORR(false, false) }
+    CLBM_STEP_RAW(2)
   }
+#undef CLBM_STEP_RAW
 #undef CLBM_STEP_CORR
 #undef CLBM_STEP
   return hipGetLastError();
@@ -331,10 +346,11 @@ static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* 
     P.dst[a] = nullptr;
   }
   const dim3 grid((unsigned)nb), blk(block);
-  if (use_general_gather(h))
-    hipLaunchKernelGGL((k_density<ST, true>), grid, blk, 0, st, P, drho, h.k, bpr);
-  else
-    hipLaunchKernelGGL((k_density<ST, false>), grid, blk, 0, st, P, drho, h.k, bpr);
+  switch (gather_kind(h)) {
+    case 0: hipLaunchKernelGGL((k_density<ST, 0>), grid, blk, 0, st, P, drho, h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_density<ST, 1>), grid, blk, 0, st, P, drho, h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_density<ST, 2>), grid, blk, 0, st, P, drho, h.k, bpr); break;
+  }
   return hipGetLastError();
 }
 
