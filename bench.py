@@ -44,6 +44,9 @@ BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108,
                  # exact density gradient: + a density pass (one more state read, one field write)
                  "full_f32_exact": 216 + 4 + 108 + 4}
 FULL_VARIANTS = {"full_f32": ("f32", "lagged"), "full_f16": ("f16", "lagged"), "full_f32_exact": ("f32", "exact")}
+# in-place AA layout (one buffer): same bytes per update, half the memory
+AA_VARIANTS = {"aa_f32": "f32", "aa_f16": "f16"}
+BYTES_PER_LUP.update({"aa_f32": 216, "aa_f16": 108})
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
 ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
 KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip",
@@ -97,24 +100,28 @@ def time_steps(lat, a, b, steps, warmup, force=None, full_mode=None):
     t0 = time.perf_counter()
     ev0.record(stream)
     if full_mode is None:
-        P.lbm_step(lat.h, steps, a, b, force, stream=stream)
+        P.lbm_step(lat.h, steps, a, None if lat.aa else b, force, stream=stream)
     else:
         P.lbm_step_full(lat.h, steps, a, b, da, db, full_mode, force, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    if steps % 2:
+    if steps % 2 and not lat.aa:
         a, b = b, a
     return wall, ev0.elapsed_time(ev1) / steps, a, b
 
 
 def run_forward(w, variant, steps, warmup, u0_dev):
     import paper_2107_14774_amd as P
-    storage, mode = FULL_VARIANTS.get(variant, (variant, None))
+    storage, mode = FULL_VARIANTS.get(variant, (AA_VARIANTS.get(variant, variant), None))
+    layout = "aa" if variant in AA_VARIANTS else "ab"
+    if layout == "aa":  # the in-place layout advances in pairs of steps
+        steps += steps % 2
+        warmup += warmup % 2
     on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
     lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
-                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local" if mode is None else "full")
-    a, b = lat.new_state(), lat.new_state()
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local" if mode is None else "full", layout=layout)
+    a, b = lat.new_state(), (None if layout == "aa" else lat.new_state())
     lat.init(a, u=u0_dev)
     torch.cuda.synchronize()
     log(f"[bench] {variant}: {w.nx}x{w.ny}x{w.nz}, state {lat.h.state_bytes / 2**30:.2f} GiB, "
@@ -357,7 +364,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--variants", default="f32,f16,bf16,full_f32,full_f16,adjoint_f32,adjoint_f16")
+    ap.add_argument("--variants", default="f32,f16,bf16,full_f32,full_f16,aa_f32,aa_f16,adjoint_f32,adjoint_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 CSVs under DIR (no GPU needed)")
@@ -411,7 +418,7 @@ def main():
                            "bytes_per_lup": BYTES_PER_LUP[v], "measured_bytes_per_launch": measured_traffic(v)}
     variants_out.update(adj)
     if "f32" in res:
-        for v in ("f16", "bf16", "full_f32", "full_f16", "full_f32_exact"):
+        for v in ("f16", "bf16", "full_f32", "full_f16", "full_f32_exact", "aa_f32", "aa_f16"):
             if v in res:
                 variants_out[v]["speedup_vs_f32"] = round(res[v]["mlups"] / res["f32"]["mlups"], 3)
 

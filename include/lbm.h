@@ -84,6 +84,22 @@ enum lbm_corr { LBM_CORR_OFF = 0, LBM_CORR_LOWMACH = 1, LBM_CORR_LOCAL = 2, LBM_
  * non-equilibrium moments. */
 enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
 
+/* Memory layout of a state.
+ * AB: two buffers; a step gathers from one and writes the other (pull), and
+ *     the state holds post-collision populations placed where the next step
+ *     gathers them (lbm_step's state_a / state_b).
+ * AA: one buffer updated in place, half the memory.  Steps alternate between
+ *     a local one (read the node's own slots, write the collided populations
+ *     to the opposite-direction slots of the same node) and a shifted one
+ *     (read the neighbours' opposite-direction slots, write to the
+ *     neighbours' own slots); each slot is read and written by one node only.
+ *     Between calls the state holds the post-stream populations in natural
+ *     order (slot (a, x) = f_a(x, t)), so every step call must advance an even
+ *     number of steps.  Forward steps only: lbm_step, lbm_step_forcing (not
+ *     the full corrections, not the adjoint).  With walls the whole state
+ *     must stay below 4 GiB (32-bit offsets; LBM_EINVAL from lbm_create). */
+enum lbm_layout { LBM_LAYOUT_AB = 0, LBM_LAYOUT_AA = 1 };
+
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
 enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1 };
 
@@ -110,6 +126,7 @@ typedef struct lbm_params {
   int32_t storage;      /* enum lbm_storage */
   int32_t corr;         /* enum lbm_corr */
   int32_t moments;      /* enum lbm_moments_basis */
+  int32_t layout;       /* enum lbm_layout */
   double rho0;          /* reference density of the stored deviations, > 0 (usually 1) */
   double force[3];      /* uniform body force used when no force field is passed */
   double wall_velocity[6][3]; /* velocity of each face (x-, x+, y-, y+, z-, z+); must be
@@ -155,7 +172,9 @@ int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream);
 /* Advance nsteps >= 0 collide-and-stream steps (Sec. 3.2).  The current state
  * is in state_a on entry; state_b is scratch of the same size (must differ
  * from state_a).  On return the current state is in state_a when nsteps is
- * even and in state_b when it is odd.
+ * even and in state_b when it is odd.  AA layout: state_b is not used (NULL
+ * or equal to state_a), nsteps must be even (LBM_EINVAL otherwise) and the
+ * state stays in state_a.
  *   force: device float[3][n_nodes] per-node body force, or NULL to use
  *          p->force for every node. */
 int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
@@ -239,7 +258,8 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
  * Moving walls (their terms depend on the node's density) and the raw-moment
- * scheme are included.  Not implemented for the full corrections (LBM_EINVAL). */
+ * scheme are included.  Not implemented for the full corrections or the AA
+ * layout (LBM_EINVAL; also for the other adjoint entry points below). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);

@@ -18,6 +18,7 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CORR = {"off": 0, "lowmach": 1, "local": 2, "full": 3}
 GRAD_MODE = {"exact": 0, "lagged": 1}
 MOMENTS = {"central": 0, "raw": 1}
+LAYOUT = {"ab": 0, "aa": 1}
 
 
 class LbmParams(ctypes.Structure):
@@ -27,6 +28,7 @@ class LbmParams(ctypes.Structure):
         ("omega_nu", ctypes.c_double), ("omega_xi", ctypes.c_double), ("omega_hi", ctypes.c_double),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("corr", ctypes.c_int32), ("moments", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
         ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
         ("wall_velocity", (ctypes.c_double * 3) * 6),
     ]

@@ -75,6 +75,9 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
   if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
   if (q.moments != LBM_CENTRAL && q.moments != LBM_RAW) return fail(LBM_EINVAL, "lbm_create: unknown moment basis");
+  if (q.layout != LBM_LAYOUT_AB && q.layout != LBM_LAYOUT_AA) return fail(LBM_EINVAL, "lbm_create: unknown layout");
+  if (q.layout == LBM_LAYOUT_AA && q.corr == LBM_CORR_FULL)
+    return fail(LBM_EINVAL, "lbm_create: the AA layout does not run the full corrections");
   if (!(q.rho0 > 0.0)) return fail(LBM_EINVAL, "lbm_create: rho0 must be > 0");
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(q.force[d])) return fail(LBM_EINVAL, "lbm_create: non-finite force");
@@ -86,6 +89,11 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   h->stride = padded_stride(n);
   h->elem = q.storage == LBM_F32 ? 4 : 2;
   h->bytes = (size_t)27 * (size_t)h->stride * h->elem;
+  if (q.layout == LBM_LAYOUT_AA && (q.bc_x == LBM_BOUNCEBACK || q.bc_y == LBM_BOUNCEBACK || q.bc_z == LBM_BOUNCEBACK) &&
+      h->bytes >= (1ull << 32)) {
+    delete h;
+    return fail(LBM_EINVAL, "lbm_create: the AA layout with walls needs a state below 4 GiB");
+  }
   // threads per block along x: the largest of 256, 192, 128, 64 that leaves the
   // fewest idle lanes in the last block of a row (e.g. 192 for nx = 384)
   h->block = 256;
@@ -109,6 +117,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   k.bb_y = q.bc_y == LBM_BOUNCEBACK;
   k.bb_z = q.bc_z == LBM_BOUNCEBACK;
   k.moving = moving;
+  k.aa = q.layout == LBM_LAYOUT_AA ? 1 : 0;
   k.ytile = 1;
   for (int t : {32, 16, 8, 4, 2})
     if (q.ny % t == 0) { k.ytile = t; break; }
@@ -191,13 +200,29 @@ int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream) {
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_export");
 }
 
+// AA layout: one buffer, steps in pairs (local, shifted).
+static int step_aa(lbm_handle* h, const char* name, int32_t nsteps, void* state, void* state_b,
+                   const float* force, const double* forces, hipStream_t st) {
+  if (state_b != nullptr && state_b != state)
+    return fail(LBM_EINVAL, std::string(name) + ": the AA layout updates state_a in place (state_b must be NULL)");
+  if (nsteps % 2 != 0) return fail(LBM_EINVAL, std::string(name) + ": the AA layout advances an even number of steps");
+  for (int32_t t = 0; t < nsteps; ++t) {
+    hipError_t e = forces ? clbm::launch_step_aa_uniform(*h, state, t & 1, (float)forces[3 * t],
+                                                         (float)forces[3 * t + 1], (float)forces[3 * t + 2], st)
+                          : clbm::launch_step_aa(*h, state, t & 1, force, st);
+    if (e != hipSuccess) return hip_fail(e, name);
+  }
+  return LBM_OK;
+}
+
 int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const float* force,
              void* hip_stream) {
   CHECK_HANDLE(h, "lbm_step");
   if (nsteps < 0) return fail(LBM_EINVAL, "lbm_step: nsteps < 0");
   CHECK_REQ(state_a, "lbm_step", "state_a");
-  CHECK_REQ(state_b, "lbm_step", "state_b");
   CHECK_PTR(force, "lbm_step", "force");
+  if (h->k.aa) return step_aa(h, "lbm_step", nsteps, state_a, state_b, force, nullptr, (hipStream_t)hip_stream);
+  CHECK_REQ(state_b, "lbm_step", "state_b");
   if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step: state_a and state_b must differ");
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step: the full corrections need a density field (use lbm_step_full)");
@@ -227,13 +252,15 @@ int lbm_step_forcing(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b
   CHECK_HANDLE(h, "lbm_step_forcing");
   if (nsteps < 0) return fail(LBM_EINVAL, "lbm_step_forcing: nsteps < 0");
   CHECK_REQ(state_a, "lbm_step_forcing", "state_a");
-  CHECK_REQ(state_b, "lbm_step_forcing", "state_b");
-  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step_forcing: state_a and state_b must differ");
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_forcing: the full corrections need a density field (use lbm_step_full)");
   if (nsteps > 0 && forces == nullptr) return fail(LBM_EINVAL, "lbm_step_forcing: NULL forces");
   for (int64_t i = 0; i < 3 * (int64_t)nsteps; ++i)
     if (!std::isfinite(forces[i])) return fail(LBM_EINVAL, "lbm_step_forcing: non-finite force");
+  if (h->k.aa)
+    return step_aa(h, "lbm_step_forcing", nsteps, state_a, state_b, nullptr, forces, (hipStream_t)hip_stream);
+  CHECK_REQ(state_b, "lbm_step_forcing", "state_b");
+  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step_forcing: state_a and state_b must differ");
   void* bufs[2] = {state_a, state_b};
   for (int32_t t = 0; t < nsteps; ++t) {
     hipError_t e = clbm::launch_step_uniform(*h, bufs[t & 1], bufs[(t + 1) & 1], (float)forces[3 * t],
@@ -314,6 +341,7 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out,
                      const float* force, float* grad_force, double* grad_force_uniform, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_step_adjoint");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_step_adjoint: the adjoint runs on the AB layout only");
   CHECK_REQ(state_t, "lbm_step_adjoint", "state_t");
   CHECK_REQ(adj_in, "lbm_step_adjoint", "adj_in");
   CHECK_REQ(adj_out, "lbm_step_adjoint", "adj_out");
@@ -331,6 +359,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
 int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force, const float* g_rho,
                         const float* g_u, float* adj, float* grad_force, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_moments_adjoint");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_moments_adjoint: the adjoint runs on the AB layout only");
   CHECK_REQ(state, "lbm_moments_adjoint", "state");
   CHECK_REQ(adj, "lbm_moments_adjoint", "adj");
   CHECK_PTR(force, "lbm_moments_adjoint", "force");
@@ -345,6 +374,7 @@ int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force, co
 int lbm_init_adjoint(lbm_handle* h, const float* adj, const double* rho, const double* u, double* g_rho,
                      double* g_u, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_init_adjoint");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_init_adjoint: the adjoint runs on the AB layout only");
   CHECK_REQ(adj, "lbm_init_adjoint", "adj");
   CHECK_PTR(rho, "lbm_init_adjoint", "rho");
   CHECK_PTR(u, "lbm_init_adjoint", "u");
@@ -356,6 +386,7 @@ int lbm_init_adjoint(lbm_handle* h, const float* adj, const double* rho, const d
 
 int lbm_adjoint_to_natural(lbm_handle* h, const float* slots, double* natural, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_adjoint_to_natural");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_adjoint_to_natural: the adjoint runs on the AB layout only");
   CHECK_REQ(slots, "lbm_adjoint_to_natural", "slots");
   CHECK_REQ(natural, "lbm_adjoint_to_natural", "natural");
   hipError_t e = clbm::launch_adjoint_natural(*h, slots, natural, 1, nullptr, nullptr, (hipStream_t)hip_stream);
@@ -364,6 +395,7 @@ int lbm_adjoint_to_natural(lbm_handle* h, const float* slots, double* natural, v
 
 int lbm_adjoint_from_natural(lbm_handle* h, const double* natural, float* slots, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_adjoint_from_natural");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_adjoint_from_natural: the adjoint runs on the AB layout only");
   CHECK_REQ(slots, "lbm_adjoint_from_natural", "slots");
   CHECK_REQ(natural, "lbm_adjoint_from_natural", "natural");
   hipError_t e = clbm::launch_adjoint_natural(*h, nullptr, nullptr, 0, natural, slots, (hipStream_t)hip_stream);

@@ -40,6 +40,7 @@ struct Consts {
   int bb_x, bb_y, bb_z;    // 1 = halfway bounce-back walls on that axis
   int moving;              // bit f set = face f moves (momentum-augmented bounce-back)
   int ytile;               // rows per y-tile of the full-correction step's row order (divides ny)
+  int aa;                  // 1 = AA layout: between calls slot (a, x) holds f_a(x) (natural order)
   float wall_u[6][3];      // face velocities, faces x-, x+, y-, y+, z-, z+
   int64_t stride;          // elements between direction arrays
   int64_t n;               // nodes
@@ -103,12 +104,14 @@ __device__ __forceinline__ NodeCoord make_coord(int x, int y, int z, const Const
   return c;
 }
 
-// Slot from which the node gathers f_a: (a, x - ebar_a) or, across a wall, (opp(a), x).
+// Slot from which the node gathers f_a: (a, x - ebar_a) or, across a wall, (opp(a), x);
+// in the AA layout between calls, (a, x).
 // WX = false compiles the x-wall test away (for callers that know x is periodic).
 template <int A, bool WX = true>
 __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts& k) {
   constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
   constexpr int opp = opposite_of(A);
+  if (k.aa) return (int64_t)A * k.stride + ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;  // natural order
   const int xs = ex == 0 ? c.x : (ex > 0 ? c.xm : c.xp);
   const int ys = ey == 0 ? c.y : (ey > 0 ? c.ym : c.yp);
   const int zs = ez == 0 ? c.z : (ez > 0 ? c.zm : c.zp);

@@ -26,6 +26,10 @@ hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const fl
 hipError_t launch_step_uniform(const lbm_handle& h, const void* src, void* dst, float fx, float fy, float fz,
                                hipStream_t st);
 hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
+// AA layout: one step in place; odd selects the shifted half of the pair.
+hipError_t launch_step_aa(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st);
+hipError_t launch_step_aa_uniform(const lbm_handle& h, void* state, int odd, float fx, float fy, float fz,
+                                  hipStream_t st);
 hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,
                        const double* perturb, hipStream_t st);
 hipError_t launch_import(const lbm_handle& h, void* dst, const double* f, hipStream_t st);

@@ -72,7 +72,7 @@ def _state(h, t, name="state"):
 
 def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, omega_hi=1.0,
                bc_y="periodic", bc_z="periodic", storage="f32", corr="local", rho0=1.0,
-               force=(0.0, 0.0, 0.0), bc_x="periodic", wall_velocity=None, moments="central"):
+               force=(0.0, 0.0, 0.0), bc_x="periodic", wall_velocity=None, moments="central", layout="ab"):
     """wall_velocity: None or six 3-vectors, faces x-, x+, y-, y+, z-, z+."""
     lib = _lib.load()
     p = _lib.LbmParams()
@@ -82,6 +82,7 @@ def lbm_create(nx, ny, nz, r=1.0, s=1.0, cs2=0.0, omega_nu=1.0, omega_xi=1.0, om
     p.bc_x, p.bc_y, p.bc_z = _lib.BC[bc_x], _lib.BC[bc_y], _lib.BC[bc_z]
     p.storage, p.corr = _lib.STORAGE[storage], _lib.CORR[corr]
     p.moments = _lib.MOMENTS[moments]
+    p.layout = _lib.LAYOUT[layout]
     p.rho0 = rho0
     for d in range(3):
         p.force[d] = float(force[d])
@@ -115,10 +116,15 @@ def lbm_export(h, state, f, stream=None):
     _lib.check(_lib.load().lbm_export(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(f), _lib.stream_ptr(stream)))
 
 
+def _state_b(h, t):
+    """state_b: a buffer, or None in the AA layout (one buffer updated in place)."""
+    return None if t is None and h.params.layout == _lib.LAYOUT["aa"] else _state(h, t, "state_b")
+
+
 def lbm_step(h, nsteps, state_a, state_b, force=None, stream=None):
     _require(force, _ABI_F32, 3 * h.n, "force")
     _lib.check(_lib.load().lbm_step(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
-                                    _lib.ptr(_state(h, state_b, "state_b")), _lib.ptr(force),
+                                    _lib.ptr(_state_b(h, state_b)), _lib.ptr(force),
                                     _lib.stream_ptr(stream)))
 
 
@@ -135,7 +141,7 @@ def lbm_step_forcing(h, nsteps, state_a, state_b, forces, stream=None):
         raise ValueError(f"forces: need {nsteps} x 3 values, got {arr.size}")
     ptr = arr.ctypes.data_as(_lib.ctypes.POINTER(_lib.ctypes.c_double))
     _lib.check(_lib.load().lbm_step_forcing(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
-                                            _lib.ptr(_state(h, state_b, "state_b")), ptr,
+                                            _lib.ptr(_state_b(h, state_b)), ptr,
                                             _lib.stream_ptr(stream)))
 
 
@@ -270,10 +276,14 @@ class Lattice:
         lbm_export(self.h, state, f)
         return f
 
+    @property
+    def aa(self):
+        return self.h.params.layout == _lib.LAYOUT["aa"]
+
     def step(self, a, b, nsteps, force=None):
-        """Advance; returns (current, scratch) after nsteps."""
+        """Advance; returns (current, scratch) after nsteps (AA layout: b may be None, a stays current)."""
         lbm_step(self.h, nsteps, a, b, force)
-        return (a, b) if nsteps % 2 == 0 else (b, a)
+        return (a, b) if (nsteps % 2 == 0 or self.aa) else (b, a)
 
     def step_full(self, a, b, nsteps, drho_a, drho_b=None, mode="lagged", force=None):
         """Full corrections; returns (current, scratch, current density field, other density field)."""
@@ -286,7 +296,7 @@ class Lattice:
         """Advance len(forces) steps, step t under the uniform force forces[t]; returns (current, scratch)."""
         n = len(forces)
         lbm_step_forcing(self.h, n, a, b, forces)
-        return (a, b) if n % 2 == 0 else (b, a)
+        return (a, b) if (n % 2 == 0 or self.aa) else (b, a)
 
     def set_force(self, force):
         lbm_set_force(self.h, force)

@@ -20,10 +20,10 @@ def test_library_exports_every_declared_function():
 
 
 def test_params_struct_layout_matches_header():
-    # int32 x3, pad, double x6, int32 x6, double, double[3], double[6][3]
-    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 6 + 8 + 24 + 144
-    assert _lib.LbmParams.rho0.offset == 4 * 3 + 4 + 8 * 6 + 4 * 6
-    assert _lib.LbmParams.wall_velocity.offset == 4 * 3 + 4 + 8 * 6 + 4 * 6 + 8 + 24
+    # int32 x3, pad, double x6, int32 x7, pad, double, double[3], double[6][3]
+    assert ctypes.sizeof(_lib.LbmParams) == 4 * 3 + 4 + 8 * 6 + 4 * 7 + 4 + 8 + 24 + 144
+    assert _lib.LbmParams.rho0.offset == 4 * 3 + 4 + 8 * 6 + 4 * 7 + 4
+    assert _lib.LbmParams.wall_velocity.offset == 4 * 3 + 4 + 8 * 6 + 4 * 7 + 4 + 8 + 24
 
 
 def test_create_sizes_and_padding():
@@ -131,3 +131,20 @@ def test_set_force_and_step_forcing_validate_on_the_host():
     f = (ctypes.c_double * 6)(0, 0, 0, float("inf"), 0, 0)
     assert lib.lbm_step_forcing(h.raw, 2, a, b, f, None) == _lib.LBM_EINVAL
     assert lib.lbm_step_forcing(h.raw, 0, a, b, None, None) == _lib.LBM_OK
+
+
+def test_aa_layout_validation():
+    lib = _lib.load()
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    h = P.lbm_create(4, 4, 4, layout="aa")
+    assert lib.lbm_step(h.raw, 1, a, None, None, None) == _lib.LBM_EINVAL           # odd step count
+    assert b"even" in lib.lbm_last_error()
+    assert lib.lbm_step(h.raw, 2, a, b, None, None) == _lib.LBM_EINVAL              # a second buffer
+    assert lib.lbm_step(h.raw, 0, a, None, None, None) == _lib.LBM_OK
+    assert lib.lbm_step_adjoint(h.raw, a, b, ctypes.c_void_p(0x30000), None, None, None, None) == _lib.LBM_EINVAL
+    with pytest.raises(_lib.LbmError):
+        P.lbm_create(4, 4, 4, layout="aa", corr="full")
+    # walls with a state of 4 GiB or more cannot use 32-bit offsets
+    with pytest.raises(_lib.LbmError) as e:
+        P.lbm_create(1024, 1024, 1100, layout="aa", bc_y="bounceback")
+    assert "4 GiB" in str(e.value)
