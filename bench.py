@@ -259,12 +259,16 @@ def cpu_baseline(w):
 PROFILE_KERNELS = {
     "f32": "k_step<0, 2, false, false>", "f16": "k_step<1, 2, false, false>", "bf16": "k_step<2, 2, false, false>",
     "full_f32": "k_step<0, 3, false, false>", "full_f16": "k_step<1, 3, false, false>",
+    "aa_f32 (local)": "k_step_aa<0, 2, false, false, false>", "aa_f32 (shifted)": "k_step_aa<0, 2, true, false, false>",
+    "aa_f16 (local)": "k_step_aa<1, 2, false, false, false>", "aa_f16 (shifted)": "k_step_aa<1, 2, true, false, false>",
     "adjoint_f32": "k_step_adjoint<0, 2, 1, false>", "adjoint_f16": "k_step_adjoint<1, 2, 0, false>",
 }
 PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),
     "bf16": (512, 512, 256, "512x512x256"), "full_f32": (512, 512, 256, "512x512x256"),
     "full_f16": (512, 512, 256, "512x512x256"), "adjoint_f32": (128, 128, 64, "128x128x64 duct"),
+    "aa_f32 (local)": (512, 512, 256, "512x512x256"), "aa_f32 (shifted)": (512, 512, 256, "512x512x256"),
+    "aa_f16 (local)": (512, 512, 256, "512x512x256"), "aa_f16 (shifted)": (512, 512, 256, "512x512x256"),
     "adjoint_f16": (384, 384, 192, "384x384x192"),
 }
 # $OUT is any output directory (the three runs write their CSVs under it)
@@ -293,12 +297,15 @@ def summarize_rocprof(out_dir):
     import csv
     import statistics
     alg = dict(BYTES_PER_LUP, **ADJ_BYTES_PER_LUP)
+    for v in PROFILE_KERNELS:
+        if v.startswith("aa_"):
+            alg[v] = BYTES_PER_LUP[v.split()[0]]
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
              "# corrections) and its adjoint (128x128x64 duct with force field; 384x384x192, r=1/2, s=1/4, FP16)",
              "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):", "  " + TRACE_CMD,
              "  " + SUMMARY_CMD, "",
-             "kernel                         variant      workload         calls  avg_ms   min_ms   max_ms   "
+             f"{'kernel':38s} {'variant':16s} {'workload':16s} calls  avg_ms   min_ms   max_ms   "
              "MLUPS(avg)  alg_B/LUP  alg_GB/s  frac_of_8TB/s"]
     for v, key in PROFILE_KERNELS.items():
         nx, ny, nz, label = PROFILE_WORKLOADS[v]
@@ -310,7 +317,7 @@ def summarize_rocprof(out_dir):
         n = nx * ny * nz
         avg = statistics.mean(d) / 1e6
         b = alg[v]
-        lines.append(f"{key:30s} {v:12s} {label:16s} {len(d):5d}  {avg:.4f}  {min(d) / 1e6:.4f}  {max(d) / 1e6:.4f}"
+        lines.append(f"{key:38s} {v:16s} {label:16s} {len(d):5d}  {avg:.4f}  {min(d) / 1e6:.4f}  {max(d) / 1e6:.4f}"
                      f"  {n / avg / 1e3:10.0f}  {b:9d}  {b * n / avg / 1e6:8.0f}  {b * n / avg / 1e6 / HBM_PEAK_GBS:.3f}")
     lines += ["", "(kernels grouped by name and grid size; the adjoint calls include the backward passes of bench.py)"]
     with open(os.path.join(ROOT, TRACE_SUMMARY), "w") as fh:
@@ -332,7 +339,7 @@ def summarize_rocprof(out_dir):
              "calibration: the 4 GiB device-to-device copy in the same runs (hipMemcpy kernel __amd_rocclr_copyBuffer,",
              f"reads and writes exactly {copy_bytes} bytes): mean FETCH_SIZE {statistics.mean(cf):.1f} KiB -> scale "
              f"{kf:.4f};", f"mean WRITE_SIZE {statistics.mean(cw):.1f} KiB -> scale {kw:.4f}", "",
-             "kernel                         variant      FETCH_KiB(raw)  WRITE_KiB(raw)  read_B/LUP  write_B/LUP  "
+             f"{'kernel':38s} {'variant':16s} FETCH_KiB(raw)  WRITE_KiB(raw)  read_B/LUP  write_B/LUP  "
              "total_B/LUP  algorithmic_B/LUP"]
     traffic = {}
     for v, key in PROFILE_KERNELS.items():
@@ -345,7 +352,7 @@ def summarize_rocprof(out_dir):
         n = nx * ny * nz
         rb = statistics.mean(fv) * 1024 * kf / n
         wb = statistics.mean(wv) * 1024 * kw / n
-        lines.append(f"{key:30s} {v:12s} {statistics.mean(fv):14.1f}  {statistics.mean(wv):14.1f}  {rb:10.2f}  "
+        lines.append(f"{key:38s} {v:16s} {statistics.mean(fv):14.1f}  {statistics.mean(wv):14.1f}  {rb:10.2f}  "
                      f"{wb:11.2f}  {rb + wb:11.2f}  {alg[v]:17d}")
         traffic[v] = {"kernel": key, "bytes_per_launch": round((rb + wb) * n), "bytes_per_lup": round(rb + wb, 3),
                       "read_bytes_per_lup": round(rb, 3), "write_bytes_per_lup": round(wb, 3),
