@@ -49,9 +49,9 @@ AA_VARIANTS = {"aa_f32": "f32", "aa_f16": "f16"}
 BYTES_PER_LUP.update({"aa_f32": 216, "aa_f16": 108})
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
 ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
-KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_forward.hip",
+KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_step.h",
                   "paper_2107_14774_amd/csrc/lbm_api.hip")
-ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint.hip",
+ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint_step.h",
                    "paper_2107_14774_amd/csrc/lbm_api.hip")
 
 

@@ -121,7 +121,9 @@ typedef struct lbm_params {
   double cs2;           /* squared sound speed; <= 0 selects min(r^2, s^2)/3 (end of Sec. 2.5) */
   double omega_nu;      /* shear rate, 0 < omega_nu < 2: nu = cs2 (1/omega_nu - 1/2) (eq. 53) */
   double omega_xi;      /* bulk rate, 0 < omega_xi < 2: xi = (2 cs2/3)(1/omega_xi - 1/2) */
-  double omega_hi;      /* rate of every third- and higher-order moment; must be 1 (App. D) */
+  double omega_hi;      /* rate of every third- and higher-order moment, 0 < omega_hi < 2
+                           (App. D; the paper uses 1, the fastest kernels); other values
+                           select kernels that keep the gathered populations live */
   int32_t bc_x, bc_y, bc_z; /* enum lbm_bc per axis */
   int32_t storage;      /* enum lbm_storage */
   int32_t corr;         /* enum lbm_corr */
@@ -137,7 +139,7 @@ typedef struct lbm_handle lbm_handle;
 
 /* Validate p and create a host-side handle holding the derived constants.
  * Rejects (LBM_EINVAL): a size < 1 (or < 2 on a bounce-back axis), more than
- * 2^31 - 1 nodes, r or s <= 0, a rate outside (0, 2), omega_hi != 1, a sound
+ * 2^31 - 1 nodes, r or s <= 0, a rate outside (0, 2), a sound
  * speed that makes a rest weight <= 0 (cs2 >= min(1, r^2, s^2)), unknown enum
  * values, rho0 <= 0, a non-finite force or wall velocity, a wall velocity on
  * a periodic axis or with a component along its face normal. */

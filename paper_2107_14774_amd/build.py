@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ("lbm_api.hip", "lbm_forward.hip", "lbm_adjoint.hip")
+SOURCES = ("lbm_api.hip", "lbm_forward.hip", "lbm_adjoint.hip",
+           "lbm_step_f32.hip", "lbm_step_f16.hip", "lbm_step_bf16.hip",
+           "lbm_adjoint_step_f32.hip", "lbm_adjoint_step_f16.hip", "lbm_adjoint_step_bf16.hip")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

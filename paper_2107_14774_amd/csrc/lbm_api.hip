@@ -71,7 +71,8 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     return fail(LBM_EINVAL, "lbm_create: cs2 must be < min(1, r^2, s^2) (positive rest weights)");
   if (!(q.omega_nu > 0.0 && q.omega_nu < 2.0) || !(q.omega_xi > 0.0 && q.omega_xi < 2.0))
     return fail(LBM_EINVAL, "lbm_create: omega_nu and omega_xi must lie in (0, 2)");
-  if (q.omega_hi != 1.0) return fail(LBM_EINVAL, "lbm_create: only omega_hi = 1 is implemented");
+  if (!(q.omega_hi > 0.0 && q.omega_hi < 2.0))
+    return fail(LBM_EINVAL, "lbm_create: omega_hi must lie in (0, 2)");
   if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
   if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
   if (q.moments != LBM_CENTRAL && q.moments != LBM_RAW) return fail(LBM_EINVAL, "lbm_create: unknown moment basis");
@@ -118,6 +119,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   k.bb_z = q.bc_z == LBM_BOUNCEBACK;
   k.moving = moving;
   k.aa = q.layout == LBM_LAYOUT_AA ? 1 : 0;
+  k.hi = q.omega_hi != 1.0 ? 1 : 0;
   k.ytile = 1;
   for (int t : {32, 16, 8, 4, 2})
     if (q.ny % t == 0) { k.ytile = t; break; }
@@ -130,7 +132,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   k.stride = h->stride;
   k.n = n;
   k.rho0 = (float)q.rho0; k.cs2 = (float)q.cs2; k.r = (float)q.r; k.s = (float)q.s;
-  k.omega_nu = (float)q.omega_nu; k.omega_xi = (float)q.omega_xi;
+  k.omega_nu = (float)q.omega_nu; k.omega_xi = (float)q.omega_xi; k.omega_hi = (float)q.omega_hi;
   k.fx = (float)q.force[0]; k.fy = (float)q.force[1]; k.fz = (float)q.force[2];
   kd.rho0 = q.rho0; kd.cs2 = q.cs2;
   double W[3][3];

@@ -52,6 +52,8 @@ struct Consts {
   float w0c[3], w0s[3];    // rest weights per axis: centre 1 - cs2/c^2, side cs2/(2 c^2)
   float sigma[27];         // storage scale per direction
   float inv_sigma[27];
+  float omega_hi;          // rate of the moments of order >= 3
+  int hi;                  // 1 = omega_hi != 1 (kernels with the general higher-order rate)
 };
 
 // FP64 copies for the one-time conversions (init, import, export).
@@ -206,7 +208,7 @@ __device__ __forceinline__ AxisVec axis_vectors(float u, int d, const Consts& k)
 
 // ----------------------------------------------------------------- collision
 // Post-collision deviations of one node (the collide bullets of Sec. 3.2 with
-// the App. D collision, every higher-order rate 1), in the deviation form
+// the App. D collision), for unit higher-order rate in the deviation form
 //   f~ - w rho0 = d_rho E(x)E(x)E + rho0 [D(x)E(x)E + W0(x)D(x)E + W0(x)W0(x)D]
 //                 + sum over the first/second-order non-equilibrium central
 //                   moments Delta_mnp of Delta_mnp A_m(x)A_n(x)A_p,
@@ -219,7 +221,14 @@ __device__ __forceinline__ AxisVec axis_vectors(float u, int d, const Consts& k)
 // equilibria plus half the source, so its relaxed second-order
 // non-equilibrium parts Delta map back through the per-axis basis at u = 0
 // (A0 = (0, 1, 0), A1 = (-1, 0, 1)/(2c), A2 unchanged) instead of at u.
-template <int CORR, bool RAW = false>
+// HI: a general rate w of the moments of order >= 3 (k.omega_hi).  Those
+// moments carry no source and all relax with w, so by the completeness of the
+// 27 moments the collision becomes
+//   f~ = w f_eq + (1 - w) f + (1 - w/2) s + sum_2 Delta'_mnp A_m(x)A_n(x)A_p,
+// s the population of the central source F (first order only), with the
+// second-order factors (1 - omega) replaced by (w - omega); the same holds in
+// the raw scheme.  w = 1 gives the form above.
+template <int CORR, bool RAW = false, bool HI = false>
 __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, float fy, float fz,
                                              const Consts& k, float (&out)[27],
                                              float grx = 0.0f, float gry = 0.0f, float grz = 0.0f) {
@@ -281,15 +290,18 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
     c2s = hx * (tx * gx + ty * gy + tz * gz + 2.0f * eb);
   }
   // relaxation of the combined moments, then segregation (B^-1 of App. D)
-  const float D2s = (1.0f - wx) * Rb + wx * c2s;
-  const float D2d1 = (1.0f - wn) * Rs1 + wn * c2d1;
-  const float D2d2 = (1.0f - wn) * Rs2 + wn * c2d2;
+  const float wh = HI ? k.omega_hi : 1.0f;
+  const float D2s = (wh - wx) * Rb + wx * c2s;
+  const float D2d1 = (wh - wn) * Rs1 + wn * c2d1;
+  const float D2d2 = (wh - wn) * Rs2 + wn * c2d2;
   constexpr float third = 1.0f / 3.0f;
   const float Dxx = (D2s + D2d1 + D2d2) * third;
   const float Dyy = (D2s - 2.0f * D2d1 + D2d2) * third;
   const float Dzz = (D2s + D2d1 - 2.0f * D2d2) * third;
-  const float Dxy = (1.0f - wn) * kxy, Dxz = (1.0f - wn) * kxz, Dyz = (1.0f - wn) * kyz;
-  const float Dx = 0.5f * fx, Dy = 0.5f * fy, Dz = 0.5f * fz;  // post-collision k_100 = F/2
+  const float Dxy = (wh - wn) * kxy, Dxz = (wh - wn) * kxz, Dyz = (wh - wn) * kyz;
+  const float hF = 1.0f - 0.5f * wh;  // post-collision k_100 = F/2 (unit rate)
+  const float Dx = hF * fx, Dy = hF * fy, Dz = hF * fz;
+  const float drhoh = wh * drho, rho0h = wh * rho0;  // equilibrium part, times w
 
   const AxisVec X = axis_vectors(ux, 0, k);
   const AxisVec Y = axis_vectors(uy, 1, k);
@@ -297,8 +309,8 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   if constexpr (!RAW) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const float eE = drho * X.E[i] + rho0 * X.D[i];
-      const float eW = rho0 * X.W0[i];
+      const float eE = drhoh * X.E[i] + rho0h * X.D[i];
+      const float eW = rho0h * X.W0[i];
       const float a0 = Dx * X.A1[i] + Dxx * X.A2[i];
       const float a1 = Dy * X.A0[i] + Dxy * X.A1[i];
       const float a2 = Dyy * X.A0[i];
@@ -323,8 +335,8 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
     const float cxy = Dxy * hx * hy, cxz = Dxz * hx * hz, cyz = Dyz * hy * hz;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const float eE = drho * X.E[i] + rho0 * X.D[i];
-      const float eW = rho0 * X.W0[i];
+      const float eE = drhoh * X.E[i] + rho0h * X.D[i];
+      const float eW = rho0h * X.W0[i];
       const float a0 = Dx * X.A1[i];
       const float a1 = Dy * X.A0[i];
       const float b0 = Dz * X.A0[i];
@@ -348,6 +360,11 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
         }
       }
     }
+  }
+  if constexpr (HI) {
+    const float wl = 1.0f - wh;
+#pragma unroll
+    for (int a = 0; a < 27; ++a) out[a] += wl * df[a];
   }
 }
 

@@ -1,223 +1,9 @@
-// Forward kernels: fused collide-and-stream step, initialisation,
-// import/export of natural populations, observables with FP64 totals.
+// Forward entry points: the collide-and-stream step (kernels in lbm_step.h,
+// one translation unit per storage type), initialisation, import/export of
+// natural populations, observables with FP64 totals.
 #include "lbm_internal.h"
 
 namespace clbm {
-
-// ------------------------------------------------------------------ step
-// One thread per node, pull scheme: gather 27 slots of the source buffer,
-// collide, write the node's 27 slots of the destination buffer (coalesced
-// along x, non-temporal).  Without walls every source slot is
-// (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
-// base pointer plus a 32-bit node index shared by the three directions of
-// one source row; with walls the general slot rule of gather_slot applies.
-// With the full corrections (CORR 3) the density gradient comes from the
-// density-deviation field grad_src, and drho_out (if not NULL) receives the
-// node's own density deviation.
-// WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
-// offsets from direction 0's array (state below 4 GiB), 2 walls, 64-bit slots.
-template <int ST, int WALLS>
-__device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
-                                            const Consts& k, float (&df)[27]) {
-  if constexpr (WALLS == 2) {
-    gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
-  } else {
-    PeriodicRows pr;
-    periodic_rows(x, y, z, k, pr);
-    if constexpr (WALLS == 1) {
-      const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-      gather_walls32<ST>(P.src[0], pr, node, wall_flags(x, y, z, k), k, df);
-    } else {
-      gather_periodic<ST>(P.src, pr, k, df);
-    }
-  }
-}
-
-// Minimum waves per SIMD the compiler must fit (1 = no register limit).
-#ifndef LBM_STEP_WAVES_F32
-#define LBM_STEP_WAVES_F32 1
-#endif
-#ifndef LBM_STEP_WAVES_F16
-#define LBM_STEP_WAVES_F16 1
-#endif
-#ifndef LBM_FULL_WAVES_F32
-#define LBM_FULL_WAVES_F32 1
-#endif
-#ifndef LBM_FULL_WAVES_F16
-#define LBM_FULL_WAVES_F16 1
-#endif
-constexpr int step_waves(int st, int corr) {
-  return corr == 3 ? (st == 0 ? LBM_FULL_WAVES_F32 : LBM_FULL_WAVES_F16)
-                   : (st == 0 ? LBM_STEP_WAVES_F32 : LBM_STEP_WAVES_F16);
-}
-
-template <int ST, int CORR, int WALLS, bool RAW>
-__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<typename Store<ST>::T> P,
-                                              const float* __restrict__ force,
-                                              const float* __restrict__ grad_src, float* __restrict__ drho_out,
-                                              Consts k, uint32_t bpr) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  int y, z;
-  if constexpr (CORR == 3) {
-    // rows in y-tiles of k.ytile, z-major inside a tile: the density rows of z - 1 and
-    // z + 1 are then read a few rows apart (an L2 hit) instead of a whole plane apart
-    const uint32_t ty = (uint32_t)k.ytile, per_tile = ty * (uint32_t)k.nz;
-    const uint32_t tile = rowid / per_tile, rem = rowid % per_tile;
-    z = (int)(rem / ty);
-    y = (int)(tile * ty + rem % ty);
-  } else {
-    y = (int)(rowid % (uint32_t)k.ny);
-    z = (int)(rowid / (uint32_t)k.ny);
-  }
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
-  // the density gradient first (block-wide, with a barrier), while no population is live
-  float grx = 0.0f, gry = 0.0f, grz = 0.0f;
-  if constexpr (CORR == 3) {
-    __shared__ float lds[3][258];
-    density_gradient_block(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
-  }
-  if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-  float df[27];
-  gather_node<ST, WALLS>(P, x, y, z, k, df);
-  float fx = k.fx, fy = k.fy, fz = k.fz;
-  if (force != nullptr) {
-    fx = ld_off(force, node);
-    fy = ld_off(force + k.n, node);
-    fz = ld_off(force + 2 * k.n, node);
-  }
-  float out[27];
-  if constexpr (CORR == 3) {
-    collide_node<CORR, RAW>(df, fx, fy, fz, k, out, grx, gry, grz);
-    if (drho_out != nullptr) drho_out[node] = low_moments(df).m000;
-  } else {
-    collide_node<CORR, RAW>(df, fx, fy, fz, k, out);
-  }
-  if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
-  if constexpr (WALLS != 0) {
-    if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
-  }
-#pragma unroll
-  for (int a = 0; a < 27; ++a)
-    st_off_nt(P.dst[a], node, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]));
-}
-
-// ------------------------------------------------------------------ step, AA layout
-// One buffer updated in place.  Even steps (ODD = false): node x reads its own
-// slots (a, x), collides and writes f~_a to (opp(a), x).  Odd steps: f_a(x) is
-// read from (opp(a), x - ebar_a), or from (a, x) when x - ebar_a lies beyond a
-// wall, and f~_a is written to (a, x + ebar_a), or to (opp(a), x) when
-// x + ebar_a lies beyond a wall.  Within a step every slot is read and written
-// by one node only, so the update needs no second buffer.  After an even
-// number of steps slot (a, x) holds f_a(x) again.  Without walls each direction
-// array is addressed through its own base pointer; with walls all 27 arrays
-// through direction 0's base with 32-bit offsets (the state below 4 GiB).
-template <int A>
-__device__ __forceinline__ bool pulls_through_wall(const WallFlags& w) {
-  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
-  bool wall = false;
-  if (ex > 0) wall |= w.lx;
-  if (ex < 0) wall |= w.hx;
-  if (ey > 0) wall |= w.ly;
-  if (ey < 0) wall |= w.hy;
-  if (ez > 0) wall |= w.lz;
-  if (ez < 0) wall |= w.hz;
-  return wall;
-}
-
-template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
-                                          const WallFlags& w, const Consts& k, float (&df)[27]) {
-  constexpr int opp = opposite_of(A);
-  typename Store<ST>::T v;
-  if constexpr (!ODD) {
-    v = ld_off(P.src[A], node);
-  } else if constexpr (WALLS) {
-    const uint32_t stride = (uint32_t)k.stride;
-    const uint32_t idx = pulls_through_wall<A>(w) ? (uint32_t)A * stride + node
-                                                  : (uint32_t)opp * stride + periodic_src<A>(pr);
-    v = ld_off(P.src[0], idx);
-  } else {
-    v = ld_off(P.src[opp], periodic_src<A>(pr));
-  }
-  const float f = Store<ST>::load_val(v);
-  df[A] = ST == 0 ? f : f * k.inv_sigma[A];
-  if constexpr (A + 1 < 27) gather_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, df);
-}
-
-template <typename T>
-__device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t idx, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
-}
-
-template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void store_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
-                                         const WallFlags& w, const Consts& k, const float (&out)[27]) {
-  constexpr int opp = opposite_of(A);
-  const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[A]);
-  if constexpr (!ODD) {
-    st_off_nt(P.dst[opp], node, v);
-  } else if constexpr (WALLS) {
-    // x + ebar_A lies beyond a wall exactly when opp(A) pulls through one
-    const uint32_t stride = (uint32_t)k.stride;
-    const uint32_t idx = pulls_through_wall<opp>(w) ? (uint32_t)opp * stride + node
-                                                    : (uint32_t)A * stride + periodic_src<opp>(pr);
-    st_off(P.dst[0], idx, v);
-  } else {
-    // shifted by one node along x for most directions: plain stores, partial lines merge in L2
-    // (non-temporal stores measured 0-1.5% slower here)
-    st_off(P.dst[A], periodic_src<opp>(pr), v);
-  }
-  if constexpr (A + 1 < 27) store_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, out);
-}
-
-template <int ST, int CORR, bool ODD, bool WALLS, bool RAW>
-__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(DirPtrs<typename Store<ST>::T> P,
-                                                                       const float* __restrict__ force, Consts k,
-                                                                       uint32_t bpr) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
-  if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-  PeriodicRows pr;
-  WallFlags w{};
-  if constexpr (ODD) periodic_rows(x, y, z, k, pr);
-  if constexpr (WALLS) w = wall_flags(x, y, z, k);
-  float df[27];
-  gather_aa<ST, ODD, WALLS>(P, pr, node, w, k, df);
-  float fx = k.fx, fy = k.fy, fz = k.fz;
-  if (force != nullptr) {
-    fx = ld_off(force, node);
-    fy = ld_off(force + k.n, node);
-    fz = ld_off(force + 2 * k.n, node);
-  }
-  float out[27];
-  collide_node<CORR, RAW>(df, fx, fy, fz, k, out);
-  if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
-  if constexpr (WALLS) {
-    if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
-  }
-  store_aa<ST, ODD, WALLS>(P, pr, node, w, k, out);
-}
-
-// Density deviation of every node of a state: the same gather and the same
-// FP32 sum as the step, so the value is bit-identical to the step's.
-template <int ST, int WALLS>
-__global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> P, float* __restrict__ drho,
-                                                 Consts k, uint32_t bpr) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
-  if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-  float df[27];
-  gather_node<ST, WALLS>(P, x, y, z, k, df);
-  drho[node] = low_moments(df).m000;
-}
 
 // ------------------------------------------------------------------ init / import / export
 // FP64 equilibrium deviation f_eq(rho, u) - w rho0 of one node, written
@@ -378,15 +164,6 @@ __global__ __launch_bounds__(256) void k_moments(const typename Store<ST>::T* __
 }
 
 // ------------------------------------------------------------------ launchers
-// Gather path: 0 periodic (32-bit offsets per direction array), 1 walls with
-// 32-bit offsets across the whole state, 2 walls with 64-bit slots.
-static int gather_kind(const lbm_handle& h) {
-  const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  if (!walls && (uint64_t)h.stride * h.elem < (1ull << 32)) return 0;
-  if (27ull * (uint64_t)h.stride * h.elem < (1ull << 32)) return 1;
-  return 2;
-}
-
 static int grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -394,114 +171,20 @@ static int grid_for(int64_t n, int block, int64_t cap) {
   return (int)g;
 }
 
-template <int ST>
-static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst, const float* force,
-                                const float* grad_src, float* drho_out, hipStream_t st) {
-  using T = typename Store<ST>::T;
-  const int block = h.block;
-  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
-  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
-  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)src + (int64_t)a * h.stride;
-    P.dst[a] = (T*)dst + (int64_t)a * h.stride;
-  }
-  const int kind = gather_kind(h);
-  const dim3 grid((unsigned)nb), blk(block);
-#define CLBM_STEP(C, W, R) \
-  hipLaunchKernelGGL((k_step<ST, C, W, R>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
-#define CLBM_STEP_CORR(W, R)                   \
-  switch (h.p.corr) {                          \
-    case 0: CLBM_STEP(0, W, R); break;         \
-    case 1: CLBM_STEP(1, W, R); break;         \
-    case 2: CLBM_STEP(2, W, R); break;         \
-    default: CLBM_STEP(3, W, R); break;        \
-  }
-#define CLBM_STEP_RAW(W)                                           \
-  if (h.p.moments == LBM_RAW) { CLBM_STEP_CORR(W, true) } else { CLBM_STEP_CORR(W, false) }
-  if (kind == 0) {
-    CLBM_STEP_RAW(0)
-  } else if (kind == 1) {
-    CLBM_STEP_RAW(1)
-  } else {
-    CLBM_STEP_RAW(2)
-  }
-#undef CLBM_STEP_RAW
-#undef CLBM_STEP_CORR
-#undef CLBM_STEP
-  return hipGetLastError();
-}
-
-template <int ST>
-static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
-  using T = typename Store<ST>::T;
-  const int block = h.block;
-  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
-  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
-  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)src + (int64_t)a * h.stride;
-    P.dst[a] = nullptr;
-  }
-  const dim3 grid((unsigned)nb), blk(block);
-  switch (h.k.aa ? 2 : gather_kind(h)) {  // the AA layout keeps natural order: general slot rule
-    case 0: hipLaunchKernelGGL((k_density<ST, 0>), grid, blk, 0, st, P, drho, h.k, bpr); break;
-    case 1: hipLaunchKernelGGL((k_density<ST, 1>), grid, blk, 0, st, P, drho, h.k, bpr); break;
-    default: hipLaunchKernelGGL((k_density<ST, 2>), grid, blk, 0, st, P, drho, h.k, bpr); break;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force,
                        const float* grad_src, float* drho_out, hipStream_t st) {
   switch (h.p.storage) {
-    case LBM_F32: return launch_step_t<0>(h, src, dst, force, grad_src, drho_out, st);
-    case LBM_F16: return launch_step_t<1>(h, src, dst, force, grad_src, drho_out, st);
-    default: return launch_step_t<2>(h, src, dst, force, grad_src, drho_out, st);
+    case LBM_F32: return StepKernels<0>::step(h, src, dst, force, grad_src, drho_out, st);
+    case LBM_F16: return StepKernels<1>::step(h, src, dst, force, grad_src, drho_out, st);
+    default: return StepKernels<2>::step(h, src, dst, force, grad_src, drho_out, st);
   }
-}
-
-template <int ST>
-static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st) {
-  using T = typename Store<ST>::T;
-  const int block = h.block;
-  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
-  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
-  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)state + (int64_t)a * h.stride;
-    P.dst[a] = (T*)state + (int64_t)a * h.stride;
-  }
-  const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  const dim3 grid((unsigned)nb), blk(block);
-#define CLBM_AA(C, O, W, R) hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R>), grid, blk, 0, st, P, force, h.k, bpr)
-#define CLBM_AA_CORR(O, W, R)                 \
-  switch (h.p.corr) {                         \
-    case 0: CLBM_AA(0, O, W, R); break;       \
-    case 1: CLBM_AA(1, O, W, R); break;       \
-    default: CLBM_AA(2, O, W, R); break;      \
-  }
-#define CLBM_AA_RAW(O, W) \
-  if (h.p.moments == LBM_RAW) { CLBM_AA_CORR(O, W, true) } else { CLBM_AA_CORR(O, W, false) }
-  if (odd) {
-    if (walls) { CLBM_AA_RAW(true, true) } else { CLBM_AA_RAW(true, false) }
-  } else {
-    if (walls) { CLBM_AA_RAW(false, true) } else { CLBM_AA_RAW(false, false) }
-  }
-#undef CLBM_AA_RAW
-#undef CLBM_AA_CORR
-#undef CLBM_AA
-  return hipGetLastError();
 }
 
 hipError_t launch_step_aa(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st) {
   switch (h.p.storage) {
-    case LBM_F32: return launch_step_aa_t<0>(h, state, odd, force, st);
-    case LBM_F16: return launch_step_aa_t<1>(h, state, odd, force, st);
-    default: return launch_step_aa_t<2>(h, state, odd, force, st);
+    case LBM_F32: return StepKernels<0>::step_aa(h, state, odd, force, st);
+    case LBM_F16: return StepKernels<1>::step_aa(h, state, odd, force, st);
+    default: return StepKernels<2>::step_aa(h, state, odd, force, st);
   }
 }
 
@@ -525,9 +208,9 @@ hipError_t launch_step_aa_uniform(const lbm_handle& h, void* state, int odd, flo
 
 hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
   switch (h.p.storage) {
-    case LBM_F32: return launch_density_t<0>(h, src, drho, st);
-    case LBM_F16: return launch_density_t<1>(h, src, drho, st);
-    default: return launch_density_t<2>(h, src, drho, st);
+    case LBM_F32: return StepKernels<0>::density(h, src, drho, st);
+    case LBM_F16: return StepKernels<1>::density(h, src, drho, st);
+    default: return StepKernels<2>::density(h, src, drho, st);
   }
 }
 

@@ -20,6 +20,28 @@ struct lbm_handle {
 
 namespace clbm {
 
+// Step and adjoint-step launchers per storage type (0 FP32, 1 FP16, 2 BF16);
+// each is instantiated in a translation unit of its own.
+template <int ST>
+struct StepKernels {
+  static hipError_t step(const lbm_handle& h, const void* src, void* dst, const float* force,
+                         const float* grad_src, float* drho_out, hipStream_t st);
+  static hipError_t step_aa(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st);
+  static hipError_t density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
+};
+extern template struct StepKernels<0>;
+extern template struct StepKernels<1>;
+extern template struct StepKernels<2>;
+
+template <int ST>
+struct AdjointKernels {
+  static hipError_t step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
+                         const float* force, float* grad_force, double* grad_uniform, hipStream_t st);
+};
+extern template struct AdjointKernels<0>;
+extern template struct AdjointKernels<1>;
+extern template struct AdjointKernels<2>;
+
 hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const float* force,
                        const float* grad_src, float* drho_out, hipStream_t st);
 // Same with the uniform force replaced for this launch only.

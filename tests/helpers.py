@@ -21,6 +21,7 @@ def gpu_lattice(p, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0):
     """HIP lattice with the same parameters as the oracle Params ``p``."""
     import paper_2107_14774_amd as P
     return P.Lattice(p.nx, p.ny, p.nz, r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi,
+                     omega_hi=p.omega_hi,
                      bc_x=p.bc_x, bc_y=p.bc_y, bc_z=p.bc_z, storage=storage, corr=p.corr, rho0=rho0,
                      force=force, wall_velocity=p.wall_velocity, moments=p.moments)
 

@@ -40,7 +40,8 @@ def test_create_sizes_and_padding():
     (dict(nx=0), "grid sizes"),
     (dict(omega_nu=2.0), "omega"),
     (dict(omega_xi=0.0), "omega"),
-    (dict(omega_hi=1.2), "omega_hi"),
+    (dict(omega_hi=2.0), "omega_hi"),
+    (dict(omega_hi=0.0), "omega_hi"),
     (dict(r=-1.0), "r and s"),
     (dict(cs2=0.5, s=0.5), "cs2"),
     (dict(rho0=0.0), "rho0"),

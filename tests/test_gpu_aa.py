@@ -24,7 +24,8 @@ def _say(*a):
 
 def _lattices(p, storage, force=Z3):
     import paper_2107_14774_amd as P
-    kw = dict(r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi, bc_x=p.bc_x, bc_y=p.bc_y,
+    kw = dict(r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi, omega_hi=p.omega_hi,
+              bc_x=p.bc_x, bc_y=p.bc_y,
               bc_z=p.bc_z, storage=storage, corr=p.corr, force=force, wall_velocity=p.wall_velocity, moments=p.moments)
     return P.Lattice(p.nx, p.ny, p.nz, **kw), P.Lattice(p.nx, p.ny, p.nz, layout="aa", **kw)
 
@@ -39,15 +40,20 @@ CASES = [
     ("periodic_f16_lowmach", (70, 9, 6), 0.5, 0.25, ("periodic",) * 3, None, "lowmach", "central", "f16", False),
     ("cavity_raw_bf16", (12, 16, 12), 0.75, 1.0, ("bounceback",) * 3,
      ((0, 0, 0),) * 3 + ((0.06, 0, 0),) + ((0, 0, 0),) * 2, "off", "raw", "bf16", False),
+    # general higher-order rate (last field)
+    ("duct_field_f32_omega_hi", (37, 12, 10), 1.0, 0.25, ("periodic", "bounceback", "bounceback"), None, "local",
+     "central", "f32", True, 1.6),
+    ("periodic_f16_raw_omega_hi", (70, 9, 6), 0.5, 0.25, ("periodic",) * 3, None, "lowmach", "raw", "f16", False, 0.7),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_aa_layout_equals_ab_bit_for_bit(case):
-    name, (nx, ny, nz), r, s, (bx, by, bz), wv, corr, moments, storage, field = case
+    name, (nx, ny, nz), r, s, (bx, by, bz), wv, corr, moments, storage, field = case[:10]
+    omega_hi = case[10] if len(case) > 10 else 1.0
     _say("case", name)
-    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.2, corr=corr, bc_x=bx, bc_y=by, bc_z=bz,
-                      wall_velocity=wv or ((0, 0, 0),) * 6, moments=moments)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.2, omega_hi=omega_hi, corr=corr, bc_x=bx,
+                      bc_y=by, bc_z=bz, wall_velocity=wv or ((0, 0, 0),) * 6, moments=moments)
     f0 = fp32_rounded_state(random_state(p, 23), p)
     g = np.random.Generator(np.random.PCG64(24))
     force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda() if field else None
