@@ -22,9 +22,12 @@ namespace clbm {
 // the unit-rate collision.
 // WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
 // offsets from direction 0's array (state below 4 GiB), 2 walls, 64-bit slots.
+// 16-bit populations are read with non-temporal loads (measured faster for
+// them only).
 template <int ST, int WALLS>
 __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
                                             const Consts& k, float (&df)[27]) {
+  constexpr bool NT = ST != 0;
   if constexpr (WALLS == 2) {
     gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
   } else {
@@ -32,9 +35,9 @@ __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>
     periodic_rows(x, y, z, k, pr);
     if constexpr (WALLS == 1) {
       const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-      gather_walls32<ST>(P.src[0], pr, node, wall_flags(x, y, z, k), k, df);
+      gather_walls32<ST, NT>(P.src[0], pr, node, wall_flags(x, y, z, k), k, df);
     } else {
-      gather_periodic<ST>(P.src, pr, k, df);
+      gather_periodic<ST, NT>(P.src, pr, k, df);
     }
   }
 }
@@ -136,16 +139,17 @@ template <int ST, bool ODD, bool WALLS, int A = 0>
 __device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
                                           const WallFlags& w, const Consts& k, float (&df)[27]) {
   constexpr int opp = opposite_of(A);
+  constexpr bool NT = ST != 0;
   typename Store<ST>::T v;
   if constexpr (!ODD) {
-    v = ld_off(P.src[A], node);
+    v = ld_pop<NT>(P.src[A], node);
   } else if constexpr (WALLS) {
     const uint32_t stride = (uint32_t)k.stride;
     const uint32_t idx = pulls_through_wall<A>(w) ? (uint32_t)A * stride + node
                                                   : (uint32_t)opp * stride + periodic_src<A>(pr);
-    v = ld_off(P.src[0], idx);
+    v = ld_pop<NT>(P.src[0], idx);
   } else {
-    v = ld_off(P.src[opp], periodic_src<A>(pr));
+    v = ld_pop<NT>(P.src[opp], periodic_src<A>(pr));
   }
   const float f = Store<ST>::load_val(v);
   df[A] = ST == 0 ? f : f * k.inv_sigma[A];
