@@ -566,9 +566,8 @@ __device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t idx) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
 
-// Non-temporal variant of ld_off (populations read once per step).  Measured on
-// the 16-bit forward step: +3.5% at 512x512x256; slower for FP32 (-1.8%) and
-// for the adjoint's state gather (-5.6%), which keep ld_off.
+// Non-temporal variant of ld_off, for population lines that no other wave reads
+// in the same step.
 template <typename T>
 __device__ __forceinline__ T ld_off_nt(const T* __restrict__ base, uint32_t idx) {
   const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
@@ -661,19 +660,27 @@ __device__ __forceinline__ uint32_t wall_slot32(const PeriodicRows& pr, uint32_t
   return wall ? (uint32_t)opp * stride + node : (uint32_t)A * stride + periodic_src<A>(pr);
 }
 
-// NT: non-temporal loads (ld_off_nt)
-template <int ST, bool NT = false, int A = 0>
+// NT: 0 plain loads; 1 non-temporal loads; 2 non-temporal loads for the
+// directions with ebar_x = 0 only.  A wave reads whole aligned lines for those;
+// the x-shifted directions straddle lines that the neighbouring wave reads too,
+// which plain loads keep in L2.
+template <int NT>
+constexpr bool nt_dir(int a) {
+  return NT == 1 || (NT == 2 && kEx[a] == 0);
+}
+
+template <int ST, int NT = 0, int A = 0>
 __device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const PeriodicRows& pr,
                                                uint32_t node, const WallFlags& w, const Consts& k, float (&df)[27]) {
-  const float v = Store<ST>::load_val(ld_pop<NT>(base, wall_slot32<A>(pr, node, w, k)));
+  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(base, wall_slot32<A>(pr, node, w, k)));
   df[A] = ST == 0 ? v : v * k.inv_sigma[A];
   if constexpr (A + 1 < 27) gather_walls32<ST, NT, A + 1>(base, pr, node, w, k, df);
 }
 
-template <int ST, bool NT = false, int A = 0>
+template <int ST, int NT = 0, int A = 0>
 __device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* const (&src)[27], const PeriodicRows& pr,
                                                 const Consts& k, float (&df)[27]) {
-  const float v = Store<ST>::load_val(ld_pop<NT>(src[A], periodic_src<A>(pr)));
+  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(src[A], periodic_src<A>(pr)));
   df[A] = ST == 0 ? v : v * k.inv_sigma[A];
   if constexpr (A + 1 < 27) gather_periodic<ST, NT, A + 1>(src, pr, k, df);
 }

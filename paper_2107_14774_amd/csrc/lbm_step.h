@@ -22,12 +22,11 @@ namespace clbm {
 // the unit-rate collision.
 // WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
 // offsets from direction 0's array (state below 4 GiB), 2 walls, 64-bit slots.
-// 16-bit populations are read with non-temporal loads (measured faster for
-// them only).
+// The directions with ebar_x = 0 are read with non-temporal loads (nt_dir).
 template <int ST, int WALLS>
 __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
                                             const Consts& k, float (&df)[27]) {
-  constexpr bool NT = ST != 0;
+  constexpr int NT = 2;
   if constexpr (WALLS == 2) {
     gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
   } else {
@@ -139,7 +138,9 @@ template <int ST, bool ODD, bool WALLS, int A = 0>
 __device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
                                           const WallFlags& w, const Consts& k, float (&df)[27]) {
   constexpr int opp = opposite_of(A);
-  constexpr bool NT = true;  // non-temporal loads: measured +0.6% (FP32) and +8.5% (FP16) here
+  // even steps read the node's own slots (no line shared between waves): all non-temporal;
+  // odd steps as the two-buffer gather
+  constexpr bool NT = !ODD || kEx[A] == 0;
   typename Store<ST>::T v;
   if constexpr (!ODD) {
     v = ld_pop<NT>(P.src[A], node);
