@@ -288,15 +288,19 @@ struct AdjPtrs {
 template <int A = 0>
 __device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const PeriodicRows& pr, uint32_t node,
                                                 const WallFlags& w, const Consts& k, const float (&mu)[27]) {
-  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (uint32_t)(wall_slot32<A>(pr, node, w, k) * 4u)) = mu[A];
+  const uint32_t idx = wall_slot32<A>(pr, node, w, k);
+  if constexpr (kEx[A] == 0) st_off_nt(base, idx, mu[A]);
+  else *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + idx * 4u) = mu[A];
   if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, pr, node, w, k, mu);
 }
 
 template <int A = 0>
 __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const PeriodicRows& pr,
                                                  const float (&mu)[27]) {
-  // plain stores: the shifted scatter writes partial lines that L2 merges with the neighbours'
-  *reinterpret_cast<float*>(reinterpret_cast<char*>(dst[A]) + (uint32_t)(periodic_src<A>(pr) * 4u)) = mu[A];
+  // the x-shifted scatter writes partial lines that L2 merges with the neighbours' (plain
+  // stores); the directions with ebar_x = 0 write whole lines (non-temporal stores)
+  if constexpr (kEx[A] == 0) st_off_nt(dst[A], periodic_src<A>(pr), mu[A]);
+  else *reinterpret_cast<float*>(reinterpret_cast<char*>(dst[A]) + (uint32_t)(periodic_src<A>(pr) * 4u)) = mu[A];
   if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
 }
 

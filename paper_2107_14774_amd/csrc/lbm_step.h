@@ -174,11 +174,13 @@ __device__ __forceinline__ void store_aa(const DirPtrs<typename Store<ST>::T>& P
     const uint32_t stride = (uint32_t)k.stride;
     const uint32_t idx = pulls_through_wall<opp>(w) ? (uint32_t)opp * stride + node
                                                     : (uint32_t)A * stride + periodic_src<opp>(pr);
-    st_off(P.dst[0], idx, v);
+    if constexpr (kEx[A] == 0) st_off_nt(P.dst[0], idx, v);
+    else st_off(P.dst[0], idx, v);
   } else {
-    // shifted by one node along x for most directions: plain stores, partial lines merge in L2
-    // (non-temporal stores measured 0-1.5% slower here)
-    st_off(P.dst[A], periodic_src<opp>(pr), v);
+    // shifted by one node along x for 18 directions: plain stores, partial lines merge in L2;
+    // the 9 with ebar_x = 0 write whole lines: non-temporal stores
+    if constexpr (kEx[A] == 0) st_off_nt(P.dst[A], periodic_src<opp>(pr), v);
+    else st_off(P.dst[A], periodic_src<opp>(pr), v);
   }
   if constexpr (A + 1 < 27) store_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, out);
 }
