@@ -16,6 +16,7 @@ struct lbm_handle {
   size_t elem;       // bytes per stored element
   size_t bytes;      // bytes of one state
   int block;         // threads per block of the node kernels
+  int block_step;    // threads per block of the FP32 step without full corrections
 };
 
 namespace clbm {

@@ -246,7 +246,7 @@ template <int ST, bool HI>
 static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst, const float* force,
                                 const float* grad_src, float* drho_out, hipStream_t st) {
   using T = typename Store<ST>::T;
-  const int block = h.block;
+  const int block = h.p.corr == LBM_CORR_FULL ? h.block : h.block_step;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
@@ -305,7 +305,7 @@ static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* 
 template <int ST, bool HI>
 static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st) {
   using T = typename Store<ST>::T;
-  const int block = h.block;
+  const int block = h.block_step;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
