@@ -106,7 +106,7 @@ def test_large_duct_step_matches_oracle(storage, nz):
     ft = C.collide(fs, force, p)
     want = ft[torch.arange(fs.shape[0]), torch.from_numpy(comp.ravel())].reshape(got.shape)
     err = (got - want).abs().max().item()
-    dev = (want - ft.new_tensor(_rest_weights(p))).abs().max().item()
+    dev = (want - _rest_weights(p).to(want.dtype)).abs().max().item()
     nwall = int(wall.any(1).sum())
     _say(f"512x512x{NZ} duct {storage} (state {lat.h.state_bytes / 2**30:.2f} GiB), one step, {len(zs)} sampled "
          f"nodes ({nwall} next to a wall): max |f_gpu - f_oracle| = {err:.3e} (max deviation {dev:.2e})")
