@@ -6,8 +6,9 @@
  * populations of a node (streaming, Sec. 3.2), takes raw moments (App. A),
  * scales them by the grid aspect ratios r, s (App. B, eq. 59), shifts them to
  * central moments about the force-shifted velocity of eq. 12 (App. C),
- * relaxes them with the shear rate omega_nu, the bulk rate omega_xi and unit
- * rates for every higher order, using the extended equilibria whose
+ * relaxes them with the shear rate omega_nu, the bulk rate omega_xi and one
+ * rate omega_hi for every higher order (1 in the paper), using the extended
+ * equilibria whose
  * corrections cancel the grid-anisotropy and non-Galilean-invariant errors
  * (Sec. 2.4, eq. 38-40) with strain rates from the local system of App. D
  * (eq. 44-49), adds the body force through eq. 11c, and maps back (App. E-G).
@@ -259,8 +260,8 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *               for a per-node force field
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
- * Moving walls (their terms depend on the node's density) and the raw-moment
- * scheme are included.  Not implemented for the full corrections or the AA
+ * Moving walls (their terms depend on the node's density), the raw-moment
+ * scheme and a general omega_hi are included.  Not implemented for the full corrections or the AA
  * layout (LBM_EINVAL; also for the other adjoint entry points below). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
