@@ -260,7 +260,8 @@ def cpu_baseline(w):
 
 # ---------------------------------------------------------------------- rocprofv3 summaries
 PROFILE_KERNELS = {
-    "f32": "k_step<0, 2, 0, false, false>", "f16": "k_step<1, 2, 0, false, false>", "bf16": "k_step<2, 2, 0, false, false>",
+    "f32": "k_step<0, 2, 0, false, false>", "f16": "k_step_pair<1, 2, false, false>",
+    "bf16": "k_step_pair<2, 2, false, false>",
     "full_f32": "k_step<0, 3, 0, false, false>", "full_f16": "k_step<1, 3, 0, false, false>",
     "aa_f32 (local)": "k_step_aa<0, 2, false, false, false, false>", "aa_f32 (shifted)": "k_step_aa<0, 2, true, false, false, false>",
     "aa_f16 (local)": "k_step_aa<1, 2, false, false, false, false>", "aa_f16 (shifted)": "k_step_aa<1, 2, true, false, false, false>",

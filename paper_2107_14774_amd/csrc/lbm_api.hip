@@ -110,6 +110,8 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   };
   h->block = pick_block({256, 192, 128, 64});
   h->block_step = q.storage == LBM_F32 ? pick_block({128, 256, 192, 64}) : h->block;
+  h->pairs = 1;
+  if (const char* env = std::getenv("LBM_PAIRS")) h->pairs = std::atoi(env) != 0;  // 0: one node per thread
   if (const char* env = std::getenv("LBM_BLOCK")) {
     const int b = std::atoi(env);
     if (b == 64 || b == 128 || b == 192 || b == 256) h->block = h->block_step = b;

@@ -74,11 +74,19 @@ template <> struct Store<0> {
   static __device__ __forceinline__ T pack(float v) { return v; }
 };
 
+// 16-bit formats also convert from / to the raw 16 bits (the pair step keeps
+// two nodes' values in one 32-bit word), with the same conversions.
 template <> struct Store<1> {
   using T = __half;
   static __device__ __forceinline__ float load(const T* p) { return __half2float(*p); }
   static __device__ __forceinline__ float load_val(T v) { return __half2float(v); }
   static __device__ __forceinline__ T pack(float v) { return __float2half_rn(v); }
+  static __device__ __forceinline__ float from_bits(uint32_t b) {
+    return __half2float(__builtin_bit_cast(__half, (unsigned short)b));
+  }
+  static __device__ __forceinline__ uint32_t to_bits(float v) {
+    return __builtin_bit_cast(unsigned short, __float2half_rn(v));
+  }
 };
 
 template <> struct Store<2> {
@@ -86,6 +94,12 @@ template <> struct Store<2> {
   static __device__ __forceinline__ float load(const T* p) { return __bfloat162float(*p); }
   static __device__ __forceinline__ float load_val(T v) { return __bfloat162float(v); }
   static __device__ __forceinline__ T pack(float v) { return __float2bfloat16(v); }
+  static __device__ __forceinline__ float from_bits(uint32_t b) {
+    return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, (unsigned short)b));
+  }
+  static __device__ __forceinline__ uint32_t to_bits(float v) {
+    return __builtin_bit_cast(unsigned short, __float2bfloat16(v));
+  }
 };
 
 // ----------------------------------------------------------------- indexing

@@ -17,6 +17,7 @@ struct lbm_handle {
   size_t bytes;      // bytes of one state
   int block;         // threads per block of the node kernels
   int block_step;    // threads per block of the FP32 step without full corrections
+  int pairs;         // 1 = the periodic 16-bit step may run two nodes per thread
 };
 
 namespace clbm {
