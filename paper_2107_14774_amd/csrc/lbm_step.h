@@ -283,6 +283,98 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(DirPtrs<t
   store_aa<ST, ODD, WALLS>(P, pr, node, w, k, out);
 }
 
+// 16-bit AA step with two x-adjacent nodes per thread (periodic grids, even nx;
+// the pairing of k_step_pair).  Even steps read and write whole words of the
+// node pair's own slots.  Odd steps gather like k_step_pair from the opposite
+// directions' arrays; their x-shifted outputs land in words that two threads
+// share, so those go out as 2-byte stores.
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_aa_pair(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr,
+                                               uint32_t t, uint32_t tm, uint32_t tp, bool odd, uint32_t (&w)[27]) {
+  constexpr int ex = kEx[A];
+  if (!odd) {
+    w[A] = ld_off_nt(reinterpret_cast<const uint32_t*>(P.src[A]), pr.row[1][1] / 2 + t);
+  } else {
+    const uint32_t* base = reinterpret_cast<const uint32_t*>(P.src[opposite_of(A)]);
+    const uint32_t row = pr.row[kEy[A] + 1][kEz[A] + 1] / 2;
+    if constexpr (ex == 0) {
+      w[A] = ld_off_nt(base, row + t);
+    } else if constexpr (ex > 0) {
+      const uint32_t own = ld_off(base, row + t), prev = ld_off(base, row + tm);
+      w[A] = (prev >> 16) | (own << 16);
+    } else {
+      const uint32_t own = ld_off(base, row + t), next = ld_off(base, row + tp);
+      w[A] = (own >> 16) | (next << 16);
+    }
+  }
+  if constexpr (A + 1 < 27) gather_aa_pair<ST, A + 1>(P, pr, t, tm, tp, odd, w);
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void store_aa_pair(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr,
+                                              uint32_t t, uint32_t tm, uint32_t tp, bool odd, const uint32_t (&o)[27]) {
+  constexpr int ex = kEx[A];
+  if (!odd) {
+    st_off_nt(reinterpret_cast<uint32_t*>(P.dst[opposite_of(A)]), pr.row[1][1] / 2 + t, o[A]);
+  } else {
+    // f~_A of nodes 2t, 2t + 1 goes to (A, x + ebar_A)
+    const uint32_t row = pr.row[1 - kEy[A]][1 - kEz[A]];       // row y + ey, z + ez (element index)
+    if constexpr (ex == 0) {
+      st_off_nt(reinterpret_cast<uint32_t*>(P.dst[A]), row / 2 + t, o[A]);
+    } else {
+      unsigned short* base = reinterpret_cast<unsigned short*>(P.dst[A]);
+      const uint32_t lo = o[A] & 0xffffu, hi = o[A] >> 16;
+      if constexpr (ex > 0) {                                    // positions 2t + 1, 2t + 2
+        st_off(base, row + 2 * t + 1, (unsigned short)lo);
+        st_off(base, row + 2 * tp, (unsigned short)hi);
+      } else {                                                   // positions 2t - 1, 2t
+        st_off(base, row + 2 * tm + 1, (unsigned short)lo);
+        st_off(base, row + 2 * t, (unsigned short)hi);
+      }
+    }
+  }
+  if constexpr (A + 1 < 27) store_aa_pair<ST, A + 1>(P, pr, t, tm, tp, odd, o);
+}
+
+template <int ST, int CORR, bool ODD, bool RAW, bool HI>
+__global__ __launch_bounds__(256) void k_step_aa_pair(DirPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
+                                                      Consts k, uint32_t bpr) {
+  static_assert(ST != 0, "two nodes per thread is the 16-bit path");
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const uint32_t tpr = (uint32_t)k.nx / 2;
+  const uint32_t t = bxi * blockDim.x + threadIdx.x;
+  if (t >= tpr) return;
+  const uint32_t tm = t == 0 ? tpr - 1 : t - 1, tp = t + 1 == tpr ? 0 : t + 1;
+  PeriodicRows pr;
+  periodic_rows((int)(2 * t), y, z, k, pr);
+  uint32_t w[27];
+  gather_aa_pair<ST>(P, pr, t, tm, tp, ODD, w);
+  const uint32_t node0 = pr.row[1][1] + 2 * t;
+  uint32_t o[27];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float df[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[a];
+    float fx = k.fx, fy = k.fy, fz = k.fz;
+    if (force != nullptr) {
+      fx = ld_off(force, node0 + h);
+      fy = ld_off(force + k.n, node0 + h);
+      fz = ld_off(force + 2 * k.n, node0 + h);
+    }
+    float out[27];
+    collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) {
+      const uint32_t bits = Store<ST>::to_bits(out[a] * k.sigma[a]);
+      o[a] = h ? (o[a] | (bits << 16)) : bits;
+    }
+  }
+  store_aa_pair<ST>(P, pr, t, tm, tp, ODD, o);
+}
+
 // Density deviation of every node of a state: the same gather and the same
 // FP32 sum as the step, so the value is bit-identical to the step's.
 template <int ST, int WALLS>
@@ -400,6 +492,25 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
     P.dst[a] = (T*)state + (int64_t)a * h.stride;
   }
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
+  if constexpr (ST != 0) {
+    if (!walls && h.pairs && h.p.nx % 2 == 0) {
+      constexpr int pblock = 128;
+      const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);
+      const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
+      if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+      const dim3 pgrid((unsigned)pnb), pblk(pblock);
+#define CLBM_AAP(C, O, R) hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, 0, st, P, force, h.k, pbpr)
+#define CLBM_AAP_R(C, O) if (h.p.moments == LBM_RAW) CLBM_AAP(C, O, true); else CLBM_AAP(C, O, false)
+      switch (h.p.corr) {
+        case 0: if (odd) { CLBM_AAP_R(0, true); } else { CLBM_AAP_R(0, false); } break;
+        case 1: if (odd) { CLBM_AAP_R(1, true); } else { CLBM_AAP_R(1, false); } break;
+        default: if (odd) { CLBM_AAP_R(2, true); } else { CLBM_AAP_R(2, false); } break;
+      }
+#undef CLBM_AAP_R
+#undef CLBM_AAP
+      return hipGetLastError();
+    }
+  }
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_AA(C, O, W, R) hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R, HI>), grid, blk, 0, st, P, force, h.k, bpr)
 #define CLBM_AA_CORR(O, W, R)                 \

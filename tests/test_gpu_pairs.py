@@ -1,8 +1,10 @@
-"""GPU check of the 16-bit step that runs two x-adjacent nodes per thread
-(periodic grids with even nx): it gathers the same values and runs the same
-collision as the one-node kernel (selected with LBM_PAIRS=0), so the states
-must agree bit for bit; and it must match the FP64 oracle like that kernel."""
+"""GPU check of the 16-bit steps that run two x-adjacent nodes per thread
+(periodic grids with even nx, two-buffer and AA layouts): they gather the same
+values and run the same collision as the one-node kernels (selected with
+LBM_PAIRS=0), so the states must agree bit for bit; and the two-buffer step
+must match the FP64 oracle like the one-node kernel."""
 
+import contextlib
 import os
 import sys
 
@@ -23,16 +25,23 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _lattice(p, storage, force, pairs):
+@contextlib.contextmanager
+def _pairs(enabled):
+    """LBM_PAIRS is read when a handle is created."""
     old = os.environ.get("LBM_PAIRS")
-    os.environ["LBM_PAIRS"] = "1" if pairs else "0"
+    os.environ["LBM_PAIRS"] = "1" if enabled else "0"
     try:
-        return gpu_lattice(p, storage=storage, force=force)
+        yield
     finally:
         if old is None:
             del os.environ["LBM_PAIRS"]
         else:
             os.environ["LBM_PAIRS"] = old
+
+
+def _lattice(p, storage, force, pairs):
+    with _pairs(pairs):
+        return gpu_lattice(p, storage=storage, force=force)
 
 
 CASES = [
@@ -80,3 +89,38 @@ def test_pair_step_equals_one_node_step(case):
     _say(f"{name}: one pair step vs FP64 oracle: max error {err:.2e} (max deviation {dev:.2e})")
     bound = 2e-3 if storage == "f16" else 1.6e-2       # 11 / 8 significand bits on the deviations
     assert err < bound * dev
+
+
+AA_CASES = [
+    ("aa_ragged_local_f16", (300, 6, 5), 1.0, 0.5, "local", "central", 1.0, "f16", True),
+    ("aa_raw_lowmach_bf16", (70, 8, 6), 0.5, 0.25, "lowmach", "raw", 1.3, "bf16", False),
+    ("aa_two_wide_f16", (2, 5, 4), 1.0, 0.5, "off", "central", 1.0, "f16", True),
+]
+
+
+@pytest.mark.parametrize("case", AA_CASES, ids=[c[0] for c in AA_CASES])
+def test_aa_pair_step_equals_one_node_step(case):
+    """The in-place (AA) 16-bit step with two nodes per thread against its one-node kernel."""
+    import paper_2107_14774_amd as P
+    name, (nx, ny, nz), r, s, corr, moments, omega_hi, storage, field = case
+    _say("case", name)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.3, omega_xi=1.1, omega_hi=omega_hi, corr=corr,
+                      moments=moments)
+    f0 = random_state(p, 73)
+    g = np.random.Generator(np.random.PCG64(74))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda() if field else None
+    kw = dict(r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi, omega_hi=p.omega_hi,
+              storage=storage, corr=p.corr, moments=p.moments, force=(2e-6, 1e-6, -3e-6), layout="aa")
+    with _pairs(False):
+        one = P.Lattice(nx, ny, nz, **kw)
+    with _pairs(True):
+        two = P.Lattice(nx, ny, nz, **kw)
+    s1, s2 = one.new_state(), two.new_state()
+    one.import_populations(s1, f0.cuda())
+    two.import_populations(s2, f0.cuda())
+    for n in (2, 6):
+        s1, _ = one.step(s1, None, n, force)
+        s2, _ = two.step(s2, None, n, force)
+        f1, f2 = one.export_populations(s1), two.export_populations(s2)
+        _say(f"{name}: max |pairs - one node| = {(f1 - f2).abs().max().item():.3e}")
+        assert torch.equal(f1, f2)
