@@ -285,8 +285,11 @@ TRACE_SUMMARY = "profiles/k_step_and_adjoint_kernel_trace.txt"
 TRAFFIC_SUMMARY = "profiles/k_step_and_adjoint_hbm_traffic.txt"
 
 
-def _launch_grid(nx, ny, nz):
-    """Total threads of a node-kernel launch (the library's block-width rule)."""
+def _launch_grid(nx, ny, nz, kernel=""):
+    """Total threads of a node-kernel launch (the library's block-width rule; the 16-bit
+    two-nodes-per-thread kernels run nx / 2 threads per row in blocks of 128)."""
+    if "_pair<" in kernel:
+        return str((nx // 2 + 127) // 128 * 128 * ny * nz)
     best, waste = 256, 1 << 30
     for b in (256, 192, 128, 64):
         w = (nx + b - 1) // b * b - nx
@@ -313,7 +316,7 @@ def summarize_rocprof(out_dir):
              "MLUPS(avg)  alg_B/LUP  alg_GB/s  frac_of_8TB/s"]
     for v, key in PROFILE_KERNELS.items():
         nx, ny, nz, label = PROFILE_WORKLOADS[v]
-        grid = _launch_grid(nx, ny, nz)
+        grid = _launch_grid(nx, ny, nz, key)
         d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
              if key in r["Kernel_Name"] and r["Grid_Size_X"] == grid]
         if not d:
@@ -348,7 +351,7 @@ def summarize_rocprof(out_dir):
     traffic = {}
     for v, key in PROFILE_KERNELS.items():
         nx, ny, nz, _ = PROFILE_WORKLOADS[v]
-        grid = _launch_grid(nx, ny, nz)
+        grid = _launch_grid(nx, ny, nz, key)
         fv = [float(r["Counter_Value"]) for r in fe if key in r["Kernel_Name"] and r["Grid_Size"] == grid]
         wv = [float(r["Counter_Value"]) for r in wr if key in r["Kernel_Name"] and r["Grid_Size"] == grid]
         if not fv or not wv:
