@@ -124,4 +124,3 @@ def test_aa_pair_step_equals_one_node_step(case):
         f1, f2 = one.export_populations(s1), two.export_populations(s2)
         _say(f"{name}: max |pairs - one node| = {(f1 - f2).abs().max().item():.3e}")
         assert torch.equal(f1, f2)
-
