@@ -232,7 +232,8 @@ def lat_n(w):
 
 
 def cpu_baseline(w):
-    """FP64 oracle on a 64x64x32 replica of the workload, a few steps, all host cores."""
+    """FP64 oracle on a 64x64x32 replica of the workload: 24 steps on all host cores (about 15 s),
+    then 2 steps on one thread."""
     import oracle
     from oracle import analytic as A
     from oracle import lbm as OL
@@ -246,16 +247,28 @@ def cpu_baseline(w):
                       + W.random_modes(rep.nx, rep.ny, rep.nz, rep.r, rep.s, 2, rep.extra["rms"], rep.extra["seed"]))
     f = OL.init_equilibrium(torch.ones(p.shape, dtype=torch.float64), u0, p)
     f = OL.step(f, p)
-    steps = 12
+    steps = 24
     t0 = time.perf_counter()
     for _ in range(steps):
         f = OL.step(f, p)
     dt = time.perf_counter() - t0
     val = p.n * steps / dt / 1e6
-    log(f"[bench] cpu oracle: {val:.4f} MLUPS on {cores} threads ({dt:.1f} s)")
-    return {"value": val, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+    used = torch.get_num_threads()
+    log(f"[bench] cpu oracle: {val:.4f} MLUPS on {used} threads ({dt:.1f} s)")
+    torch.set_num_threads(1)
+    steps1 = 2
+    t0 = time.perf_counter()
+    for _ in range(steps1):
+        f = OL.step(f, p)
+    dt1 = time.perf_counter() - t0
+    val1 = p.n * steps1 / dt1 / 1e6
+    torch.set_num_threads(cores)
+    log(f"[bench] cpu oracle: {val1:.4f} MLUPS on 1 thread ({dt1:.1f} s)")
+    return {"value": val, "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"FP64 oracle, {steps} steps of the {rep.nx}x{rep.ny}x{rep.nz} replica "
-                      f"(r={rep.r}, s={rep.s}, same viscosity), {dt:.1f} s"}
+                      f"(r={rep.r}, s={rep.s}, same viscosity), {dt:.1f} s",
+            "single_thread_value": val1,
+            "single_thread_sample": f"{steps1} steps of the same replica on 1 thread, {dt1:.1f} s"}
 
 
 # ---------------------------------------------------------------------- rocprofv3 summaries
