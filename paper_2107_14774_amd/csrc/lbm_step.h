@@ -14,8 +14,10 @@ namespace clbm {
 // along x, non-temporal).  Without walls every source slot is
 // (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
 // base pointer plus a 32-bit node index shared by the three directions of
-// one source row; with walls the general slot rule of gather_slot applies.
-// With the full corrections (CORR 3) the density gradient comes from the
+// one source row; with walls the slot rule of gather_slot applies (as 32-bit
+// offsets from direction 0's array below 4 GiB, wall_slot32).  Periodic
+// 16-bit grids with even nx run k_step_pair below instead, unless they use the
+// full corrections.  With the full corrections (CORR 3) the density gradient comes from the
 // density-deviation field grad_src, and drho_out (if not NULL) receives the
 // node's own density deviation.
 // HI: general rate of the moments of order >= 3 (k.omega_hi); false compiles
