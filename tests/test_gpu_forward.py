@@ -132,7 +132,7 @@ def taylor_green_oracle():
 
 
 def test_taylor_green_fp32_within_1e5(taylor_green_oracle):
-    """North-star gate: FP32 GPU vs FP64 oracle, relative L2 of u after 200 steps <= 1e-5."""
+    """Accuracy gate: FP32 GPU vs FP64 oracle, relative L2 of u after 200 steps <= 1e-5."""
     rho_o, u_o, sums_o = taylor_green_oracle
     _, _, _, m = _taylor_green_run("f32", W.TAYLOR_GREEN_32.steps)
     err = rel_l2(m.u.cpu(), u_o)
