@@ -187,3 +187,28 @@ def test_nonfinite_totals_are_reported():
     with pytest.raises(_lib.LbmError) as e:
         P.lbm_check_sums(m.sums)
     assert e.value.code == _lib.LBM_ENONFINITE
+
+
+def test_zero_steps_leave_the_state_unchanged():
+    """nsteps = 0 is a valid call that launches nothing: two-buffer, AA, full corrections, forcing."""
+    import paper_2107_14774_amd as P
+    p = oracle.Params(12, 8, 6, r=1.0, s=0.5, bc_y="bounceback")
+    f0 = fp32_rounded_state(random_state(p, 11), p)
+    for layout in ("ab", "aa"):
+        lat = P.Lattice(p.nx, p.ny, p.nz, r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi,
+                        bc_y=p.bc_y, layout=layout)
+        a = lat.new_state()
+        b = None if layout == "aa" else lat.new_state()
+        lat.import_populations(a, f0.cuda())
+        before = lat.export_populations(a)
+        cur, _ = lat.step(a, b, 0)
+        assert cur is a and torch.equal(lat.export_populations(cur), before)
+        cur, _ = lat.step_forcing(a, b, np.zeros((0, 3)))
+        assert cur is a and torch.equal(lat.export_populations(cur), before)
+    full = gpu_lattice(oracle.Params(12, 8, 6, r=1.0, s=0.5, corr="full"))
+    a, b = full.new_state(), full.new_state()
+    full.import_populations(a, f0.cuda())
+    before = full.export_populations(a)
+    da = full.density(a)
+    cur, _, d_cur, _ = full.step_full(a, b, 0, da, full.field(1), "lagged")
+    assert cur is a and d_cur is da and torch.equal(full.export_populations(cur), before)
