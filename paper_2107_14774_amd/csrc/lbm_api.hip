@@ -161,8 +161,8 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     kd.w[a] = w;
     // power-of-two scale near 1/w for the 16-bit formats (exact, so it adds no rounding)
     const double sig = q.storage == LBM_F32 ? 1.0 : std::ldexp(1.0, (int)std::lround(-std::log2(w)));
-    k.sigma[a] = (float)sig;
-    k.inv_sigma[a] = (float)(1.0 / sig);
+    k.sigma[clbm::wclass(a)] = (float)sig;          // equal within a weight class
+    k.inv_sigma[clbm::wclass(a)] = (float)(1.0 / sig);
   }
   *out = h;
   return LBM_OK;

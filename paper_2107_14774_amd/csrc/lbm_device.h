@@ -27,6 +27,11 @@ constexpr int opposite_of(int a) {
   return -1;
 }
 
+// Weight class of a direction: which of its components are non-zero.  The
+// weights of eq. 9-10 are products of per-axis factors that depend only on
+// |ebar_d|, so the eight classes carry every distinct weight (and storage scale).
+constexpr int wclass(int a) { return (kEx[a] != 0) + 2 * (kEy[a] != 0) + 4 * (kEz[a] != 0); }
+
 // Direction with components (i-1, j-1, k-1), i, j, k in {0, 1, 2}.
 constexpr int dir_of(int i, int j, int k) {
   for (int a = 0; a < 27; ++a)
@@ -50,8 +55,8 @@ struct Consts {
   float c2[3];             // squared particle speeds 1, r^2, s^2
   float ic[3], ic2[3];     // 1/c, 1/c^2 per axis
   float w0c[3], w0s[3];    // rest weights per axis: centre 1 - cs2/c^2, side cs2/(2 c^2)
-  float sigma[27];         // storage scale per direction
-  float inv_sigma[27];
+  float sigma[8];          // storage scale per weight class (wclass)
+  float inv_sigma[8];
   float omega_hi;          // rate of the moments of order >= 3
   int hi;                  // 1 = omega_hi != 1 (kernels with the general higher-order rate)
 };
@@ -74,8 +79,8 @@ template <> struct Store<0> {
   static __device__ __forceinline__ T pack(float v) { return v; }
 };
 
-// 16-bit formats also convert from / to the raw 16 bits (the pair step keeps
-// two nodes' values in one 32-bit word), with the same conversions.
+// 16-bit formats also convert from the raw 16 bits (the pair steps keep two
+// nodes' values in one 32-bit word), with the same conversion.
 template <> struct Store<1> {
   using T = __half;
   static __device__ __forceinline__ float load(const T* p) { return __half2float(*p); }
@@ -83,9 +88,6 @@ template <> struct Store<1> {
   static __device__ __forceinline__ T pack(float v) { return __float2half_rn(v); }
   static __device__ __forceinline__ float from_bits(uint32_t b) {
     return __half2float(__builtin_bit_cast(__half, (unsigned short)b));
-  }
-  static __device__ __forceinline__ uint32_t to_bits(float v) {
-    return __builtin_bit_cast(unsigned short, __float2half_rn(v));
   }
 };
 
@@ -97,9 +99,35 @@ template <> struct Store<2> {
   static __device__ __forceinline__ float from_bits(uint32_t b) {
     return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, (unsigned short)b));
   }
-  static __device__ __forceinline__ uint32_t to_bits(float v) {
-    return __builtin_bit_cast(unsigned short, __float2bfloat16(v));
+};
+
+// One direction's values of two x-adjacent nodes in the 32-bit word the pair
+// steps store (first node in the low half), filled one node at a time with the
+// same rounding as Store<ST>::pack.  FP16 converts each value as it comes (the
+// high half is written in place); BF16 keeps the first value and converts both
+// with one two-value instruction.
+template <int ST> struct PairWord;
+
+template <> struct PairWord<1> {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  h2 v;
+  __device__ __forceinline__ void put(int h, float x) {
+    if (h) v.y = (_Float16)x;
+    else v.x = (_Float16)x;
   }
+  __device__ __forceinline__ uint32_t bits() const { return __builtin_bit_cast(uint32_t, v); }
+};
+
+template <> struct PairWord<2> {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  float first;
+  uint32_t word;
+  __device__ __forceinline__ void put(int h, float x) {
+    if (h) word = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){first, x}, b2));
+    else first = x;
+  }
+  __device__ __forceinline__ uint32_t bits() const { return word; }
 };
 
 // ----------------------------------------------------------------- indexing
@@ -144,7 +172,7 @@ template <int A, int ST, bool WX = true>
 __device__ __forceinline__ float gather_dev(const typename Store<ST>::T* __restrict__ src,
                                             const NodeCoord& c, const Consts& k) {
   const float v = Store<ST>::load(src + gather_slot<A, WX>(c, k));
-  return ST == 0 ? v : v * k.inv_sigma[A];
+  return ST == 0 ? v : v * k.inv_sigma[wclass(A)];
 }
 
 template <int ST, int A = 0, bool WX = true>
@@ -281,15 +309,20 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
     const float csy = inw - ay - g * uyy, cby = -inx + ay + g * uyy;
     const float csz = inw - az - g * uzz, cbz = -inx + az + g * uzz;
     const float det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
-    // density-gradient terms e_sr1, e_sr2, e_br of App. D (A, B, C = a_d u_d)
+    // density-gradient terms e_sr1, e_sr2, e_br of App. D (A, B, C = a_d u_d);
+    // zero without the full corrections, and then not added at all (x + 0 is
+    // not folded by the compiler, as it turns -0 into +0)
     float es1 = 0.0f, es2 = 0.0f, eb = 0.0f;
+    float Rs1e = Rs1, Rs2e = Rs2, Rbe = Rb;
     if constexpr (CORR == 3) {
       const float tA = ax * ux * grx, tB = ay * uy * gry, tC = az * uz * grz;
       es1 = tB - tA;
       es2 = tC - tA;
       eb = -(tA + tB + tC);
+      Rs1e += es1;
+      Rs2e += es2;
+      Rbe += eb;
     }
-    const float Rs1e = Rs1 + es1, Rs2e = Rs2 + es2, Rbe = Rb + eb;
     // closed-form solution of eq. 49 (the corrections only need a few digits of it)
     const float gx = (-csz * cby * Rs1e - csy * (cbz * Rs2e - csz * Rbe)) * __builtin_amdgcn_rcpf(det);
     const float gy = (Rs1e - csx * gx) * __builtin_amdgcn_rcpf(csy);
@@ -299,9 +332,15 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
     const float g3 = (CORR >= 2) ? 3.0f : 0.0f;
     const float tx = -(g3 * uxx + 2.0f * ax), ty = -(g3 * uyy + 2.0f * ay), tz = -(g3 * uzz + 2.0f * az);
     // lambda . grad rho of eq. 38-40 equals 2 (1/omega - 1/2) times the e terms above
-    c2d1 = hn * (tx * gx - ty * gy + 2.0f * es1);
-    c2d2 = hn * (tx * gx - tz * gz + 2.0f * es2);
-    c2s = hx * (tx * gx + ty * gy + tz * gz + 2.0f * eb);
+    float l1 = tx * gx - ty * gy, l2 = tx * gx - tz * gz, lb = tx * gx + ty * gy + tz * gz;
+    if constexpr (CORR == 3) {
+      l1 += 2.0f * es1;
+      l2 += 2.0f * es2;
+      lb += 2.0f * eb;
+    }
+    c2d1 = hn * l1;
+    c2d2 = hn * l2;
+    c2s = hx * lb;
   }
   // relaxation of the combined moments, then segregation (B^-1 of App. D)
   const float wh = HI ? k.omega_hi : 1.0f;
@@ -598,6 +637,15 @@ __device__ __forceinline__ T ld_pop(const T* __restrict__ base, uint32_t idx) {
   else return ld_off(base, idx);
 }
 
+// The same 32-bit value, defined anew where it is called.  A node offset that
+// the loads already used reaches the stores of another basic block widened to
+// 64 bits, and each store then adds its base in a 64-bit VALU operation; an
+// offset defined next to the stores lets them take their base from SGPRs.
+__device__ __forceinline__ uint32_t store_offset(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ void st_off_nt(T* __restrict__ base, uint32_t idx, T v) {
   T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
@@ -621,6 +669,18 @@ struct PeriodicRows {
   uint32_t row[3][3];
   uint32_t xs[3];
 };
+
+// A copy of the row offsets defined anew for a block of stores (store_offset).
+__device__ __forceinline__ PeriodicRows store_rows(const PeriodicRows& pr) {
+  PeriodicRows s;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    s.xs[j] = store_offset(pr.xs[j]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.row[j][i] = store_offset(pr.row[j][i]);
+  }
+  return s;
+}
 
 __device__ __forceinline__ void periodic_rows(int x, int y, int z, const Consts& k, PeriodicRows& pr) {
   pr.xs[0] = (uint32_t)(x == k.nx - 1 ? 0 : x + 1);
@@ -687,7 +747,7 @@ template <int ST, int NT = 0, int A = 0>
 __device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const PeriodicRows& pr,
                                                uint32_t node, const WallFlags& w, const Consts& k, float (&df)[27]) {
   const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(base, wall_slot32<A>(pr, node, w, k)));
-  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
+  df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
   if constexpr (A + 1 < 27) gather_walls32<ST, NT, A + 1>(base, pr, node, w, k, df);
 }
 
@@ -695,7 +755,7 @@ template <int ST, int NT = 0, int A = 0>
 __device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* const (&src)[27], const PeriodicRows& pr,
                                                 const Consts& k, float (&df)[27]) {
   const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(src[A], periodic_src<A>(pr)));
-  df[A] = ST == 0 ? v : v * k.inv_sigma[A];
+  df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
   if constexpr (A + 1 < 27) gather_periodic<ST, NT, A + 1>(src, pr, k, df);
 }
 

@@ -37,7 +37,7 @@ __device__ __forceinline__ void init_store(typename Store<ST>::T* __restrict__ d
   double v = drho * X.E[i] * Y.E[j] * Z.E[l]
            + kd.rho0 * (X.D[i] * Y.E[j] * Z.E[l] + X.W0[i] * Y.D[j] * Z.E[l] + X.W0[i] * Y.W0[j] * Z.D[l]);
   if (perturb != nullptr) v += perturb[A * k.n + node];
-  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[A]));
+  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[wclass(A)]));
   if constexpr (A + 1 < 27) init_store<ST, A + 1>(dst, c, node, X, Y, Z, drho, perturb, k, kd);
 }
 
@@ -60,7 +60,7 @@ __device__ __forceinline__ void import_store(typename Store<ST>::T* __restrict__
                                              int64_t node, const double* __restrict__ f,
                                              const Consts& k, const ConstsD& kd) {
   const double v = f[A * k.n + node] - kd.w[A] * kd.rho0;
-  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[A]));
+  dst[gather_slot<A>(c, k)] = Store<ST>::pack((float)(v * (double)k.sigma[wclass(A)]));
   if constexpr (A + 1 < 27) import_store<ST, A + 1>(dst, c, node, f, k, kd);
 }
 
@@ -77,7 +77,7 @@ template <int ST, int A = 0>
 __device__ __forceinline__ void export_load(const typename Store<ST>::T* __restrict__ src, const NodeCoord& c,
                                             int64_t node, double* __restrict__ f, const Consts& k,
                                             const ConstsD& kd) {
-  const double v = (double)Store<ST>::load(src + gather_slot<A>(c, k)) / (double)k.sigma[A];
+  const double v = (double)Store<ST>::load(src + gather_slot<A>(c, k)) / (double)k.sigma[wclass(A)];
   f[A * k.n + node] = kd.w[A] * kd.rho0 + v;
   if constexpr (A + 1 < 27) export_load<ST, A + 1>(src, c, node, f, k, kd);
 }

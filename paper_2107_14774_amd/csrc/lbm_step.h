@@ -108,9 +108,10 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
   if constexpr (WALLS != 0) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
+  const uint32_t so = store_offset(node);
 #pragma unroll
   for (int a = 0; a < 27; ++a)
-    st_off_nt(P.dst[a], node, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[a]));
+    st_off_nt(P.dst[a], so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
 }
 
 // ------------------------------------------------------------------ 16-bit step, two nodes per thread
@@ -156,12 +157,12 @@ __global__ __launch_bounds__(256) void k_step_pair(DirPtrs<typename Store<ST>::T
   uint32_t w[27];
   gather_pair<ST>(P, pr, t, tm, tp, w);
   const uint32_t node0 = pr.row[1][1] + 2 * t;
-  uint32_t o[27];
+  PairWord<ST> o[27];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     float df[27];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[a];
+    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
       fx = ld_off(force, node0 + h);
@@ -171,13 +172,11 @@ __global__ __launch_bounds__(256) void k_step_pair(DirPtrs<typename Store<ST>::T
     float out[27];
     collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
 #pragma unroll
-    for (int a = 0; a < 27; ++a) {
-      const uint32_t bits = Store<ST>::to_bits(out[a] * k.sigma[a]);
-      o[a] = h ? (o[a] | (bits << 16)) : bits;
-    }
+    for (int a = 0; a < 27; ++a) o[a].put(h, out[a] * k.sigma[wclass(a)]);
   }
+  const uint32_t so = store_offset(pr.row[1][1] / 2 + t);
 #pragma unroll
-  for (int a = 0; a < 27; ++a) st_off_nt(reinterpret_cast<uint32_t*>(P.dst[a]), pr.row[1][1] / 2 + t, o[a]);
+  for (int a = 0; a < 27; ++a) st_off_nt(reinterpret_cast<uint32_t*>(P.dst[a]), so, o[a].bits());
 }
 
 // ------------------------------------------------------------------ step, AA layout
@@ -222,7 +221,7 @@ __device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& 
     v = ld_pop<NT>(P.src[opp], periodic_src<A>(pr));
   }
   const float f = Store<ST>::load_val(v);
-  df[A] = ST == 0 ? f : f * k.inv_sigma[A];
+  df[A] = ST == 0 ? f : f * k.inv_sigma[wclass(A)];
   if constexpr (A + 1 < 27) gather_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, df);
 }
 
@@ -235,7 +234,7 @@ template <int ST, bool ODD, bool WALLS, int A = 0>
 __device__ __forceinline__ void store_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
                                          const WallFlags& w, const Consts& k, const float (&out)[27]) {
   constexpr int opp = opposite_of(A);
-  const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[A]);
+  const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[wclass(A)]);
   if constexpr (!ODD) {
     st_off_nt(P.dst[opp], node, v);
   } else if constexpr (WALLS) {
@@ -282,7 +281,8 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(DirPtrs<t
   if constexpr (WALLS) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  store_aa<ST, ODD, WALLS>(P, pr, node, w, k, out);
+  if constexpr (ODD) store_aa<ST, ODD, WALLS>(P, store_rows(pr), store_offset(node), w, k, out);
+  else store_aa<ST, ODD, WALLS>(P, pr, store_offset(node), w, k, out);
 }
 
 // 16-bit AA step with two x-adjacent nodes per thread (periodic grids, even nx;
@@ -354,12 +354,12 @@ __global__ __launch_bounds__(256) void k_step_aa_pair(DirPtrs<typename Store<ST>
   uint32_t w[27];
   gather_aa_pair<ST>(P, pr, t, tm, tp, ODD, w);
   const uint32_t node0 = pr.row[1][1] + 2 * t;
-  uint32_t o[27];
+  PairWord<ST> pw[27];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     float df[27];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[a];
+    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
       fx = ld_off(force, node0 + h);
@@ -369,12 +369,12 @@ __global__ __launch_bounds__(256) void k_step_aa_pair(DirPtrs<typename Store<ST>
     float out[27];
     collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
 #pragma unroll
-    for (int a = 0; a < 27; ++a) {
-      const uint32_t bits = Store<ST>::to_bits(out[a] * k.sigma[a]);
-      o[a] = h ? (o[a] | (bits << 16)) : bits;
-    }
+    for (int a = 0; a < 27; ++a) pw[a].put(h, out[a] * k.sigma[wclass(a)]);
   }
-  store_aa_pair<ST>(P, pr, t, tm, tp, ODD, o);
+  uint32_t o[27];
+#pragma unroll
+  for (int a = 0; a < 27; ++a) o[a] = pw[a].bits();
+  store_aa_pair<ST>(P, ODD ? store_rows(pr) : pr, store_offset(t), store_offset(tm), store_offset(tp), ODD, o);
 }
 
 // Density deviation of every node of a state: the same gather and the same
