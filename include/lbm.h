@@ -97,8 +97,9 @@ enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
  *     Between calls the state holds the post-stream populations in natural
  *     order (slot (a, x) = f_a(x, t)), so every step call must advance an even
  *     number of steps.  Forward steps only: lbm_step, lbm_step_forcing (not
- *     the full corrections, not the adjoint).  With walls the whole state
- *     must stay below 4 GiB (32-bit offsets; LBM_EINVAL from lbm_create). */
+ *     the full corrections, not the adjoint).  It addresses through 32-bit
+ *     offsets, so lbm_create returns LBM_EINVAL for 2^30 nodes or more, and
+ *     with walls for a whole state of 4 GiB or more. */
 enum lbm_layout { LBM_LAYOUT_AB = 0, LBM_LAYOUT_AA = 1 };
 
 /* Time level of the density gradient of the full corrections (lbm_step_full). */

@@ -333,12 +333,12 @@ __global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k
     }
     // lambda(t+1) is read at the node only: non-temporal loads (FP32 duct adjoint +15%)
 #pragma unroll
-    for (int a = 0; a < 27; ++a) lam[a] = ld_off_nt(P.lin[a], node);
+    for (int a = 0; a < 27; ++a) lam[a] = ld_field<WALLS == 2, true>(P.lin[a], node);
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
-      fx = ld_off(force, node);
-      fy = ld_off(force + k.n, node);
-      fz = ld_off(force + 2 * k.n, node);
+      fx = ld_field<WALLS == 2>(force, node);
+      fy = ld_field<WALLS == 2>(force + k.n, node);
+      fz = ld_field<WALLS == 2>(force + 2 * k.n, node);
     }
     collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
     if constexpr (WALLS == 2) {

@@ -96,6 +96,12 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     delete h;
     return fail(LBM_EINVAL, "lbm_create: the AA layout with walls needs a state below 4 GiB");
   }
+  // the periodic AA kernels address each direction array and the force field
+  // (N floats) through 32-bit byte offsets
+  if (q.layout == LBM_LAYOUT_AA && (uint64_t)h->stride * 4u >= (1ull << 32)) {
+    delete h;
+    return fail(LBM_EINVAL, "lbm_create: the AA layout needs fewer than 2^30 nodes");
+  }
   // threads per block along x: of the candidates in order of preference, the
   // first that leaves the fewest idle lanes in the last block of a row (e.g. 192
   // for nx = 384).  The FP32 step without full corrections prefers 128 (measured

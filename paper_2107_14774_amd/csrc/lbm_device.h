@@ -551,16 +551,23 @@ __device__ __forceinline__ TransverseRows transverse_rows(int y, int z, const Co
   return t;
 }
 
+template <bool WIDE, bool NT = false>
+__device__ __forceinline__ float ld_field(const float* __restrict__ base, uint32_t idx);
+
+// WIDE: 64-bit indices into the density field (the general kernels); the others
+// read it through 32-bit byte offsets (the field below 4 GiB).
+template <bool WIDE>
 __device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho, const TransverseRows& t,
                                                   int xc, const Consts& k) {
   float v[3][3];
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) v[j][l] = drho[t.row[j][l] + (uint32_t)xc];
+    for (int l = 0; l < 3; ++l) v[j][l] = ld_field<WIDE>(drho, t.row[j][l] + (uint32_t)xc);
   const float wy[3] = {k.w0s[1], k.w0c[1], k.w0s[1]};
   const float wz[3] = {k.w0s[2], k.w0c[2], k.w0s[2]};
-  ColumnSums c{0.0f, 0.0f, 0.0f};
+  // -0 is the exact additive identity, so the first product needs no add
+  ColumnSums c{-0.0f, -0.0f, -0.0f};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     c.U += wz[a] * (v[2][a] - v[0][a]);
@@ -576,20 +583,21 @@ __device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho
 // reduce the halo columns x0 - 1 and x_last + 1 (wrapped or mirrored), the x
 // neighbours are exchanged through LDS.  Every thread of the block must call
 // it (it contains a barrier); threads with x >= nx pass active = false.
+template <bool WIDE>
 __device__ __forceinline__ void density_gradient_block(const float* __restrict__ drho, int x, int y, int z,
                                                        bool active, const Consts& k, float (&lds)[3][258],
                                                        float& gx, float& gy, float& gz) {
   const int t = (int)threadIdx.x;
   const TransverseRows rows = transverse_rows(y, z, k);
   if (active) {
-    const ColumnSums c = column_sums(drho, rows, x, k);
+    const ColumnSums c = column_sums<WIDE>(drho, rows, x, k);
     lds[0][t + 1] = c.T; lds[1][t + 1] = c.U; lds[2][t + 1] = c.V;
     if (t == 0) {
-      const ColumnSums h = column_sums(drho, rows, x == 0 ? (k.bb_x ? 0 : k.nx - 1) : x - 1, k);
+      const ColumnSums h = column_sums<WIDE>(drho, rows, x == 0 ? (k.bb_x ? 0 : k.nx - 1) : x - 1, k);
       lds[0][0] = h.T; lds[1][0] = h.U; lds[2][0] = h.V;
     }
     if (t == (int)blockDim.x - 1 || x == k.nx - 1) {
-      const ColumnSums h = column_sums(drho, rows, x == k.nx - 1 ? (k.bb_x ? x : 0) : x + 1, k);
+      const ColumnSums h = column_sums<WIDE>(drho, rows, x == k.nx - 1 ? (k.bb_x ? x : 0) : x + 1, k);
       lds[0][t + 2] = h.T; lds[1][t + 2] = h.U; lds[2][t + 2] = h.V;
     }
   }
@@ -644,6 +652,15 @@ __device__ __forceinline__ T ld_pop(const T* __restrict__ base, uint32_t idx) {
 __device__ __forceinline__ uint32_t store_offset(uint32_t v) {
   asm volatile("" : "+v"(v));
   return v;
+}
+
+// Element idx of a field of N floats (a force component, an adjoint array):
+// through a 32-bit byte offset while such a field is below 4 GiB, which the
+// launchers guarantee for every kernel but the general (64-bit) one.
+template <bool WIDE, bool NT>
+__device__ __forceinline__ float ld_field(const float* __restrict__ base, uint32_t idx) {
+  if constexpr (WIDE) return NT ? __builtin_nontemporal_load(base + idx) : base[idx];
+  else return NT ? ld_off_nt(base, idx) : ld_off(base, idx);
 }
 
 template <typename T>

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
   float grx = 0.0f, gry = 0.0f, grz = 0.0f;
   if constexpr (CORR == 3) {
     __shared__ float lds[3][258];
-    density_gradient_block(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
+    density_gradient_block<WALLS == 2>(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
   }
   if (x >= k.nx) return;
   const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
@@ -93,9 +93,9 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
   gather_node<ST, WALLS>(P, x, y, z, k, df);
   float fx = k.fx, fy = k.fy, fz = k.fz;
   if (force != nullptr) {
-    fx = ld_off(force, node);
-    fy = ld_off(force + k.n, node);
-    fz = ld_off(force + 2 * k.n, node);
+    fx = ld_field<WALLS == 2>(force, node);
+    fy = ld_field<WALLS == 2>(force + k.n, node);
+    fz = ld_field<WALLS == 2>(force + 2 * k.n, node);
   }
   float out[27];
   if constexpr (CORR == 3) {
@@ -401,9 +401,12 @@ __global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> 
 // ------------------------------------------------------------------ launchers
 // Gather path: 0 periodic (32-bit offsets per direction array), 1 walls with
 // 32-bit offsets across the whole state, 2 walls with 64-bit slots.
+// Kinds 0 and 1 use 32-bit byte offsets: kind 0 per direction array and into
+// the force field (N floats, so N < 2^30 whatever the storage), kind 1 across
+// the whole state.  Kind 2 is general.
 static inline int gather_kind(const lbm_handle& h) {
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  if (!walls && (uint64_t)h.stride * h.elem < (1ull << 32)) return 0;
+  if (!walls && (uint64_t)h.stride * 4u < (1ull << 32)) return 0;
   if (27ull * (uint64_t)h.stride * h.elem < (1ull << 32)) return 1;
   return 2;
 }

@@ -149,3 +149,9 @@ def test_aa_layout_validation():
     with pytest.raises(_lib.LbmError) as e:
         P.lbm_create(1024, 1024, 1100, layout="aa", bc_y="bounceback")
     assert "4 GiB" in str(e.value)
+    # periodic AA: every direction array and the force field through 32-bit byte offsets
+    for storage in ("f32", "f16"):
+        with pytest.raises(_lib.LbmError) as e:
+            P.lbm_create(1024, 1024, 1024, layout="aa", storage=storage)
+        assert "2^30" in str(e.value)
+    assert P.lbm_create(1024, 1024, 1000, layout="aa", storage="f16").stride * 4 < 1 << 32

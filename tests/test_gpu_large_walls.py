@@ -77,8 +77,9 @@ def _gather_nodes(full, zs, ys, xs):
     return full[:, idx[0], idx[1], idx[2]].T.cpu()
 
 
-@pytest.mark.parametrize("storage,nz", [("f32", 160), ("f16", 320)])
-def test_large_duct_step_matches_oracle(storage, nz):
+@pytest.mark.parametrize("storage,nz,field", [("f32", 160, False), ("f16", 320, False), ("f32", 160, True)])
+def test_large_duct_step_matches_oracle(storage, nz, field):
+    """field: a force field (N floats per component, read with 64-bit indices on this path)."""
     NZ = nz
     p = _params(nz)
     lat = gpu_lattice(p, storage=storage, force=FORCE)
@@ -86,7 +87,11 @@ def test_large_duct_step_matches_oracle(storage, nz):
     a = _state(lat, p, 61)
     b = lat.new_state()
     f0 = lat.export_populations(a)
-    cur, _ = lat.step(a, b, 1)
+    ffield = None
+    if field:
+        g = np.random.Generator(np.random.PCG64(63))
+        ffield = torch.from_numpy((1e-5 * g.standard_normal((3, NZ, NY, NX))).astype(np.float32)).cuda()
+    cur, _ = lat.step(a, b, 1, ffield)
     f1 = lat.export_populations(cur)
     zs, ys, xs = _samples(62, NZ)
     got = _gather_nodes(f1, zs, ys, xs)                      # (S, 27)
@@ -102,13 +107,17 @@ def test_large_duct_step_matches_oracle(storage, nz):
     sx = np.where(wall, xs[:, None], sx)
     comp = np.where(wall, np.array(opp)[None, :], np.arange(27)[None, :])
     fs = _gather_nodes(f0, sz.ravel(), sy.ravel(), sx.ravel())        # (S*27, 27)
-    force = torch.tensor([FORCE] * fs.shape[0], dtype=DT)
+    if field:                                                           # the force of the colliding node
+        force = _gather_nodes(ffield, sz.ravel(), sy.ravel(), sx.ravel()).to(DT)
+    else:
+        force = torch.tensor([FORCE] * fs.shape[0], dtype=DT)
     ft = C.collide(fs, force, p)
     want = ft[torch.arange(fs.shape[0]), torch.from_numpy(comp.ravel())].reshape(got.shape)
     err = (got - want).abs().max().item()
     dev = (want - _rest_weights(p).to(want.dtype)).abs().max().item()
     nwall = int(wall.any(1).sum())
-    _say(f"512x512x{NZ} duct {storage} (state {lat.h.state_bytes / 2**30:.2f} GiB), one step, {len(zs)} sampled "
+    _say(f"512x512x{NZ} duct {storage}{' + force field' if field else ''} (state {lat.h.state_bytes / 2**30:.2f} GiB), "
+         f"one step, {len(zs)} sampled "
          f"nodes ({nwall} next to a wall): max |f_gpu - f_oracle| = {err:.3e} (max deviation {dev:.2e})")
     assert nwall >= 24
     if storage == "f32":
