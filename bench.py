@@ -302,6 +302,8 @@ PMC_CMD = ("timeout -s KILL 240 rocprofv3 --pmc {c} -d $OUT/pmc_{d} -o {d} --out
 SUMMARY_CMD = "python3 bench.py --summarize-rocprof $OUT"
 TRACE_SUMMARY = "profiles/k_step_and_adjoint_kernel_trace.txt"
 TRAFFIC_SUMMARY = "profiles/k_step_and_adjoint_hbm_traffic.txt"
+VALU_COUNTERS = "VALUBusy SQ_INSTS_VALU SQ_WAVES"
+VALU_SUMMARY = "profiles/k_step_and_adjoint_valu_busy.txt"
 
 
 def _launch_grid(nx, ny, nz, kernel=""):
@@ -390,6 +392,39 @@ def summarize_rocprof(out_dir):
         json.dump(traffic, fh, indent=1)
     print(open(os.path.join(ROOT, TRACE_SUMMARY)).read())
     print(open(os.path.join(ROOT, TRAFFIC_SUMMARY)).read())
+    if os.path.isdir(os.path.join(out_dir, "pmc_valu")):
+        summarize_valu(out_dir)
+
+
+def summarize_valu(out_dir):
+    """VALU summary from the optional third counter pass (VALU_COUNTERS): rocprofv3's derived
+    VALUBusy (time the vector ALUs issue, % of the kernel's GPU time) and the executed VALU
+    instructions per wave, per profiled kernel."""
+    import csv
+    import statistics
+    rows = list(csv.DictReader(open(os.path.join(out_dir, "pmc_valu", "valu_counter_collection.csv"))))
+    lines = ["# VALU activity of the step kernels (512x512x256, r=1, s=1/2) and the adjoint from rocprofv3 counters",
+             "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):",
+             "  " + PMC_CMD.format(c=VALU_COUNTERS, d="valu"), "  " + SUMMARY_CMD, "",
+             "VALUBusy = 100 * sum(SQ_ACTIVE_INST_VALU) / CU_NUM / GRBM_GUI_ACTIVE (rocprofv3's definition for",
+             "gfx950); VALU/wave = SQ_INSTS_VALU / SQ_WAVES (executed, so exits and branches count as run).", "",
+             f"{'kernel':44s} {'variant':16s} dispatches  VALUBusy_%  VALU/wave"]
+    for v, key in PROFILE_KERNELS.items():
+        nx, ny, nz, _ = PROFILE_WORKLOADS[v]
+        grid = _launch_grid(nx, ny, nz, key)
+        mine = [r for r in rows if key in r["Kernel_Name"] and r["Grid_Size"] == grid]
+        if not mine:
+            continue
+        busy = [float(r["Counter_Value"]) for r in mine if r["Counter_Name"] == "VALUBusy"]
+        insts = [float(r["Counter_Value"]) for r in mine if r["Counter_Name"] == "SQ_INSTS_VALU"]
+        waves = [float(r["Counter_Value"]) for r in mine if r["Counter_Name"] == "SQ_WAVES"]
+        if not busy or not insts or not waves:
+            continue
+        lines.append(f"{key:44s} {v:16s} {len(busy):10d}  {statistics.mean(busy):10.1f}  "
+                     f"{sum(insts) / sum(waves):9.0f}")
+    with open(os.path.join(ROOT, VALU_SUMMARY), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(open(os.path.join(ROOT, VALU_SUMMARY)).read())
 
 
 def main():
