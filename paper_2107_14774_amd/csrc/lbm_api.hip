@@ -118,9 +118,18 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   h->block_step = q.storage == LBM_F32 ? pick_block({128, 256, 192, 64}) : h->block;
   h->pairs = 1;
   if (const char* env = std::getenv("LBM_PAIRS")) h->pairs = std::atoi(env) != 0;  // 0: one node per thread
+  // The FP32 one-node steps fit 5 waves per SIMD in registers but run fastest at
+  // 4 (512x512x256: 2.595 ms at 4, 2.645 ms at 5, 2.614 ms at 3.5): reserve
+  // 160 KiB / (16 waves per CU / waves per block) of LDS per block to hold them
+  // there.  The 16-bit ones are fastest unlimited.
   if (const char* env = std::getenv("LBM_BLOCK")) {
     const int b = std::atoi(env);
     if (b == 64 || b == 128 || b == 192 || b == 256) h->block = h->block_step = b;
+  }
+  h->step_lds = q.storage == LBM_F32 ? 10240 * (h->block_step / 64) : 0;
+  if (const char* env = std::getenv("LBM_STEP_LDS")) {
+    const int b = std::atoi(env);
+    if (b >= 0 && b <= 65536) h->step_lds = b;
   }
 
   const double c[3] = {1.0, q.r, q.s};

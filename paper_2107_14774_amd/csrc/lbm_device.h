@@ -370,16 +370,26 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
       const float b0 = Dz * X.A0[i] + Dxz * X.A1[i];
       const float b1 = Dyz * X.A0[i];
       const float c0 = Dzz * X.A0[i];
+      // The per-axis vectors satisfy E = W0 + D, A0 = D at ebar = -1, +1 and
+      // 1 + D at ebar = 0, and W0, A2 take equal values at -1 and +1.  Along y
+      // and z the sums below use these identities; with QW = eW Y.W0 the z sums
+      // are QE Z.E + QW Z.D + Q0 Z.A0 + Q1 Z.A1 + Q2 Z.A2, where
+      // S = QE + QW + Q0 = (eE + eW) Y.E + Q0 multiplies Z.D.
+      const float eEW = eE + eW;
+      const float P = eE * Y.W0[0], R = a2 * Y.A2[0];
+      const float QEs[3] = {P + eEW * Y.D[0], eE * Y.E[1] + eW * Y.D[1], P + eEW * Y.D[2]};
+      const float Q0s[3] = {R + a0 * Y.D[0] + a1 * Y.A1[0], a0 * Y.A0[1] + a1 * Y.A1[1] + a2 * Y.A2[1],
+                            R + a0 * Y.D[2] + a1 * Y.A1[2]};
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const float QE = eE * Y.E[j] + eW * Y.D[j];
-        const float QW = eW * Y.W0[j];
-        const float Q0 = a0 * Y.A0[j] + a1 * Y.A1[j] + a2 * Y.A2[j];
+        const float QE = QEs[j], Q0 = Q0s[j];
         const float Q1 = b0 * Y.A0[j] + b1 * Y.A1[j];
         const float Q2 = c0 * Y.A0[j];
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-          out[dir_of(i, j, l)] = QE * Z.E[l] + QW * Z.D[l] + Q0 * Z.A0[l] + Q1 * Z.A1[l] + Q2 * Z.A2[l];
+        const float S = eEW * Y.E[j] + Q0;
+        const float T = QE * Z.W0[0] + Q2 * Z.A2[0];
+        out[dir_of(i, j, 0)] = T + S * Z.D[0] + Q1 * Z.A1[0];
+        out[dir_of(i, j, 2)] = T + S * Z.D[2] + Q1 * Z.A1[2];
+        out[dir_of(i, j, 1)] = QE * Z.W0[1] + Q0 + S * Z.D[1] + Q1 * Z.A1[1] + Q2 * Z.A2[1];
       }
     }
   } else {

@@ -18,6 +18,8 @@ struct lbm_handle {
   int block;         // threads per block of the node kernels
   int block_step;    // threads per block of the FP32 step without full corrections
   int pairs;         // 1 = the periodic 16-bit step may run two nodes per thread
+  int step_lds;      // dynamic LDS bytes per block of the one-node steps without full
+                     // corrections, AB and AA (unused by the kernels; caps the blocks per CU)
 };
 
 namespace clbm {

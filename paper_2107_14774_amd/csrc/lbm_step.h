@@ -444,8 +444,9 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
     }
   }
   const dim3 grid((unsigned)nb), blk(block);
+  const unsigned lds = h.p.corr == LBM_CORR_FULL ? 0u : (unsigned)h.step_lds;
 #define CLBM_STEP(C, W, R) \
-  hipLaunchKernelGGL((k_step<ST, C, W, R, HI>), grid, blk, 0, st, P, force, grad_src, drho_out, h.k, bpr)
+  hipLaunchKernelGGL((k_step<ST, C, W, R, HI>), grid, blk, lds, st, P, force, grad_src, drho_out, h.k, bpr)
 #define CLBM_STEP_CORR(W, R)                   \
   switch (h.p.corr) {                          \
     case 0: CLBM_STEP(0, W, R); break;         \
@@ -522,7 +523,8 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
     }
   }
   const dim3 grid((unsigned)nb), blk(block);
-#define CLBM_AA(C, O, W, R) hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R, HI>), grid, blk, 0, st, P, force, h.k, bpr)
+#define CLBM_AA(C, O, W, R) \
+  hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R, HI>), grid, blk, (unsigned)h.step_lds, st, P, force, h.k, bpr)
 #define CLBM_AA_CORR(O, W, R)                 \
   switch (h.p.corr) {                         \
     case 0: CLBM_AA(0, O, W, R); break;       \
