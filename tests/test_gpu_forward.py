@@ -212,3 +212,35 @@ def test_zero_steps_leave_the_state_unchanged():
     da = full.density(a)
     cur, _, d_cur, _ = full.step_full(a, b, 0, da, full.field(1), "lagged")
     assert cur is a and d_cur is da and torch.equal(full.export_populations(cur), before)
+
+
+@pytest.mark.parametrize("layout", ["ab", "aa"])
+def test_lds_reservation_does_not_change_results(layout):
+    """The FP32 one-node steps reserve LDS only to limit the blocks per CU (LBM_STEP_LDS, read when a
+    handle is created): states with and without the reservation agree bit for bit, walls included."""
+    import os
+    import paper_2107_14774_amd as P
+    p = oracle.Params(70, 9, 6, r=1.0, s=0.5, bc_z="bounceback" if layout == "ab" else "periodic")
+    f0 = fp32_rounded_state(random_state(p, 17), p)
+    out = []
+    old = os.environ.get("LBM_STEP_LDS")
+    try:
+        for lds in ("0", None):
+            if lds is None:
+                os.environ.pop("LBM_STEP_LDS", None)
+            else:
+                os.environ["LBM_STEP_LDS"] = lds
+            lat = P.Lattice(p.nx, p.ny, p.nz, r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi,
+                            bc_z=p.bc_z, force=(1e-5, 0.0, -2e-6), layout=layout)
+            a = lat.new_state()
+            b = None if layout == "aa" else lat.new_state()
+            lat.import_populations(a, f0.cuda())
+            cur, _ = lat.step(a, b, 4)
+            out.append(lat.export_populations(cur))
+    finally:
+        if old is None:
+            os.environ.pop("LBM_STEP_LDS", None)
+        else:
+            os.environ["LBM_STEP_LDS"] = old
+    print(f"{layout}: max |lds 0 - default| = {(out[0] - out[1]).abs().max().item():.3e}", flush=True)
+    assert torch.equal(out[0], out[1])
