@@ -127,8 +127,9 @@ def test_large_duct_step_matches_oracle(storage, nz, field):
         assert err < 2e-3 * dev
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_large_duct_adjoint_matches_oracle(storage):
+@pytest.mark.parametrize("storage,field", [("f32", False), ("f16", False), ("f32", True)])
+def test_large_duct_adjoint_matches_oracle(storage, field):
+    """field: a force field and its per-node gradient (N floats per component, 64-bit indices here)."""
     NZ = 160
     p = _params(NZ)
     lat = gpu_lattice(p, storage=storage, force=FORCE)
@@ -141,7 +142,12 @@ def test_large_duct_adjoint_matches_oracle(storage):
     lam_in, lam_out = lat.new_adjoint(zero=False), lat.new_adjoint()
     P.lbm_adjoint_from_natural(lat.h, lam, lam_in)
     gFu = torch.zeros(3, dtype=torch.float64, device="cuda")
-    P.lbm_step_adjoint(lat.h, st, lam_in, lam_out, None, None, gFu)
+    ffield = gfield = None
+    if field:
+        gf = np.random.Generator(np.random.PCG64(66))
+        ffield = torch.from_numpy((1e-5 * gf.standard_normal((3, NZ, NY, NX))).astype(np.float32)).cuda()
+        gfield = torch.zeros((3, NZ, NY, NX), dtype=torch.float32, device="cuda")
+    P.lbm_step_adjoint(lat.h, st, lam_in, lam_out, ffield, gfield, gFu)
     out = torch.empty((27, NZ, NY, NX), dtype=DT, device="cuda")
     P.lbm_adjoint_to_natural(lat.h, lam_out, out)
     lam32 = lam.to(torch.float32).to(DT)                     # the kernel reads lambda in FP32
@@ -162,12 +168,22 @@ def test_large_duct_adjoint_matches_oracle(storage):
     idx = torch.from_numpy(np.stack([comp.ravel(), tz.ravel(), ty.ravel(), tx.ravel()])).cuda()
     mu = lam32[idx[0], idx[1], idx[2], idx[3]].reshape(len(zs), 27).cpu()
     fy = _gather_nodes(f0, zs, ys, xs).clone().requires_grad_(True)
-    force = torch.tensor([FORCE] * len(zs), dtype=DT)
+    if field:
+        force = _gather_nodes(ffield, zs, ys, xs).to(DT).requires_grad_(True)
+    else:
+        force = torch.tensor([FORCE] * len(zs), dtype=DT)
     ft = C.collide(fy, force, p)
-    (want,) = torch.autograd.grad(ft, (fy,), grad_outputs=mu)
+    if field:
+        want, want_gF = torch.autograd.grad(ft, (fy, force), grad_outputs=mu)
+        got_gF = _gather_nodes(gfield, zs, ys, xs).to(DT)
+        errF = (got_gF - want_gF).abs().max().item() / want_gF.abs().max().item()
+        _say(f"force-field gradient at the sampled nodes: rel max err {errF:.2e}")
+        assert errF < 2e-6
+    else:
+        (want,) = torch.autograd.grad(ft, (fy,), grad_outputs=mu)
     err = (got - want).abs().max().item() / want.abs().max().item()
     nwall = int(wall.any(1).sum())
-    _say(f"512x512x160 duct adjoint, {storage} state (adjoint arrays {27 * lat.h.stride * 4 / 2**30:.2f} GiB), "
+    _say(f"512x512x160 duct adjoint, {storage} state{' + force field' if field else ''} (adjoint arrays {27 * lat.h.stride * 4 / 2**30:.2f} GiB), "
          f"{len(zs)} sampled nodes ({nwall} next to a wall): rel max err {err:.2e}")
     assert nwall >= 24
     assert err < 2e-6
