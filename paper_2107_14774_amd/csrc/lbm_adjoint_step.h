@@ -305,7 +305,8 @@ __device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const 
 }
 
 // WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit offsets
-// across the whole state and adjoint (both below 4 GiB), 2 walls with 64-bit slots.
+// across the whole state and adjoint (both below 4 GiB), 2 general (64-bit slots and
+// field indices; walls, or periodic grids too large for kind 0).
 template <int ST, int CORR, int WALLS, bool RAW, bool HI>
 __global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
                                                       float* __restrict__ grad_force, double* __restrict__ grad_uniform,

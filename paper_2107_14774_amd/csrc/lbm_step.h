@@ -23,7 +23,8 @@ namespace clbm {
 // HI: general rate of the moments of order >= 3 (k.omega_hi); false compiles
 // the unit-rate collision.
 // WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
-// offsets from direction 0's array (state below 4 GiB), 2 walls, 64-bit slots.
+// offsets from direction 0's array (state below 4 GiB), 2 general (64-bit slots
+// and field indices; walls, or periodic grids too large for kind 0).
 // The directions with ebar_x = 0 are read with non-temporal loads (nt_dir).
 template <int ST, int WALLS>
 __device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
@@ -399,11 +400,10 @@ __global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> 
 }
 
 // ------------------------------------------------------------------ launchers
-// Gather path: 0 periodic (32-bit offsets per direction array), 1 walls with
-// 32-bit offsets across the whole state, 2 walls with 64-bit slots.
-// Kinds 0 and 1 use 32-bit byte offsets: kind 0 per direction array and into
-// the force field (N floats, so N < 2^30 whatever the storage), kind 1 across
-// the whole state.  Kind 2 is general.
+// Gather path: 0 periodic, 32-bit byte offsets per direction array and into the
+// force field (N floats, so N < 2^30 whatever the storage); 1 walls, 32-bit
+// offsets across the whole state (below 4 GiB); 2 general, 64-bit slots and
+// field indices (walls or periodic, any size).
 static inline int gather_kind(const lbm_handle& h) {
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
   if (!walls && (uint64_t)h.stride * 4u < (1ull << 32)) return 0;
