@@ -16,6 +16,14 @@ __device__ __forceinline__ void add_to_gathered(float* __restrict__ dst, const N
   if constexpr (A + 1 < 27) add_to_gathered<A + 1>(dst, c, k, v);
 }
 
+// The values of a slot-indexed float array at the node's own slots (a, x).
+template <int A = 0>
+__device__ __forceinline__ void own_slots(const float* __restrict__ src, int x, int y, int z, const Consts& k,
+                                          float (&v)[27]) {
+  v[A] = src[slot_of<A>(x, y, z, k)];
+  if constexpr (A + 1 < 27) own_slots<A + 1>(src, x, y, z, k, v);
+}
+
 __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __restrict__ adj_in, float* __restrict__ adj_out,
                                                              Consts k) {
   for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
@@ -28,8 +36,7 @@ __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __rest
                            (k.bb_z && (((k.moving & 16) && z == 0) || ((k.moving & 32) && z == k.nz - 1)));
     if (!on_moving) continue;
     float lam[27];
-#pragma unroll
-    for (int a = 0; a < 27; ++a) lam[a] = adj_in[(int64_t)a * k.stride + node];
+    own_slots(adj_in, x, y, z, k, lam);
     const float c = moving_wall_vjp(x, y, z, k, lam);
     add_to_gathered(adj_out, make_coord(x, y, z, k), k, -c);
   }

@@ -277,82 +277,74 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Per-direction base pointers of one adjoint step.
-template <typename T>
-struct AdjPtrs {
-  const T* state[27];
-  const float* lin[27];
-  float* lout[27];
-};
-
 template <int A = 0>
-__device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const PeriodicRows& pr, uint32_t node,
-                                                const WallFlags& w, const Consts& k, const float (&mu)[27]) {
-  const uint32_t idx = wall_slot32<A>(pr, node, w, k);
+__device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const Upstream& u, const WallFlags& w,
+                                                const float (&mu)[27]) {
+  const uint32_t idx = wall_slot32<A>(u, w);
   if constexpr (kEx[A] == 0) st_off_nt(base, idx, mu[A]);
-  else *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + idx * 4u) = mu[A];
-  if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, pr, node, w, k, mu);
+  else st_off(base, idx, mu[A]);
+  if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, u, w, mu);
 }
 
 template <int A = 0>
-__device__ __forceinline__ void scatter_periodic(float* const (&dst)[27], const PeriodicRows& pr,
-                                                 const float (&mu)[27]) {
+__device__ __forceinline__ void scatter_periodic(float* __restrict__ dst, const Upstream& u, const float (&mu)[27]) {
   // the x-shifted scatter writes partial lines that L2 merges with the neighbours' (plain
   // stores); the directions with ebar_x = 0 write whole lines (non-temporal stores)
-  if constexpr (kEx[A] == 0) st_off_nt(dst[A], periodic_src<A>(pr), mu[A]);
-  else *reinterpret_cast<float*>(reinterpret_cast<char*>(dst[A]) + (uint32_t)(periodic_src<A>(pr) * 4u)) = mu[A];
-  if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, pr, mu);
+  if constexpr (kEx[A] == 0) st_off_nt(dst + pull_row<A>(u), u.xo[1], mu[A]);
+  else st_off(dst + pull_row<A>(u), u.xo[kEx[A] + 1], mu[A]);
+  if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, u, mu);
 }
 
-// WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit offsets
-// across the whole state and adjoint (both below 4 GiB), 2 general (64-bit slots and
-// field indices; walls, or periodic grids too large for kind 0).
+// WALLS: 0 periodic (row addresses, any size), 1 walls with 32-bit offsets
+// across the whole state and adjoint (both below 4 GiB), 2 general (64-bit slots).
 template <int ST, int CORR, int WALLS, bool RAW, bool HI>
-__global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(AdjPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
-                                                      float* __restrict__ grad_force, double* __restrict__ grad_uniform,
-                                                      Consts k, uint32_t bpr) {
+__global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(
+    const typename Store<ST>::T* __restrict__ state, const float* __restrict__ lin, float* __restrict__ lout,
+    const float* __restrict__ force, float* __restrict__ grad_force, double* __restrict__ grad_uniform, Consts k,
+    uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   float gfx = 0.0f, gfy = 0.0f, gfz = 0.0f;
   if (x < k.nx) {
-    const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+    Upstream u;
+    upstream(x, y, z, k, u);
     float df[27], lam[27], mu[27];
-    PeriodicRows pr;
     WallFlags w;
     if constexpr (WALLS == 2) {
-      gather_all<ST>(P.state[0], make_coord(x, y, z, k), k, df);
+      gather_all<ST>(state, make_coord(x, y, z, k), k, df);
+    } else if constexpr (WALLS == 1) {
+      w = wall_flags(x, y, z, k);
+      gather_walls32<ST>(state, u, w, k, df);
     } else {
-      periodic_rows(x, y, z, k, pr);
-      if constexpr (WALLS == 1) {
-        w = wall_flags(x, y, z, k);
-        gather_walls32<ST>(P.state[0], pr, node, w, k, df);
-      } else {
-        gather_periodic<ST>(P.state, pr, k, df);
-      }
+      gather_periodic<ST>(state, u, k, df);
     }
-    // lambda(t+1) is read at the node only: non-temporal loads (FP32 duct adjoint +15%)
+    // lambda(t+1) is read at the node's own slots only: non-temporal loads (FP32 duct adjoint +15%)
+    const float* lrow = lin + u.row[1][1];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) lam[a] = ld_field<WALLS == 2, true>(P.lin[a], node);
+    for (int a = 0; a < 27; ++a) lam[a] = ld_off_nt(lrow + chunk_of(a) * kB, u.xo[1]);
+    const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
-      fx = ld_field<WALLS == 2>(force, node);
-      fy = ld_field<WALLS == 2>(force + k.n, node);
-      fz = ld_field<WALLS == 2>(force + 2 * k.n, node);
+      const float* f = force + nrow;
+      fx = ld_off(f, (uint32_t)x);
+      fy = ld_off(f + k.n, (uint32_t)x);
+      fz = ld_off(f + 2 * k.n, (uint32_t)x);
     }
     collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
     if constexpr (WALLS == 2) {
-      scatter_all<true>(P.lout[0], make_coord(x, y, z, k), k, mu);
+      scatter_all<true>(lout, make_coord(x, y, z, k), k, mu);
     } else if constexpr (WALLS == 1) {
-      scatter_walls32(P.lout[0], pr, node, w, k, mu);
+      scatter_walls32(lout, u, w, mu);
     } else {
-      scatter_periodic(P.lout, pr, mu);
+      scatter_periodic(lout, u, mu);
     }
     if (grad_force != nullptr) {
-      grad_force[node] += gfx;
-      grad_force[k.n + node] += gfy;
-      grad_force[2 * k.n + node] += gfz;
+      float* g = grad_force + nrow;
+      g[x] += gfx;
+      g[k.n + x] += gfy;
+      g[2 * k.n + x] += gfz;
     }
   }
   if (grad_uniform != nullptr) {
@@ -378,20 +370,16 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  AdjPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.state[a] = (const T*)state + (int64_t)a * h.stride;
-    P.lin[a] = adj_in + (int64_t)a * h.stride;
-    P.lout[a] = adj_out + (int64_t)a * h.stride;
-  }
-  // 32-bit offsets: per direction array (periodic) or across all 27 (walls), for the
-  // state and the float adjoint arrays alike
+  const T* s = (const T*)state;
+  // 32-bit offsets across all 27 chunks (walls): the float adjoint arrays below 4 GiB
   const bool any_wall = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  const int kind = (!any_wall && (uint64_t)h.stride * 4u < (1ull << 32)) ? 0
-                   : (27ull * (uint64_t)h.stride * 4u < (1ull << 32) ? 1 : 2);
+  const bool fits32 = 27ull * (uint64_t)h.stride * 4u < (1ull << 32);
+  int kind = !any_wall ? 0 : (fits32 ? 1 : 2);
+  if (h.force_kind > kind && (h.force_kind == 2 || fits32)) kind = h.force_kind;
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_ADJ(C, W, R)                                                                              \
-  hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R, HI>), grid, blk, 0, st, P, force, grad_force, grad_uniform, h.k, bpr)
+  hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R, HI>), grid, blk, 0, st, s, adj_in, adj_out, force, grad_force, \
+                     grad_uniform, h.k, bpr)
 #define CLBM_ADJ_CORR(W, R)                  \
   switch (h.p.corr) {                        \
     case 0: CLBM_ADJ(0, W, R); break;        \

@@ -25,15 +25,6 @@ int hip_fail(hipError_t e, const char* where) {
 
 bool aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-int64_t padded_stride(int64_t n) {
-  // Round each direction array up to 256 elements, then shift it off a
-  // power-of-two pitch so the 27 streams do not start on the same channel.
-  int64_t s = (n + 255) / 256 * 256;
-  if ((s & (s - 1)) == 0 && s >= 65536) s += 256;
-  if (const char* env = std::getenv("LBM_STRIDE_PAD")) s += std::atoll(env);
-  return s;
-}
-
 }  // namespace
 
 extern "C" {
@@ -88,19 +79,16 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   if (h == nullptr) return fail(LBM_EINVAL, "lbm_create: out of host memory");
   h->p = q;
   h->n = n;
-  h->stride = padded_stride(n);
+  // blocked layout: every x-row padded to whole blocks of kB nodes
+  const int64_t nxp = ((int64_t)q.nx + clbm::kB - 1) / clbm::kB * clbm::kB;
+  h->stride = nxp * q.ny * q.nz;
   h->elem = q.storage == LBM_F32 ? 4 : 2;
   h->bytes = (size_t)27 * (size_t)h->stride * h->elem;
+  // the AA kernels with walls address the state through 32-bit offsets
   if (q.layout == LBM_LAYOUT_AA && (q.bc_x == LBM_BOUNCEBACK || q.bc_y == LBM_BOUNCEBACK || q.bc_z == LBM_BOUNCEBACK) &&
       h->bytes >= (1ull << 32)) {
     delete h;
     return fail(LBM_EINVAL, "lbm_create: the AA layout with walls needs a state below 4 GiB");
-  }
-  // the periodic AA kernels address each direction array and the force field
-  // (N floats) through 32-bit byte offsets
-  if (q.layout == LBM_LAYOUT_AA && (uint64_t)h->stride * 4u >= (1ull << 32)) {
-    delete h;
-    return fail(LBM_EINVAL, "lbm_create: the AA layout needs fewer than 2^30 nodes");
   }
   // threads per block along x: of the candidates in order of preference, the
   // first that leaves the fewest idle lanes in the last block of a row (e.g. 192
@@ -118,6 +106,11 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   h->block_step = q.storage == LBM_F32 ? pick_block({128, 256, 192, 64}) : h->block;
   h->pairs = 1;
   if (const char* env = std::getenv("LBM_PAIRS")) h->pairs = std::atoi(env) != 0;  // 0: one node per thread
+  h->force_kind = 0;
+  if (const char* env = std::getenv("LBM_GATHER_KIND")) {  // testing: 1 or 2, taken where valid
+    const int kind = std::atoi(env);
+    if (kind == 1 || kind == 2) h->force_kind = kind;
+  }
   // The FP32 one-node steps fit 5 waves per SIMD in registers but run fastest at
   // 4 (512x512x256: 2.595 ms at 4, 2.645 ms at 5, 2.614 ms at 3.5): reserve
   // 160 KiB / (16 waves per CU / waves per block) of LDS per block to hold them
@@ -151,7 +144,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   }
   for (int f = 0; f < 6; ++f)
     for (int c = 0; c < 3; ++c) k.wall_u[f][c] = (float)q.wall_velocity[f][c];
-  k.stride = h->stride;
+  k.row_slots = 27 * nxp;
   k.n = n;
   k.rho0 = (float)q.rho0; k.cs2 = (float)q.cs2; k.r = (float)q.r; k.s = (float)q.s;
   k.omega_nu = (float)q.omega_nu; k.omega_xi = (float)q.omega_xi; k.omega_hi = (float)q.omega_hi;

@@ -1,12 +1,14 @@
 // Device-side building blocks of the cuboid D3Q27 central-moment step (gfx950).
 //
-// Layout: a state is 27 arrays (one per direction of eq. 1a-c) of `stride`
-// elements; element n of array alpha is a population slot.  Slots hold the
-// deviation (f - w_alpha rho0) scaled by sigma_alpha (1 for FP32 storage).
-// Pull scheme: the step at node x gathers f_alpha(x) from slot
-// (alpha, x - ebar_alpha), or from (opposite(alpha), x) when x - ebar_alpha
-// lies beyond a bounce-back wall (Sec. 4, stationary wall), and writes its
-// post-collision populations to the slots (alpha, x) of the other buffer.
+// Layout: a state is blocked.  Each x-row of the grid is padded to a multiple
+// of kB nodes and cut into blocks of kB consecutive nodes; a block stores the
+// 27 directions (eq. 1a-c) of its nodes as 27 chunks of kB elements.  An
+// element is a population slot holding the deviation (f - w_alpha rho0)
+// scaled by sigma_alpha (1 for FP32 storage).  Pull scheme: the step at node x
+// gathers f_alpha(x) from slot (alpha, x - ebar_alpha), or from
+// (opposite(alpha), x) when x - ebar_alpha lies beyond a bounce-back wall
+// (Sec. 4, stationary wall), and writes its post-collision populations to the
+// slots (alpha, x) of the other buffer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,7 +49,7 @@ struct Consts {
   int ytile;               // rows per y-tile of the full-correction step's row order (divides ny)
   int aa;                  // 1 = AA layout: between calls slot (a, x) holds f_a(x) (natural order)
   float wall_u[6][3];      // face velocities, faces x-, x+, y-, y+, z-, z+
-  int64_t stride;          // elements between direction arrays
+  int64_t row_slots;       // elements of one grid row of a state (27 kB ceil(nx / kB))
   int64_t n;               // nodes
   float rho0, cs2, r, s;
   float omega_nu, omega_xi;
@@ -130,7 +132,34 @@ template <> struct PairWord<2> {
   __device__ __forceinline__ uint32_t bits() const { return word; }
 };
 
-// ----------------------------------------------------------------- indexing
+// ----------------------------------------------------------------- state layout
+// Nodes per block.  A wave of 64 lanes reads one direction of 64 (one node per
+// lane) or 128 (two per lane) consecutive nodes as whole lines of one chunk,
+// and a node's 27 slots lie in one block instead of 27 separate arrays; at
+// 512x512x256 the pull pattern moved 6.07 TB/s this way against 5.54 with
+// one array per direction.
+constexpr int kB = 128;
+
+// Chunk of direction a within a block: grouped by upstream row, the three
+// directions with the same (ebar_y, ebar_z) side by side in the order
+// ebar_x = -1, 0, +1, so a node's pulls from one row are adjacent in memory.
+// The opposite direction's chunk is 26 - chunk_of(a).
+constexpr int chunk_of(int a) { return 3 * (3 * (kEy[a] + 1) + (kEz[a] + 1)) + (kEx[a] + 1); }
+
+// Element offset of node x within its row: (x / kB) 27 kB + x % kB.
+__device__ __forceinline__ uint32_t xoff(uint32_t x) { return (x / kB) * (27u * kB) + x % kB; }
+
+// First element of grid row (y, z).
+__device__ __forceinline__ int64_t row_start(int y, int z, const Consts& k) {
+  return ((int64_t)z * k.ny + y) * k.row_slots;
+}
+
+// Element of slot (a, x, y, z).
+template <int A>
+__device__ __forceinline__ int64_t slot_of(int x, int y, int z, const Consts& k) {
+  return row_start(y, z, k) + (int64_t)(chunk_of(A) * kB) + (int64_t)xoff((uint32_t)x);
+}
+
 struct NodeCoord {
   int x, y, z;
   int xm, xp, ym, yp, zm, zp;  // periodic neighbours
@@ -149,13 +178,13 @@ __device__ __forceinline__ NodeCoord make_coord(int x, int y, int z, const Const
 }
 
 // Slot from which the node gathers f_a: (a, x - ebar_a) or, across a wall, (opp(a), x);
-// in the AA layout between calls, (a, x).
+// in the AA layout between calls, (a, x).  64-bit element index (any state size).
 // WX = false compiles the x-wall test away (for callers that know x is periodic).
 template <int A, bool WX = true>
 __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts& k) {
   constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
   constexpr int opp = opposite_of(A);
-  if (k.aa) return (int64_t)A * k.stride + ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;  // natural order
+  if (k.aa) return slot_of<A>(c.x, c.y, c.z, k);  // natural order
   const int xs = ex == 0 ? c.x : (ex > 0 ? c.xm : c.xp);
   const int ys = ey == 0 ? c.y : (ey > 0 ? c.ym : c.yp);
   const int zs = ez == 0 ? c.z : (ez > 0 ? c.zm : c.zp);
@@ -163,9 +192,7 @@ __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts&
   if (WX && ex != 0) wall |= k.bb_x && (ex > 0 ? c.x == 0 : c.x == k.nx - 1);
   if (ey != 0) wall |= k.bb_y && (ey > 0 ? c.y == 0 : c.y == k.ny - 1);
   if (ez != 0) wall |= k.bb_z && (ez > 0 ? c.z == 0 : c.z == k.nz - 1);
-  const int64_t node = ((int64_t)c.z * k.ny + c.y) * k.nx + c.x;
-  const int64_t src = ((int64_t)zs * k.ny + ys) * k.nx + xs;
-  return wall ? (int64_t)opp * k.stride + node : (int64_t)A * k.stride + src;
+  return wall ? slot_of<opp>(c.x, c.y, c.z, k) : slot_of<A>(xs, ys, zs, k);
 }
 
 template <int A, int ST, bool WX = true>
@@ -431,6 +458,39 @@ __device__ __forceinline__ void collide_node(const float (&df)[27], float fx, fl
   }
 }
 
+// Values made opaque to the optimiser (no instruction is emitted).  Every
+// forward kernel runs the collision between such fences, so the compiler
+// fuses its multiply-adds the same way in each of them whatever code
+// surrounds it, and the kernels that must agree bit for bit (two-buffer and
+// AA steps, one and two nodes per thread) round identically.
+template <int N>
+__device__ __forceinline__ void fence_values(float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(v[i]));
+}
+
+__device__ __forceinline__ void fence_value(float& v) { asm volatile("" : "+v"(v)); }
+
+// IN: fence the inputs too.  The 16-bit kernels with unit higher-order rate
+// leave them open: their decode (an exact conversion and a power-of-two scale)
+// folds into the first moment sums as mixed-precision multiply-adds, which
+// round like separate operations because the product is exact.  With a general
+// higher-order rate the inputs also enter the output ((1 - w) f), so they are
+// fenced there.
+template <int CORR, bool RAW = false, bool HI = false, bool IN = true>
+__device__ __forceinline__ void collide_fenced(float (&df)[27], float fx, float fy, float fz, const Consts& k,
+                                               float (&out)[27], float grx = 0.0f, float gry = 0.0f,
+                                               float grz = 0.0f) {
+  if constexpr (IN) {
+    fence_values(df);
+    fence_value(fx);
+    fence_value(fy);
+    fence_value(fz);
+  }
+  collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out, grx, gry, grz);
+  fence_values(out);
+}
+
 // Momentum-augmented bounce-back (Sec. 4) applied where the populations are
 // stored: the slot (alpha, x) of a population that leaves the fluid through a
 // wall is read only by the bounce-back gather of node x itself, so the
@@ -535,11 +595,14 @@ struct ColumnSums {
   float T, U, V;
 };
 
+// Row pointers of the 3 x 3 transverse neighbourhood: [y offset][z offset] ->
+// the density field's row (y', z'), a uniform 64-bit pointer (any field size).
 struct TransverseRows {
-  uint32_t row[3][3];  // [y offset][z offset] -> (z' ny + y') nx
+  const float* row[3][3];
 };
 
-__device__ __forceinline__ TransverseRows transverse_rows(int y, int z, const Consts& k) {
+__device__ __forceinline__ TransverseRows transverse_rows(const float* __restrict__ drho, int y, int z,
+                                                          const Consts& k) {
   int ys[3], zs[3];
   if (k.bb_y) {
     ys[0] = y == 0 ? 0 : y - 1; ys[2] = y == k.ny - 1 ? y : y + 1;
@@ -557,23 +620,19 @@ __device__ __forceinline__ TransverseRows transverse_rows(int y, int z, const Co
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) t.row[j][l] = ((uint32_t)zs[l] * (uint32_t)k.ny + (uint32_t)ys[j]) * (uint32_t)k.nx;
+    for (int l = 0; l < 3; ++l) t.row[j][l] = drho + ((int64_t)zs[l] * k.ny + ys[j]) * k.nx;
   return t;
 }
 
-template <bool WIDE, bool NT = false>
-__device__ __forceinline__ float ld_field(const float* __restrict__ base, uint32_t idx);
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t idx);
 
-// WIDE: 64-bit indices into the density field (the general kernels); the others
-// read it through 32-bit byte offsets (the field below 4 GiB).
-template <bool WIDE>
-__device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho, const TransverseRows& t,
-                                                  int xc, const Consts& k) {
+__device__ __forceinline__ ColumnSums column_sums(const TransverseRows& t, int xc, const Consts& k) {
   float v[3][3];
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) v[j][l] = ld_field<WIDE>(drho, t.row[j][l] + (uint32_t)xc);
+    for (int l = 0; l < 3; ++l) v[j][l] = ld_off(t.row[j][l], (uint32_t)xc);
   const float wy[3] = {k.w0s[1], k.w0c[1], k.w0s[1]};
   const float wz[3] = {k.w0s[2], k.w0c[2], k.w0s[2]};
   // -0 is the exact additive identity, so the first product needs no add
@@ -593,21 +652,20 @@ __device__ __forceinline__ ColumnSums column_sums(const float* __restrict__ drho
 // reduce the halo columns x0 - 1 and x_last + 1 (wrapped or mirrored), the x
 // neighbours are exchanged through LDS.  Every thread of the block must call
 // it (it contains a barrier); threads with x >= nx pass active = false.
-template <bool WIDE>
 __device__ __forceinline__ void density_gradient_block(const float* __restrict__ drho, int x, int y, int z,
                                                        bool active, const Consts& k, float (&lds)[3][258],
                                                        float& gx, float& gy, float& gz) {
   const int t = (int)threadIdx.x;
-  const TransverseRows rows = transverse_rows(y, z, k);
+  const TransverseRows rows = transverse_rows(drho, y, z, k);
   if (active) {
-    const ColumnSums c = column_sums<WIDE>(drho, rows, x, k);
+    const ColumnSums c = column_sums(rows, x, k);
     lds[0][t + 1] = c.T; lds[1][t + 1] = c.U; lds[2][t + 1] = c.V;
     if (t == 0) {
-      const ColumnSums h = column_sums<WIDE>(drho, rows, x == 0 ? (k.bb_x ? 0 : k.nx - 1) : x - 1, k);
+      const ColumnSums h = column_sums(rows, x == 0 ? (k.bb_x ? 0 : k.nx - 1) : x - 1, k);
       lds[0][0] = h.T; lds[1][0] = h.U; lds[2][0] = h.V;
     }
     if (t == (int)blockDim.x - 1 || x == k.nx - 1) {
-      const ColumnSums h = column_sums<WIDE>(drho, rows, x == k.nx - 1 ? (k.bb_x ? x : 0) : x + 1, k);
+      const ColumnSums h = column_sums(rows, x == k.nx - 1 ? (k.bb_x ? x : 0) : x + 1, k);
       lds[0][t + 2] = h.T; lds[1][t + 2] = h.U; lds[2][t + 2] = h.V;
     }
   }
@@ -664,13 +722,9 @@ __device__ __forceinline__ uint32_t store_offset(uint32_t v) {
   return v;
 }
 
-// Element idx of a field of N floats (a force component, an adjoint array):
-// through a 32-bit byte offset while such a field is below 4 GiB, which the
-// launchers guarantee for every kernel but the general (64-bit) one.
-template <bool WIDE, bool NT>
-__device__ __forceinline__ float ld_field(const float* __restrict__ base, uint32_t idx) {
-  if constexpr (WIDE) return NT ? __builtin_nontemporal_load(base + idx) : base[idx];
-  else return NT ? ld_off_nt(base, idx) : ld_off(base, idx);
+template <typename T>
+__device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t idx, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
 }
 
 template <typename T>
@@ -683,53 +737,48 @@ __device__ __forceinline__ void st_off_nt(T* __restrict__ base, uint32_t idx, T 
   }
 }
 
-// Per-direction base pointers of the two buffers of a step.
-template <typename T>
-struct DirPtrs {
-  const T* src[27];
-  T* dst[27];
+// Upstream rows and x offsets of a node, for the row-addressed paths.
+// row[j][l]: first element of the grid row (y - (j - 1), z - (l - 1)), the row a
+// direction with ebar_y = j - 1, ebar_z = l - 1 pulls from (wrapped; on a wall
+// axis the wrapped row is never used, the wall test selects the node's own
+// slot instead).  The rows depend on y and z only, so they are uniform across
+// a block and live in scalar registers: every access is a 64-bit scalar row
+// address plus a small per-lane offset.  xo[i]: offset within a row of
+// x - (i - 1) (wrapped).
+struct Upstream {
+  int64_t row[3][3];
+  uint32_t xo[3];
 };
 
-// Source offsets of the periodic fast path: the node x - ebar for every
-// direction is row[ebar_y + 1][ebar_z + 1] + xs[ebar_x + 1] (32-bit node index).
-struct PeriodicRows {
-  uint32_t row[3][3];
-  uint32_t xs[3];
-};
-
-// A copy of the row offsets defined anew for a block of stores (store_offset).
-__device__ __forceinline__ PeriodicRows store_rows(const PeriodicRows& pr) {
-  PeriodicRows s;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    s.xs[j] = store_offset(pr.xs[j]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) s.row[j][i] = store_offset(pr.row[j][i]);
-  }
-  return s;
-}
-
-__device__ __forceinline__ void periodic_rows(int x, int y, int z, const Consts& k, PeriodicRows& pr) {
-  pr.xs[0] = (uint32_t)(x == k.nx - 1 ? 0 : x + 1);
-  pr.xs[1] = (uint32_t)x;
-  pr.xs[2] = (uint32_t)(x == 0 ? k.nx - 1 : x - 1);
-  const uint32_t ys[3] = {(uint32_t)(y == k.ny - 1 ? 0 : y + 1), (uint32_t)y, (uint32_t)(y == 0 ? k.ny - 1 : y - 1)};
-  const uint32_t zs[3] = {(uint32_t)(z == k.nz - 1 ? 0 : z + 1), (uint32_t)z, (uint32_t)(z == 0 ? k.nz - 1 : z - 1)};
+__device__ __forceinline__ void upstream(int x, int y, int z, const Consts& k, Upstream& u) {
+  u.xo[0] = xoff((uint32_t)(x == k.nx - 1 ? 0 : x + 1));
+  u.xo[1] = xoff((uint32_t)x);
+  u.xo[2] = xoff((uint32_t)(x == 0 ? k.nx - 1 : x - 1));
+  const int ys[3] = {y == k.ny - 1 ? 0 : y + 1, y, y == 0 ? k.ny - 1 : y - 1};
+  const int zs[3] = {z == k.nz - 1 ? 0 : z + 1, z, z == 0 ? k.nz - 1 : z - 1};
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) pr.row[j][l] = (zs[l] * (uint32_t)k.ny + ys[j]) * (uint32_t)k.nx;
+    for (int l = 0; l < 3; ++l) u.row[j][l] = row_start(ys[j], zs[l], k);
 }
 
+// A copy of the x offsets defined anew for a block of stores (store_offset).
+__device__ __forceinline__ Upstream store_upstream(const Upstream& u) {
+  Upstream s = u;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s.xo[i] = store_offset(u.xo[i]);
+  return s;
+}
+
+// Element of the chunk row that direction A pulls from: add xo[ebar_x + 1].
 template <int A>
-__device__ __forceinline__ uint32_t periodic_src(const PeriodicRows& pr) {
-  return pr.row[kEy[A] + 1][kEz[A] + 1] + pr.xs[kEx[A] + 1];
+__device__ __forceinline__ int64_t pull_row(const Upstream& u) {
+  return u.row[kEy[A] + 1][kEz[A] + 1] + chunk_of(A) * kB;
 }
 
 // Walls with 32-bit offsets (the whole state below 4 GiB): the slot of f_A is
-// (A, x - ebar_A) from the periodic row offsets, or (opp(A), x) across a wall,
-// written as one 32-bit element offset from direction 0's array; a wall costs
-// a compare and a select instead of 64-bit index arithmetic.
+// (A, x - ebar_A) or, across a wall, (opp(A), x), as one 32-bit element offset
+// from the start of the state; a wall costs a compare and a select.
 struct WallFlags {
   bool lx, hx, ly, hy, lz, hz;  // upstream node beyond the wall at the low / high end of an axis
 };
@@ -745,11 +794,10 @@ __device__ __forceinline__ WallFlags wall_flags(int x, int y, int z, const Const
   return w;
 }
 
+// Whether direction A's upstream node lies beyond a wall.
 template <int A>
-__device__ __forceinline__ uint32_t wall_slot32(const PeriodicRows& pr, uint32_t node, const WallFlags& w,
-                                                const Consts& k) {
+__device__ __forceinline__ bool pulls_through_wall(const WallFlags& w) {
   constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
-  constexpr int opp = opposite_of(A);
   bool wall = false;
   if (ex > 0) wall |= w.lx;
   if (ex < 0) wall |= w.hx;
@@ -757,33 +805,49 @@ __device__ __forceinline__ uint32_t wall_slot32(const PeriodicRows& pr, uint32_t
   if (ey < 0) wall |= w.hy;
   if (ez > 0) wall |= w.lz;
   if (ez < 0) wall |= w.hz;
-  const uint32_t stride = (uint32_t)k.stride;
-  return wall ? (uint32_t)opp * stride + node : (uint32_t)A * stride + periodic_src<A>(pr);
+  return wall;
+}
+
+// 32-bit element of the node's own slot (A, x).
+template <int A>
+__device__ __forceinline__ uint32_t own_slot32(const Upstream& u) {
+  return (uint32_t)u.row[1][1] + (uint32_t)(chunk_of(A) * kB) + u.xo[1];
+}
+
+// 32-bit element of slot (C, x - ebar_A): direction A's upstream node, chunk of C.
+template <int A, int C>
+__device__ __forceinline__ uint32_t upstream_slot32(const Upstream& u) {
+  return (uint32_t)u.row[kEy[A] + 1][kEz[A] + 1] + (uint32_t)(chunk_of(C) * kB) + u.xo[kEx[A] + 1];
+}
+
+template <int A>
+__device__ __forceinline__ uint32_t wall_slot32(const Upstream& u, const WallFlags& w) {
+  return pulls_through_wall<A>(w) ? own_slot32<opposite_of(A)>(u) : upstream_slot32<A, A>(u);
 }
 
 // NT: 0 plain loads; 1 non-temporal loads; 2 non-temporal loads for the
 // directions with ebar_x = 0 only.  A wave reads whole aligned lines for those;
-// the x-shifted directions straddle lines that the neighbouring wave reads too,
-// which plain loads keep in L2.
+// the x-shifted directions straddle a line that the neighbouring wave reads
+// too, which plain loads keep in L2.
 template <int NT>
 constexpr bool nt_dir(int a) {
   return NT == 1 || (NT == 2 && kEx[a] == 0);
 }
 
 template <int ST, int NT = 0, int A = 0>
-__device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const PeriodicRows& pr,
-                                               uint32_t node, const WallFlags& w, const Consts& k, float (&df)[27]) {
-  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(base, wall_slot32<A>(pr, node, w, k)));
+__device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const Upstream& u,
+                                               const WallFlags& w, const Consts& k, float (&df)[27]) {
+  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(base, wall_slot32<A>(u, w)));
   df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
-  if constexpr (A + 1 < 27) gather_walls32<ST, NT, A + 1>(base, pr, node, w, k, df);
+  if constexpr (A + 1 < 27) gather_walls32<ST, NT, A + 1>(base, u, w, k, df);
 }
 
 template <int ST, int NT = 0, int A = 0>
-__device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* const (&src)[27], const PeriodicRows& pr,
+__device__ __forceinline__ void gather_periodic(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
                                                 const Consts& k, float (&df)[27]) {
-  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(src[A], periodic_src<A>(pr)));
+  const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(src + pull_row<A>(u), u.xo[kEx[A] + 1]));
   df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
-  if constexpr (A + 1 < 27) gather_periodic<ST, NT, A + 1>(src, pr, k, df);
+  if constexpr (A + 1 < 27) gather_periodic<ST, NT, A + 1>(src, u, k, df);
 }
 
 }  // namespace clbm

@@ -12,14 +12,16 @@ struct lbm_handle {
   clbm::Consts k;
   clbm::ConstsD kd;
   int64_t n;         // nodes
-  int64_t stride;    // elements per direction array
+  int64_t stride;    // slots per direction: nodes with every x-row padded to a multiple of clbm::kB
   size_t elem;       // bytes per stored element
-  size_t bytes;      // bytes of one state
+  size_t bytes;      // bytes of one state (27 stride elem)
   int block;         // threads per block of the node kernels
   int block_step;    // threads per block of the FP32 step without full corrections
   int pairs;         // 1 = the periodic 16-bit step may run two nodes per thread
   int step_lds;      // dynamic LDS bytes per block of the one-node steps without full
                      // corrections, AB and AA (unused by the kernels; caps the blocks per CU)
+  int force_kind;    // 0, or a more general gather path to take where valid (1: 32-bit
+                     // offsets across the state, 2: 64-bit slots); a testing override
 };
 
 namespace clbm {

@@ -6,41 +6,53 @@
 
 #include "lbm_internal.h"
 
+// Loads of the gathers: 2 = non-temporal for the directions with ebar_x = 0,
+// plain for the x-shifted ones (nt_dir); 1 = non-temporal for all 27.
+#ifndef LBM_GATHER_NT
+#define LBM_GATHER_NT 2
+#endif
+
 namespace clbm {
 
 // ------------------------------------------------------------------ step
 // One thread per node, pull scheme: gather 27 slots of the source buffer,
 // collide, write the node's 27 slots of the destination buffer (coalesced
 // along x, non-temporal).  Without walls every source slot is
-// (alpha, x - ebar_alpha) with periodic wrap, addressed as a per-direction
-// base pointer plus a 32-bit node index shared by the three directions of
-// one source row; with walls the slot rule of gather_slot applies (as 32-bit
-// offsets from direction 0's array below 4 GiB, wall_slot32).  Periodic
-// 16-bit grids with even nx run k_step_pair below instead, unless they use the
-// full corrections.  With the full corrections (CORR 3) the density gradient comes from the
-// density-deviation field grad_src, and drho_out (if not NULL) receives the
-// node's own density deviation.
+// (alpha, x - ebar_alpha) with periodic wrap, addressed as the scalar start of
+// the source row plus a per-lane offset (any state size); with walls the slot
+// rule of gather_slot applies, as 32-bit offsets from the start of the state
+// below 4 GiB (wall_slot32) and as 64-bit slots above.  Periodic 16-bit grids
+// with even nx run k_step_pair below instead, unless they use the full
+// corrections.  With the full corrections (CORR 3) the density gradient comes
+// from the density-deviation field grad_src, and drho_out (if not NULL)
+// receives the node's own density deviation.
 // HI: general rate of the moments of order >= 3 (k.omega_hi); false compiles
 // the unit-rate collision.
-// WALLS: 0 periodic (per-direction bases, 32-bit offsets), 1 walls with 32-bit
-// offsets from direction 0's array (state below 4 GiB), 2 general (64-bit slots
-// and field indices; walls, or periodic grids too large for kind 0).
-// The directions with ebar_x = 0 are read with non-temporal loads (nt_dir).
+// WALLS: 0 periodic (row addresses), 1 walls with 32-bit offsets (state below
+// 4 GiB), 2 general (64-bit slots).
 template <int ST, int WALLS>
-__device__ __forceinline__ void gather_node(const DirPtrs<typename Store<ST>::T>& P, int x, int y, int z,
-                                            const Consts& k, float (&df)[27]) {
-  constexpr int NT = 2;
+__device__ __forceinline__ void gather_node(const typename Store<ST>::T* __restrict__ src, const Upstream& u, int x,
+                                            int y, int z, const Consts& k, float (&df)[27]) {
+  constexpr int NT = LBM_GATHER_NT;
   if constexpr (WALLS == 2) {
-    gather_all<ST>(P.src[0], make_coord(x, y, z, k), k, df);
+    gather_all<ST>(src, make_coord(x, y, z, k), k, df);
+  } else if constexpr (WALLS == 1) {
+    gather_walls32<ST, NT>(src, u, wall_flags(x, y, z, k), k, df);
   } else {
-    PeriodicRows pr;
-    periodic_rows(x, y, z, k, pr);
-    if constexpr (WALLS == 1) {
-      const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-      gather_walls32<ST, NT>(P.src[0], pr, node, wall_flags(x, y, z, k), k, df);
-    } else {
-      gather_periodic<ST, NT>(P.src, pr, k, df);
-    }
+    gather_periodic<ST, NT>(src, u, k, df);
+  }
+}
+
+// Body force of a node: the uniform one, or the field's value through the
+// scalar start of the node's row (natural order, any field size).
+__device__ __forceinline__ void node_force(const float* __restrict__ force, int64_t nrow, uint32_t x, const Consts& k,
+                                           float& fx, float& fy, float& fz) {
+  fx = k.fx; fy = k.fy; fz = k.fz;
+  if (force != nullptr) {
+    const float* f = force + nrow;
+    fx = ld_off(f, x);
+    fy = ld_off(f + k.n, x);
+    fz = ld_off(f + 2 * k.n, x);
   }
 }
 
@@ -63,10 +75,12 @@ constexpr int step_waves(int st, int corr) {
 }
 
 template <int ST, int CORR, int WALLS, bool RAW, bool HI>
-__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<typename Store<ST>::T> P,
-                                              const float* __restrict__ force,
-                                              const float* __restrict__ grad_src, float* __restrict__ drho_out,
-                                              Consts k, uint32_t bpr) {
+__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(const typename Store<ST>::T* __restrict__ src,
+                                                                    typename Store<ST>::T* __restrict__ dst,
+                                                                    const float* __restrict__ force,
+                                                                    const float* __restrict__ grad_src,
+                                                                    float* __restrict__ drho_out, Consts k,
+                                                                    uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   int y, z;
@@ -86,65 +100,119 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(DirPtrs<type
   float grx = 0.0f, gry = 0.0f, grz = 0.0f;
   if constexpr (CORR == 3) {
     __shared__ float lds[3][258];
-    density_gradient_block<WALLS == 2>(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
+    density_gradient_block(grad_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
   }
   if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  Upstream u;
+  upstream(x, y, z, k, u);
   float df[27];
-  gather_node<ST, WALLS>(P, x, y, z, k, df);
-  float fx = k.fx, fy = k.fy, fz = k.fz;
-  if (force != nullptr) {
-    fx = ld_field<WALLS == 2>(force, node);
-    fy = ld_field<WALLS == 2>(force + k.n, node);
-    fz = ld_field<WALLS == 2>(force + 2 * k.n, node);
-  }
+  gather_node<ST, WALLS>(src, u, x, y, z, k, df);
+  const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
+  float fx, fy, fz;
+  node_force(force, nrow, (uint32_t)x, k, fx, fy, fz);
   float out[27];
   if constexpr (CORR == 3) {
-    collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out, grx, gry, grz);
-    if (drho_out != nullptr) drho_out[node] = low_moments(df).m000;
+    collide_fenced<CORR, RAW, HI, ST == 0 || HI>(df, fx, fy, fz, k, out, grx, gry, grz);
+    if (drho_out != nullptr) st_off(drho_out + nrow, (uint32_t)x, low_moments(df).m000);
   } else {
-    collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
+    collide_fenced<CORR, RAW, HI, ST == 0 || HI>(df, fx, fy, fz, k, out);
   }
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
   if constexpr (WALLS != 0) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  const uint32_t so = store_offset(node);
+  typename Store<ST>::T* d = dst + u.row[1][1];
+  const uint32_t so = store_offset(u.xo[1]);
 #pragma unroll
   for (int a = 0; a < 27; ++a)
-    st_off_nt(P.dst[a], so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
+    st_off_nt(d + chunk_of(a) * kB, so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
 }
 
 // ------------------------------------------------------------------ 16-bit step, two nodes per thread
 // Periodic two-buffer step for FP16/BF16 storage with each thread owning the
-// x-adjacent nodes 2t and 2t + 1: a 32-bit word of a direction array holds
-// both nodes' values, so the gather is 27 aligned word loads (ebar_x = 0) or
-// pairs of them (the x-shifted directions take one half from the neighbouring
-// word) and the store 27 word stores; the two collisions run one after the
-// other.  Measured on the bare access pattern at 512x512x256: 1.37 vs 1.45 ms
-// for one node per thread with 2-byte accesses.  Results equal the one-node
-// kernel's bit for bit (same gather values, same collision).
-template <int ST, int A = 0>
-__device__ __forceinline__ void gather_pair(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr,
-                                            uint32_t t, uint32_t tm, uint32_t tp, uint32_t (&w)[27]) {
+// x-adjacent nodes 2t and 2t + 1: a 32-bit word of a chunk holds both nodes'
+// values, so the gather is 27 aligned word loads (ebar_x = 0) or pairs of them
+// (the x-shifted directions take one half from the neighbouring word) and the
+// store 27 word stores; the two collisions run one after the other.  Results
+// equal the one-node kernel's bit for bit (same gather values, same collision).
+
+// Word offset of word t (nodes 2t, 2t + 1) within a row: xoff(2t) / 2.
+__device__ __forceinline__ uint32_t xoffw(uint32_t t) {
+  return (t / (kB / 2)) * (27u * kB / 2) + t % (kB / 2);
+}
+
+// Word offsets of the words t + 1, t, t - 1 (wrapped), indexed like Upstream::xo.
+struct PairWords {
+  uint32_t xw[3];
+};
+
+__device__ __forceinline__ PairWords pair_words(uint32_t t, uint32_t tm, uint32_t tp) {
+  PairWords p;
+  p.xw[0] = xoffw(tp);
+  p.xw[1] = xoffw(t);
+  p.xw[2] = xoffw(tm);
+  return p;
+}
+
+// Words of chunk CH of the grid row starting at element `row` (rows and chunks
+// start on even elements).
+template <int CH, typename T>
+__device__ __forceinline__ const uint32_t* word_row(const T* state, int64_t row) {
+  static_assert(CH >= 0 && CH < 27, "chunk index");
+  return reinterpret_cast<const uint32_t*>(state + row + CH * kB);
+}
+
+// The two values f_A of nodes 2t, 2t + 1 from the slots of direction D (A in
+// the pull step, opp(A) in the AA odd step) at the nodes upstream of A: one
+// word (ebar_x = 0) or the halves of two (ebar_x != 0).
+template <int A, int D, typename T>
+__device__ __forceinline__ uint32_t pair_gather_word(const T* src, const Upstream& u, const PairWords& p) {
   constexpr int ex = kEx[A];
-  const uint32_t* base = reinterpret_cast<const uint32_t*>(P.src[A]);
-  const uint32_t row = pr.row[kEy[A] + 1][kEz[A] + 1] / 2;      // word index of the source row
+  const uint32_t* base = word_row<chunk_of(D)>(src, u.row[kEy[A] + 1][kEz[A] + 1]);
   if constexpr (ex == 0) {
-    w[A] = ld_off_nt(base, row + t);                            // whole lines: non-temporal
+    return ld_off_nt(base, p.xw[1]);                            // whole lines: non-temporal
   } else if constexpr (ex > 0) {                                // nodes 2t - 1, 2t
-    const uint32_t own = ld_off(base, row + t), prev = ld_off(base, row + tm);
-    w[A] = (prev >> 16) | (own << 16);
+    const uint32_t own = ld_pop<LBM_GATHER_NT == 1>(base, p.xw[1]), prev = ld_pop<LBM_GATHER_NT == 1>(base, p.xw[2]);
+    return (prev >> 16) | (own << 16);
   } else {                                                      // nodes 2t + 1, 2t + 2
-    const uint32_t own = ld_off(base, row + t), next = ld_off(base, row + tp);
-    w[A] = (own >> 16) | (next << 16);
+    const uint32_t own = ld_pop<LBM_GATHER_NT == 1>(base, p.xw[1]), next = ld_pop<LBM_GATHER_NT == 1>(base, p.xw[0]);
+    return (own >> 16) | (next << 16);
   }
-  if constexpr (A + 1 < 27) gather_pair<ST, A + 1>(P, pr, t, tm, tp, w);
+}
+
+template <int ST, int A = 0>
+__device__ __forceinline__ void gather_pair(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
+                                            const PairWords& p, uint32_t (&w)[27]) {
+  w[A] = pair_gather_word<A, A>(src, u, p);
+  if constexpr (A + 1 < 27) gather_pair<ST, A + 1>(src, u, p, w);
+}
+
+// Decode, collide and encode the two nodes of a pair (shared by the two-buffer
+// and AA pair steps).
+template <int ST, int CORR, bool RAW, bool HI>
+__device__ __forceinline__ void collide_pair(const uint32_t (&w)[27], const float* __restrict__ force, int64_t nrow,
+                                             uint32_t x0, const Consts& k, uint32_t (&o)[27]) {
+  PairWord<ST> pw[27];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float df[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
+    float fx, fy, fz;
+    node_force(force, nrow, x0 + h, k, fx, fy, fz);
+    float out[27];
+    collide_fenced<CORR, RAW, HI, ST == 0 || HI>(df, fx, fy, fz, k, out);
+#pragma unroll
+    for (int a = 0; a < 27; ++a) pw[a].put(h, out[a] * k.sigma[wclass(a)]);
+  }
+#pragma unroll
+  for (int a = 0; a < 27; ++a) o[a] = pw[a].bits();
 }
 
 template <int ST, int CORR, bool RAW, bool HI>
-__global__ __launch_bounds__(256) void k_step_pair(DirPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
-                                                   Consts k, uint32_t bpr) {
+__global__ __launch_bounds__(256) void k_step_pair(const typename Store<ST>::T* __restrict__ src,
+                                                   typename Store<ST>::T* __restrict__ dst,
+                                                   const float* __restrict__ force, Consts k, uint32_t bpr) {
   static_assert(ST != 0, "two nodes per thread is the 16-bit path");
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
@@ -153,31 +221,17 @@ __global__ __launch_bounds__(256) void k_step_pair(DirPtrs<typename Store<ST>::T
   const uint32_t t = bxi * blockDim.x + threadIdx.x;
   if (t >= tpr) return;
   const uint32_t tm = t == 0 ? tpr - 1 : t - 1, tp = t + 1 == tpr ? 0 : t + 1;
-  PeriodicRows pr;
-  periodic_rows((int)(2 * t), y, z, k, pr);
+  Upstream u;
+  upstream((int)(2 * t), y, z, k, u);
+  const PairWords p = pair_words(t, tm, tp);
   uint32_t w[27];
-  gather_pair<ST>(P, pr, t, tm, tp, w);
-  const uint32_t node0 = pr.row[1][1] + 2 * t;
-  PairWord<ST> o[27];
+  gather_pair<ST>(src, u, p, w);
+  uint32_t o[27];
+  collide_pair<ST, CORR, RAW, HI>(w, force, ((int64_t)z * k.ny + y) * k.nx, 2 * t, k, o);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst + u.row[1][1]);
+  const uint32_t so = store_offset(p.xw[1]);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    float df[27];
-#pragma unroll
-    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
-    float fx = k.fx, fy = k.fy, fz = k.fz;
-    if (force != nullptr) {
-      fx = ld_off(force, node0 + h);
-      fy = ld_off(force + k.n, node0 + h);
-      fz = ld_off(force + 2 * k.n, node0 + h);
-    }
-    float out[27];
-    collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
-#pragma unroll
-    for (int a = 0; a < 27; ++a) o[a].put(h, out[a] * k.sigma[wclass(a)]);
-  }
-  const uint32_t so = store_offset(pr.row[1][1] / 2 + t);
-#pragma unroll
-  for (int a = 0; a < 27; ++a) st_off_nt(reinterpret_cast<uint32_t*>(P.dst[a]), so, o[a].bits());
+  for (int a = 0; a < 27; ++a) st_off_nt(d + chunk_of(a) * (kB / 2), so, o[a]);
 }
 
 // ------------------------------------------------------------------ step, AA layout
@@ -187,75 +241,53 @@ __global__ __launch_bounds__(256) void k_step_pair(DirPtrs<typename Store<ST>::T
 // wall, and f~_a is written to (a, x + ebar_a), or to (opp(a), x) when
 // x + ebar_a lies beyond a wall.  Within a step every slot is read and written
 // by one node only, so the update needs no second buffer.  After an even
-// number of steps slot (a, x) holds f_a(x) again.  Without walls each direction
-// array is addressed through its own base pointer; with walls all 27 arrays
-// through direction 0's base with 32-bit offsets (the state below 4 GiB).
-template <int A>
-__device__ __forceinline__ bool pulls_through_wall(const WallFlags& w) {
-  constexpr int ex = kEx[A], ey = kEy[A], ez = kEz[A];
-  bool wall = false;
-  if (ex > 0) wall |= w.lx;
-  if (ex < 0) wall |= w.hx;
-  if (ey > 0) wall |= w.ly;
-  if (ey < 0) wall |= w.hy;
-  if (ez > 0) wall |= w.lz;
-  if (ez < 0) wall |= w.hz;
-  return wall;
-}
-
+// number of steps slot (a, x) holds f_a(x) again.  Without walls through row
+// addresses (any state size); with walls through 32-bit offsets from the start
+// of the state (below 4 GiB).
 template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void gather_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
+__device__ __forceinline__ void gather_aa(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
                                           const WallFlags& w, const Consts& k, float (&df)[27]) {
   constexpr int opp = opposite_of(A);
   // even steps read the node's own slots (no line shared between waves): all non-temporal;
   // odd steps as the two-buffer gather
-  constexpr bool NT = !ODD || kEx[A] == 0;
+  constexpr bool NT = !ODD || kEx[A] == 0 || LBM_GATHER_NT == 1;
   typename Store<ST>::T v;
   if constexpr (!ODD) {
-    v = ld_pop<NT>(P.src[A], node);
+    v = ld_pop<NT>(src + u.row[1][1] + chunk_of(A) * kB, u.xo[1]);
   } else if constexpr (WALLS) {
-    const uint32_t stride = (uint32_t)k.stride;
-    const uint32_t idx = pulls_through_wall<A>(w) ? (uint32_t)A * stride + node
-                                                  : (uint32_t)opp * stride + periodic_src<A>(pr);
-    v = ld_pop<NT>(P.src[0], idx);
+    v = ld_pop<NT>(src, pulls_through_wall<A>(w) ? own_slot32<A>(u) : upstream_slot32<A, opp>(u));
   } else {
-    v = ld_pop<NT>(P.src[opp], periodic_src<A>(pr));
+    v = ld_pop<NT>(src + u.row[kEy[A] + 1][kEz[A] + 1] + chunk_of(opp) * kB, u.xo[kEx[A] + 1]);
   }
   const float f = Store<ST>::load_val(v);
   df[A] = ST == 0 ? f : f * k.inv_sigma[wclass(A)];
-  if constexpr (A + 1 < 27) gather_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, df);
-}
-
-template <typename T>
-__device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t idx, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+  if constexpr (A + 1 < 27) gather_aa<ST, ODD, WALLS, A + 1>(src, u, w, k, df);
 }
 
 template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void store_aa(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr, uint32_t node,
+__device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst, const Upstream& u,
                                          const WallFlags& w, const Consts& k, const float (&out)[27]) {
   constexpr int opp = opposite_of(A);
   const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[wclass(A)]);
   if constexpr (!ODD) {
-    st_off_nt(P.dst[opp], node, v);
+    st_off_nt(dst + u.row[1][1] + chunk_of(opp) * kB, u.xo[1], v);
   } else if constexpr (WALLS) {
     // x + ebar_A lies beyond a wall exactly when opp(A) pulls through one
-    const uint32_t stride = (uint32_t)k.stride;
-    const uint32_t idx = pulls_through_wall<opp>(w) ? (uint32_t)opp * stride + node
-                                                    : (uint32_t)A * stride + periodic_src<opp>(pr);
-    if constexpr (kEx[A] == 0) st_off_nt(P.dst[0], idx, v);
-    else st_off(P.dst[0], idx, v);
+    const uint32_t idx = pulls_through_wall<opp>(w) ? own_slot32<opp>(u) : upstream_slot32<opp, A>(u);
+    if constexpr (kEx[A] == 0) st_off_nt(dst, idx, v);
+    else st_off(dst, idx, v);
   } else {
     // shifted by one node along x for 18 directions: plain stores, partial lines merge in L2;
     // the 9 with ebar_x = 0 write whole lines: non-temporal stores
-    if constexpr (kEx[A] == 0) st_off_nt(P.dst[A], periodic_src<opp>(pr), v);
-    else st_off(P.dst[A], periodic_src<opp>(pr), v);
+    typename Store<ST>::T* p = dst + u.row[1 - kEy[A]][1 - kEz[A]] + chunk_of(A) * kB;
+    if constexpr (kEx[A] == 0) st_off_nt(p, u.xo[1], v);
+    else st_off(p, u.xo[1 - kEx[A]], v);
   }
-  if constexpr (A + 1 < 27) store_aa<ST, ODD, WALLS, A + 1>(P, pr, node, w, k, out);
+  if constexpr (A + 1 < 27) store_aa<ST, ODD, WALLS, A + 1>(dst, u, w, k, out);
 }
 
 template <int ST, int CORR, bool ODD, bool WALLS, bool RAW, bool HI>
-__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(DirPtrs<typename Store<ST>::T> P,
+__global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(typename Store<ST>::T* __restrict__ state,
                                                                        const float* __restrict__ force, Consts k,
                                                                        uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -263,90 +295,66 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(DirPtrs<t
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
-  PeriodicRows pr;
+  Upstream u;
+  upstream(x, y, z, k, u);
   WallFlags w{};
-  if constexpr (ODD) periodic_rows(x, y, z, k, pr);
   if constexpr (WALLS) w = wall_flags(x, y, z, k);
   float df[27];
-  gather_aa<ST, ODD, WALLS>(P, pr, node, w, k, df);
-  float fx = k.fx, fy = k.fy, fz = k.fz;
-  if (force != nullptr) {
-    fx = ld_off(force, node);
-    fy = ld_off(force + k.n, node);
-    fz = ld_off(force + 2 * k.n, node);
-  }
+  gather_aa<ST, ODD, WALLS>(state, u, w, k, df);
+  float fx, fy, fz;
+  node_force(force, ((int64_t)z * k.ny + y) * k.nx, (uint32_t)x, k, fx, fy, fz);
   float out[27];
-  collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
+  collide_fenced<CORR, RAW, HI, ST == 0 || HI>(df, fx, fy, fz, k, out);
   if constexpr (ST == 0) conserve(df, fx, fy, fz, k, out);
   if constexpr (WALLS) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  // Store offsets defined next to the stores (store_offset), except in the FP32
-  // odd step: there they cut the registers from 150 to 100, and the extra waves
-  // let L2 evict the x-shifted partial lines before their second half arrives
-  // (writes 113.9 instead of 109.3 B/LUP, 0.4% slower).
-  if constexpr (ODD && ST == 0) store_aa<ST, ODD, WALLS>(P, pr, node, w, k, out);
-  else if constexpr (ODD) store_aa<ST, ODD, WALLS>(P, store_rows(pr), store_offset(node), w, k, out);
-  else store_aa<ST, ODD, WALLS>(P, pr, store_offset(node), w, k, out);
+  store_aa<ST, ODD, WALLS>(state, store_upstream(u), w, k, out);
 }
 
 // 16-bit AA step with two x-adjacent nodes per thread (periodic grids, even nx;
 // the pairing of k_step_pair).  Even steps read and write whole words of the
 // node pair's own slots.  Odd steps gather like k_step_pair from the opposite
-// directions' arrays; their x-shifted outputs land in words that two threads
+// directions' chunks; their x-shifted outputs land in words that two threads
 // share, so those go out as 2-byte stores.
 template <int ST, int A = 0>
-__device__ __forceinline__ void gather_aa_pair(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr,
-                                               uint32_t t, uint32_t tm, uint32_t tp, bool odd, uint32_t (&w)[27]) {
-  constexpr int ex = kEx[A];
-  if (!odd) {
-    w[A] = ld_off_nt(reinterpret_cast<const uint32_t*>(P.src[A]), pr.row[1][1] / 2 + t);
-  } else {
-    const uint32_t* base = reinterpret_cast<const uint32_t*>(P.src[opposite_of(A)]);
-    const uint32_t row = pr.row[kEy[A] + 1][kEz[A] + 1] / 2;
-    if constexpr (ex == 0) {
-      w[A] = ld_off_nt(base, row + t);
-    } else if constexpr (ex > 0) {
-      const uint32_t own = ld_off(base, row + t), prev = ld_off(base, row + tm);
-      w[A] = (prev >> 16) | (own << 16);
-    } else {
-      const uint32_t own = ld_off(base, row + t), next = ld_off(base, row + tp);
-      w[A] = (own >> 16) | (next << 16);
-    }
-  }
-  if constexpr (A + 1 < 27) gather_aa_pair<ST, A + 1>(P, pr, t, tm, tp, odd, w);
+__device__ __forceinline__ void gather_aa_pair(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
+                                               const PairWords& p, bool odd, uint32_t (&w)[27]) {
+  if (!odd) w[A] = ld_off_nt(word_row<chunk_of(A)>(src, u.row[1][1]), p.xw[1]);
+  else w[A] = pair_gather_word<A, opposite_of(A)>(src, u, p);
+  if constexpr (A + 1 < 27) gather_aa_pair<ST, A + 1>(src, u, p, odd, w);
 }
 
 template <int ST, int A = 0>
-__device__ __forceinline__ void store_aa_pair(const DirPtrs<typename Store<ST>::T>& P, const PeriodicRows& pr,
-                                              uint32_t t, uint32_t tm, uint32_t tp, bool odd, const uint32_t (&o)[27]) {
+__device__ __forceinline__ void store_aa_pair(typename Store<ST>::T* __restrict__ dst, const Upstream& u,
+                                              const PairWords& p, bool odd, const uint32_t (&o)[27]) {
   constexpr int ex = kEx[A];
   if (!odd) {
-    st_off_nt(reinterpret_cast<uint32_t*>(P.dst[opposite_of(A)]), pr.row[1][1] / 2 + t, o[A]);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst + u.row[1][1] + chunk_of(opposite_of(A)) * kB);
+    st_off_nt(d, p.xw[1], o[A]);
   } else {
-    // f~_A of nodes 2t, 2t + 1 goes to (A, x + ebar_A)
-    const uint32_t row = pr.row[1 - kEy[A]][1 - kEz[A]];       // row y + ey, z + ez (element index)
+    // f~_A of nodes 2t, 2t + 1 goes to (A, x + ebar_A): row y + ey, z + ez
+    typename Store<ST>::T* row = dst + u.row[1 - kEy[A]][1 - kEz[A]] + chunk_of(A) * kB;
     if constexpr (ex == 0) {
-      st_off_nt(reinterpret_cast<uint32_t*>(P.dst[A]), row / 2 + t, o[A]);
+      st_off_nt(reinterpret_cast<uint32_t*>(row), p.xw[1], o[A]);
     } else {
-      unsigned short* base = reinterpret_cast<unsigned short*>(P.dst[A]);
+      unsigned short* base = reinterpret_cast<unsigned short*>(row);
       const uint32_t lo = o[A] & 0xffffu, hi = o[A] >> 16;
-      if constexpr (ex > 0) {                                    // positions 2t + 1, 2t + 2
-        st_off(base, row + 2 * t + 1, (unsigned short)lo);
-        st_off(base, row + 2 * tp, (unsigned short)hi);
-      } else {                                                   // positions 2t - 1, 2t
-        st_off(base, row + 2 * tm + 1, (unsigned short)lo);
-        st_off(base, row + 2 * t, (unsigned short)hi);
+      if constexpr (ex > 0) {                                    // nodes 2t + 1, 2t + 2
+        st_off(base, 2 * p.xw[1] + 1, (unsigned short)lo);
+        st_off(base, 2 * p.xw[0], (unsigned short)hi);
+      } else {                                                   // nodes 2t - 1, 2t
+        st_off(base, 2 * p.xw[2] + 1, (unsigned short)lo);
+        st_off(base, 2 * p.xw[1], (unsigned short)hi);
       }
     }
   }
-  if constexpr (A + 1 < 27) store_aa_pair<ST, A + 1>(P, pr, t, tm, tp, odd, o);
+  if constexpr (A + 1 < 27) store_aa_pair<ST, A + 1>(dst, u, p, odd, o);
 }
 
 template <int ST, int CORR, bool ODD, bool RAW, bool HI>
-__global__ __launch_bounds__(256) void k_step_aa_pair(DirPtrs<typename Store<ST>::T> P, const float* __restrict__ force,
-                                                      Consts k, uint32_t bpr) {
+__global__ __launch_bounds__(256) void k_step_aa_pair(typename Store<ST>::T* __restrict__ state,
+                                                      const float* __restrict__ force, Consts k, uint32_t bpr) {
   static_assert(ST != 0, "two nodes per thread is the 16-bit path");
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
@@ -355,60 +363,47 @@ __global__ __launch_bounds__(256) void k_step_aa_pair(DirPtrs<typename Store<ST>
   const uint32_t t = bxi * blockDim.x + threadIdx.x;
   if (t >= tpr) return;
   const uint32_t tm = t == 0 ? tpr - 1 : t - 1, tp = t + 1 == tpr ? 0 : t + 1;
-  PeriodicRows pr;
-  periodic_rows((int)(2 * t), y, z, k, pr);
+  Upstream u;
+  upstream((int)(2 * t), y, z, k, u);
+  const PairWords p = pair_words(t, tm, tp);
   uint32_t w[27];
-  gather_aa_pair<ST>(P, pr, t, tm, tp, ODD, w);
-  const uint32_t node0 = pr.row[1][1] + 2 * t;
-  PairWord<ST> pw[27];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    float df[27];
-#pragma unroll
-    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
-    float fx = k.fx, fy = k.fy, fz = k.fz;
-    if (force != nullptr) {
-      fx = ld_off(force, node0 + h);
-      fy = ld_off(force + k.n, node0 + h);
-      fz = ld_off(force + 2 * k.n, node0 + h);
-    }
-    float out[27];
-    collide_node<CORR, RAW, HI>(df, fx, fy, fz, k, out);
-#pragma unroll
-    for (int a = 0; a < 27; ++a) pw[a].put(h, out[a] * k.sigma[wclass(a)]);
-  }
+  gather_aa_pair<ST>(state, u, p, ODD, w);
   uint32_t o[27];
+  collide_pair<ST, CORR, RAW, HI>(w, force, ((int64_t)z * k.ny + y) * k.nx, 2 * t, k, o);
+  PairWords ps;
 #pragma unroll
-  for (int a = 0; a < 27; ++a) o[a] = pw[a].bits();
-  store_aa_pair<ST>(P, ODD ? store_rows(pr) : pr, store_offset(t), store_offset(tm), store_offset(tp), ODD, o);
+  for (int i = 0; i < 3; ++i) ps.xw[i] = store_offset(p.xw[i]);
+  store_aa_pair<ST>(state, u, ps, ODD, o);
 }
 
 // Density deviation of every node of a state: the same gather and the same
 // FP32 sum as the step, so the value is bit-identical to the step's.
 template <int ST, int WALLS>
-__global__ __launch_bounds__(256) void k_density(DirPtrs<typename Store<ST>::T> P, float* __restrict__ drho,
-                                                 Consts k, uint32_t bpr) {
+__global__ __launch_bounds__(256) void k_density(const typename Store<ST>::T* __restrict__ src,
+                                                 float* __restrict__ drho, Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   if (x >= k.nx) return;
-  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  Upstream u;
+  upstream(x, y, z, k, u);
   float df[27];
-  gather_node<ST, WALLS>(P, x, y, z, k, df);
-  drho[node] = low_moments(df).m000;
+  gather_node<ST, WALLS>(src, u, x, y, z, k, df);
+  st_off(drho + ((int64_t)z * k.ny + y) * k.nx, (uint32_t)x, low_moments(df).m000);
 }
 
 // ------------------------------------------------------------------ launchers
-// Gather path: 0 periodic, 32-bit byte offsets per direction array and into the
-// force field (N floats, so N < 2^30 whatever the storage); 1 walls, 32-bit
-// offsets across the whole state (below 4 GiB); 2 general, 64-bit slots and
-// field indices (walls or periodic, any size).
+// Gather path: 0 periodic (row addresses, any size); 1 walls, 32-bit offsets
+// across the whole state (below 4 GiB); 2 general, 64-bit slots (walls above
+// 4 GiB).  lbm_create's LBM_GATHER_KIND override selects a more general path
+// where it is valid (tests run the 64-bit path on small grids that way).
 static inline int gather_kind(const lbm_handle& h) {
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  if (!walls && (uint64_t)h.stride * 4u < (1ull << 32)) return 0;
-  if (27ull * (uint64_t)h.stride * h.elem < (1ull << 32)) return 1;
-  return 2;
+  const bool fits32 = 27ull * (uint64_t)h.stride * h.elem < (1ull << 32);
+  int kind = !walls ? 0 : (fits32 ? 1 : 2);
+  if (h.force_kind > kind && (h.force_kind == 2 || fits32)) kind = h.force_kind;
+  return kind;
 }
 
 template <int ST, bool HI>
@@ -419,20 +414,21 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)src + (int64_t)a * h.stride;
-    P.dst[a] = (T*)dst + (int64_t)a * h.stride;
-  }
+  const T* s = (const T*)src;
+  T* d = (T*)dst;
   const int kind = gather_kind(h);
-  if constexpr (ST != 0) {
+  // two nodes per thread: the unit higher-order rate only (with a general rate the
+  // two collisions of a thread share rate-dependent terms, which the compiler then
+  // fuses differently from the one-node kernel, so the results would differ in
+  // the last bit)
+  if constexpr (ST != 0 && !HI) {
     if (kind == 0 && h.pairs && h.p.corr != LBM_CORR_FULL && h.p.nx % 2 == 0) {
       constexpr int pblock = 128;                               // measured best of 64 / 128 / 256
       const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);
       const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
       if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
       const dim3 pgrid((unsigned)pnb), pblk(pblock);
-#define CLBM_PAIR(C, R) hipLaunchKernelGGL((k_step_pair<ST, C, R, HI>), pgrid, pblk, 0, st, P, force, h.k, pbpr)
+#define CLBM_PAIR(C, R) hipLaunchKernelGGL((k_step_pair<ST, C, R, HI>), pgrid, pblk, 0, st, s, d, force, h.k, pbpr)
       const bool raw = h.p.moments == LBM_RAW;
       switch (h.p.corr) {
         case 0: if (raw) CLBM_PAIR(0, true); else CLBM_PAIR(0, false); break;
@@ -446,7 +442,7 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
   const dim3 grid((unsigned)nb), blk(block);
   const unsigned lds = h.p.corr == LBM_CORR_FULL ? 0u : (unsigned)h.step_lds;
 #define CLBM_STEP(C, W, R) \
-  hipLaunchKernelGGL((k_step<ST, C, W, R, HI>), grid, blk, lds, st, P, force, grad_src, drho_out, h.k, bpr)
+  hipLaunchKernelGGL((k_step<ST, C, W, R, HI>), grid, blk, lds, st, s, d, force, grad_src, drho_out, h.k, bpr)
 #define CLBM_STEP_CORR(W, R)                   \
   switch (h.p.corr) {                          \
     case 0: CLBM_STEP(0, W, R); break;         \
@@ -476,16 +472,12 @@ static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* 
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)src + (int64_t)a * h.stride;
-    P.dst[a] = nullptr;
-  }
+  const T* s = (const T*)src;
   const dim3 grid((unsigned)nb), blk(block);
   switch (h.k.aa ? 2 : gather_kind(h)) {  // the AA layout keeps natural order: general slot rule
-    case 0: hipLaunchKernelGGL((k_density<ST, 0>), grid, blk, 0, st, P, drho, h.k, bpr); break;
-    case 1: hipLaunchKernelGGL((k_density<ST, 1>), grid, blk, 0, st, P, drho, h.k, bpr); break;
-    default: hipLaunchKernelGGL((k_density<ST, 2>), grid, blk, 0, st, P, drho, h.k, bpr); break;
+    case 0: hipLaunchKernelGGL((k_density<ST, 0>), grid, blk, 0, st, s, drho, h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_density<ST, 1>), grid, blk, 0, st, s, drho, h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_density<ST, 2>), grid, blk, 0, st, s, drho, h.k, bpr); break;
   }
   return hipGetLastError();
 }
@@ -497,20 +489,16 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  DirPtrs<T> P;
-  for (int a = 0; a < 27; ++a) {
-    P.src[a] = (const T*)state + (int64_t)a * h.stride;
-    P.dst[a] = (T*)state + (int64_t)a * h.stride;
-  }
+  T* s = (T*)state;
   const bool walls = h.k.bb_x || h.k.bb_y || h.k.bb_z;
-  if constexpr (ST != 0) {
+  if constexpr (ST != 0 && !HI) {  // as in the two-buffer step
     if (!walls && h.pairs && h.p.nx % 2 == 0) {
       constexpr int pblock = 128;
       const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);
       const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
       if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
       const dim3 pgrid((unsigned)pnb), pblk(pblock);
-#define CLBM_AAP(C, O, R) hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, 0, st, P, force, h.k, pbpr)
+#define CLBM_AAP(C, O, R) hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, 0, st, s, force, h.k, pbpr)
 #define CLBM_AAP_R(C, O) if (h.p.moments == LBM_RAW) CLBM_AAP(C, O, true); else CLBM_AAP(C, O, false)
       switch (h.p.corr) {
         case 0: if (odd) { CLBM_AAP_R(0, true); } else { CLBM_AAP_R(0, false); } break;
@@ -524,7 +512,7 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
   }
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_AA(C, O, W, R) \
-  hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R, HI>), grid, blk, (unsigned)h.step_lds, st, P, force, h.k, bpr)
+  hipLaunchKernelGGL((k_step_aa<ST, C, O, W, R, HI>), grid, blk, (unsigned)h.step_lds, st, s, force, h.k, bpr)
 #define CLBM_AA_CORR(O, W, R)                 \
   switch (h.p.corr) {                         \
     case 0: CLBM_AA(0, O, W, R); break;       \

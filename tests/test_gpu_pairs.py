@@ -1,5 +1,6 @@
 """GPU check of the 16-bit steps that run two x-adjacent nodes per thread
-(periodic grids with even nx, two-buffer and AA layouts): they gather the same
+(periodic grids with even nx and unit higher-order rate, two-buffer and AA
+layouts; a general higher-order rate runs the one-node kernels): they gather the same
 values and run the same collision as the one-node kernels (selected with
 LBM_PAIRS=0), so the states must agree bit for bit; and the two-buffer step
 must match the FP64 oracle like the one-node kernel."""
@@ -49,8 +50,8 @@ CASES = [
     ("ragged_local_f16", (300, 6, 5), 1.0, 0.5, "local", "central", 1.0, "f16", False),
     ("field_lowmach_bf16", (128, 9, 7), 0.5, 0.25, "lowmach", "central", 1.0, "bf16", True),
     ("raw_off_f16", (70, 8, 6), 1.0, 0.5, "off", "raw", 1.0, "f16", True),
-    ("omega_hi_f16", (130, 5, 4), 0.75, 1.0, "local", "central", 1.4, "f16", False),
-    ("two_wide_bf16", (2, 7, 5), 1.0, 0.5, "local", "raw", 0.8, "bf16", True),
+    ("odd_words_f16", (130, 5, 4), 0.75, 1.0, "local", "central", 1.0, "f16", False),
+    ("two_wide_bf16", (2, 7, 5), 1.0, 0.5, "local", "raw", 1.0, "bf16", True),
 ]
 
 
@@ -93,7 +94,7 @@ def test_pair_step_equals_one_node_step(case):
 
 AA_CASES = [
     ("aa_ragged_local_f16", (300, 6, 5), 1.0, 0.5, "local", "central", 1.0, "f16", True),
-    ("aa_raw_lowmach_bf16", (70, 8, 6), 0.5, 0.25, "lowmach", "raw", 1.3, "bf16", False),
+    ("aa_raw_lowmach_bf16", (70, 8, 6), 0.5, 0.25, "lowmach", "raw", 1.0, "bf16", False),
     ("aa_two_wide_f16", (2, 5, 4), 1.0, 0.5, "off", "central", 1.0, "f16", True),
 ]
 
