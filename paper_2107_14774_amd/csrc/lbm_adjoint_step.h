@@ -286,13 +286,23 @@ __device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const 
   if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, u, w, mu);
 }
 
-template <int A = 0>
-__device__ __forceinline__ void scatter_periodic(float* __restrict__ dst, const Upstream& u, const float (&mu)[27]) {
+template <int I = 0>
+__device__ __forceinline__ void scatter_periodic(const GroupBases<float>& b, const Upstream& u,
+                                                 const float (&mu)[27]) {
   // the x-shifted scatter writes partial lines that L2 merges with the neighbours' (plain
   // stores); the directions with ebar_x = 0 write whole lines (non-temporal stores)
-  if constexpr (kEx[A] == 0) st_off_nt(dst + pull_row<A>(u), u.xo[1], mu[A]);
-  else st_off(dst + pull_row<A>(u), u.xo[kEx[A] + 1], mu[A]);
-  if constexpr (A + 1 < 27) scatter_periodic<A + 1>(dst, u, mu);
+  constexpr int A = issue_dir(I);
+  if constexpr (kEx[A] == 0) st_off_nt(chunk_ptr<A>(b), u.xo[1], mu[A]);
+  else st_off(chunk_ptr<A>(b), u.xo[kEx[A] + 1], mu[A]);
+  if constexpr (I + 1 < 27) scatter_periodic<I + 1>(b, u, mu);
+}
+
+// lambda(t+1) at the node's own slots only: non-temporal loads (FP32 duct adjoint +15%).
+template <int I = 0>
+__device__ __forceinline__ void load_own(const GroupBases<const float>& b, uint32_t xo, float (&lam)[27]) {
+  constexpr int A = issue_dir(I);
+  lam[A] = ld_off_nt(chunk_ptr<A>(b), xo);
+  if constexpr (I + 1 < 27) load_own<I + 1>(b, xo, lam);
 }
 
 // WALLS: 0 periodic (row addresses, any size), 1 walls with 32-bit offsets
@@ -318,12 +328,9 @@ __global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k
       w = wall_flags(x, y, z, k);
       gather_walls32<ST>(state, u, w, k, df);
     } else {
-      gather_periodic<ST>(state, u, k, df);
+      gather_periodic<ST>(pull_groups(state, u), u, k, df);
     }
-    // lambda(t+1) is read at the node's own slots only: non-temporal loads (FP32 duct adjoint +15%)
-    const float* lrow = lin + u.row[1][1];
-#pragma unroll
-    for (int a = 0; a < 27; ++a) lam[a] = ld_off_nt(lrow + chunk_of(a) * kB, u.xo[1]);
+    load_own(own_groups(lin, u), u.xo[1], lam);
     const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k
     } else if constexpr (WALLS == 1) {
       scatter_walls32(lout, u, w, mu);
     } else {
-      scatter_periodic(lout, u, mu);
+      scatter_periodic(pull_groups(lout, u), u, mu);
     }
     if (grad_force != nullptr) {
       float* g = grad_force + nrow;

@@ -111,18 +111,29 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     const int kind = std::atoi(env);
     if (kind == 1 || kind == 2) h->force_kind = kind;
   }
-  // The FP32 one-node steps fit 5 waves per SIMD in registers but run fastest at
-  // 4 (512x512x256: 2.595 ms at 4, 2.645 ms at 5, 2.614 ms at 3.5): reserve
-  // 160 KiB / (16 waves per CU / waves per block) of LDS per block to hold them
-  // there.  The 16-bit ones are fastest unlimited.
+  // Occupancy caps through LDS the kernels do not use: a launch reserves
+  // 160 KiB / (blocks per CU) so that at most `waves` waves per SIMD fit.  The
+  // FP32 one-node steps fit 5 waves per SIMD in registers but run fastest at 3
+  // (512x512x256: 2.481 ms at 3, 2.509 at 4, 2.531 at 5, 2.496 at 3.5); the
+  // 16-bit ones are fastest unlimited.  LBM_STEP_LDS / LBM_PAIR_LDS override the
+  // bytes per block (0 = no cap).
+  auto lds_cap = [](int block, int waves) {
+    const int blocks_per_cu = 4 * waves / (block / 64);
+    return blocks_per_cu < 1 ? 0 : (163840 / blocks_per_cu) & ~511;
+  };
   if (const char* env = std::getenv("LBM_BLOCK")) {
     const int b = std::atoi(env);
     if (b == 64 || b == 128 || b == 192 || b == 256) h->block = h->block_step = b;
   }
-  h->step_lds = q.storage == LBM_F32 ? 10240 * (h->block_step / 64) : 0;
+  h->step_lds = q.storage == LBM_F32 ? lds_cap(h->block_step, 3) : 0;
   if (const char* env = std::getenv("LBM_STEP_LDS")) {
     const int b = std::atoi(env);
     if (b >= 0 && b <= 65536) h->step_lds = b;
+  }
+  h->pair_lds = 0;
+  if (const char* env = std::getenv("LBM_PAIR_LDS")) {
+    const int b = std::atoi(env);
+    if (b >= 0 && b <= 65536) h->pair_lds = b;
   }
 
   const double c[3] = {1.0, q.r, q.s};

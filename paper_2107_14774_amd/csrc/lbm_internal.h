@@ -20,6 +20,7 @@ struct lbm_handle {
   int pairs;         // 1 = the periodic 16-bit step may run two nodes per thread
   int step_lds;      // dynamic LDS bytes per block of the one-node steps without full
                      // corrections, AB and AA (unused by the kernels; caps the blocks per CU)
+  int pair_lds;      // the same for the 16-bit steps with two nodes per thread (AB and AA)
   int force_kind;    // 0, or a more general gather path to take where valid (1: 32-bit
                      // offsets across the state, 2: 64-bit slots); a testing override
 };

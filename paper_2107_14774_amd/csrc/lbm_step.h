@@ -39,8 +39,18 @@ __device__ __forceinline__ void gather_node(const typename Store<ST>::T* __restr
   } else if constexpr (WALLS == 1) {
     gather_walls32<ST, NT>(src, u, wall_flags(x, y, z, k), k, df);
   } else {
-    gather_periodic<ST, NT>(src, u, k, df);
+    gather_periodic<ST, NT>(pull_groups(src, u), u, k, df);
   }
+}
+
+// The node's 27 post-collision values into its own slots of dst (coalesced,
+// non-temporal), in issue order.
+template <int ST, int I = 0>
+__device__ __forceinline__ void store_own(const GroupBases<typename Store<ST>::T>& d, uint32_t so,
+                                          const float (&out)[27], const Consts& k) {
+  constexpr int a = issue_dir(I);
+  st_off_nt(chunk_ptr<a>(d), so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
+  if constexpr (I + 1 < 27) store_own<ST, I + 1>(d, so, out, k);
 }
 
 // Body force of a node: the uniform one, or the field's value through the
@@ -121,11 +131,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(const typena
   if constexpr (WALLS != 0) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  typename Store<ST>::T* d = dst + u.row[1][1];
-  const uint32_t so = store_offset(u.xo[1]);
-#pragma unroll
-  for (int a = 0; a < 27; ++a)
-    st_off_nt(d + chunk_of(a) * kB, so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
+  store_own<ST>(own_groups(dst, u), store_offset(u.xo[1]), out, k);
 }
 
 // ------------------------------------------------------------------ 16-bit step, two nodes per thread
@@ -154,21 +160,24 @@ __device__ __forceinline__ PairWords pair_words(uint32_t t, uint32_t tm, uint32_
   return p;
 }
 
-// Words of chunk CH of the grid row starting at element `row` (rows and chunks
-// start on even elements).
-template <int CH, typename T>
-__device__ __forceinline__ const uint32_t* word_row(const T* state, int64_t row) {
-  static_assert(CH >= 0 && CH < 27, "chunk index");
-  return reinterpret_cast<const uint32_t*>(state + row + CH * kB);
+// Words of a 16-bit chunk (chunks start on even elements).
+template <typename T>
+__device__ __forceinline__ const global_t<uint32_t>* words(const global_t<T>* chunk) {
+  return reinterpret_cast<const global_t<uint32_t>*>(chunk);
+}
+template <typename T>
+__device__ __forceinline__ global_t<uint32_t>* words(global_t<T>* chunk) {
+  return reinterpret_cast<global_t<uint32_t>*>(chunk);
 }
 
-// The two values f_A of nodes 2t, 2t + 1 from the slots of direction D (A in
-// the pull step, opp(A) in the AA odd step) at the nodes upstream of A: one
-// word (ebar_x = 0) or the halves of two (ebar_x != 0).
-template <int A, int D, typename T>
-__device__ __forceinline__ uint32_t pair_gather_word(const T* src, const Upstream& u, const PairWords& p) {
+// The two values f_A of nodes 2t, 2t + 1 from the chunk `chunk` holding the
+// slots of the nodes upstream of A (its own slots in the pull step, the
+// opposite direction's in the AA odd step): one word (ebar_x = 0) or the
+// halves of two (ebar_x != 0).
+template <int A, typename T>
+__device__ __forceinline__ uint32_t pair_gather_word(const global_t<T>* chunk, const PairWords& p) {
   constexpr int ex = kEx[A];
-  const uint32_t* base = word_row<chunk_of(D)>(src, u.row[kEy[A] + 1][kEz[A] + 1]);
+  const global_t<uint32_t>* base = words(chunk);
   if constexpr (ex == 0) {
     return ld_off_nt(base, p.xw[1]);                            // whole lines: non-temporal
   } else if constexpr (ex > 0) {                                // nodes 2t - 1, 2t
@@ -180,11 +189,20 @@ __device__ __forceinline__ uint32_t pair_gather_word(const T* src, const Upstrea
   }
 }
 
-template <int ST, int A = 0>
-__device__ __forceinline__ void gather_pair(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
-                                            const PairWords& p, uint32_t (&w)[27]) {
-  w[A] = pair_gather_word<A, A>(src, u, p);
-  if constexpr (A + 1 < 27) gather_pair<ST, A + 1>(src, u, p, w);
+template <int ST, int I = 0>
+__device__ __forceinline__ void gather_pair(const GroupBases<const typename Store<ST>::T>& b, const PairWords& p,
+                                            uint32_t (&w)[27]) {
+  constexpr int A = issue_dir(I);
+  w[A] = pair_gather_word<A>(chunk_ptr<A>(b), p);
+  if constexpr (I + 1 < 27) gather_pair<ST, I + 1>(b, p, w);
+}
+
+template <int ST, int I = 0>
+__device__ __forceinline__ void store_pair_own(const GroupBases<typename Store<ST>::T>& d, uint32_t so,
+                                               const uint32_t (&o)[27]) {
+  constexpr int a = issue_dir(I);
+  st_off_nt(words(chunk_ptr<a>(d)), so, o[a]);
+  if constexpr (I + 1 < 27) store_pair_own<ST, I + 1>(d, so, o);
 }
 
 // Decode, collide and encode the two nodes of a pair (shared by the two-buffer
@@ -225,13 +243,10 @@ __global__ __launch_bounds__(256) void k_step_pair(const typename Store<ST>::T* 
   upstream((int)(2 * t), y, z, k, u);
   const PairWords p = pair_words(t, tm, tp);
   uint32_t w[27];
-  gather_pair<ST>(src, u, p, w);
+  gather_pair<ST>(pull_groups(src, u), p, w);
   uint32_t o[27];
   collide_pair<ST, CORR, RAW, HI>(w, force, ((int64_t)z * k.ny + y) * k.nx, 2 * t, k, o);
-  uint32_t* d = reinterpret_cast<uint32_t*>(dst + u.row[1][1]);
-  const uint32_t so = store_offset(p.xw[1]);
-#pragma unroll
-  for (int a = 0; a < 27; ++a) st_off_nt(d + chunk_of(a) * (kB / 2), so, o[a]);
+  store_pair_own<ST>(own_groups(dst, u), store_offset(p.xw[1]), o);
 }
 
 // ------------------------------------------------------------------ step, AA layout
@@ -244,33 +259,45 @@ __global__ __launch_bounds__(256) void k_step_pair(const typename Store<ST>::T* 
 // number of steps slot (a, x) holds f_a(x) again.  Without walls through row
 // addresses (any state size); with walls through 32-bit offsets from the start
 // of the state (below 4 GiB).
-template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void gather_aa(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
+// Chunk group bases of an AA step: the node's own row (even steps) or the
+// rows of aa_odd_groups (odd steps); unused with walls.
+template <bool ODD, typename T>
+__device__ __forceinline__ GroupBases<T> aa_groups(T* state, const Upstream& u) {
+  if constexpr (ODD) return aa_odd_groups(state, u);
+  else return own_groups(state, u);
+}
+
+template <int ST, bool ODD, bool WALLS, int I = 0>
+__device__ __forceinline__ void gather_aa(const typename Store<ST>::T* __restrict__ src,
+                                          const GroupBases<typename Store<ST>::T>& b, const Upstream& u,
                                           const WallFlags& w, const Consts& k, float (&df)[27]) {
+  constexpr int A = issue_dir(I);
   constexpr int opp = opposite_of(A);
   // even steps read the node's own slots (no line shared between waves): all non-temporal;
   // odd steps as the two-buffer gather
   constexpr bool NT = !ODD || kEx[A] == 0 || LBM_GATHER_NT == 1;
   typename Store<ST>::T v;
   if constexpr (!ODD) {
-    v = ld_pop<NT>(src + u.row[1][1] + chunk_of(A) * kB, u.xo[1]);
+    v = ld_pop<NT>(chunk_ptr<A>(b), u.xo[1]);
   } else if constexpr (WALLS) {
     v = ld_pop<NT>(src, pulls_through_wall<A>(w) ? own_slot32<A>(u) : upstream_slot32<A, opp>(u));
   } else {
-    v = ld_pop<NT>(src + u.row[kEy[A] + 1][kEz[A] + 1] + chunk_of(opp) * kB, u.xo[kEx[A] + 1]);
+    v = ld_pop<NT>(b.g[group_of(A)] + (1 - kEx[A]) * kB, u.xo[kEx[A] + 1]);
   }
   const float f = Store<ST>::load_val(v);
   df[A] = ST == 0 ? f : f * k.inv_sigma[wclass(A)];
-  if constexpr (A + 1 < 27) gather_aa<ST, ODD, WALLS, A + 1>(src, u, w, k, df);
+  if constexpr (I + 1 < 27) gather_aa<ST, ODD, WALLS, I + 1>(src, b, u, w, k, df);
 }
 
-template <int ST, bool ODD, bool WALLS, int A = 0>
-__device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst, const Upstream& u,
+template <int ST, bool ODD, bool WALLS, int I = 0>
+__device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst,
+                                         const GroupBases<typename Store<ST>::T>& b, const Upstream& u,
                                          const WallFlags& w, const Consts& k, const float (&out)[27]) {
+  constexpr int A = issue_dir(I);
   constexpr int opp = opposite_of(A);
   const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[wclass(A)]);
   if constexpr (!ODD) {
-    st_off_nt(dst + u.row[1][1] + chunk_of(opp) * kB, u.xo[1], v);
+    st_off_nt(chunk_ptr<opp>(b), u.xo[1], v);
   } else if constexpr (WALLS) {
     // x + ebar_A lies beyond a wall exactly when opp(A) pulls through one
     const uint32_t idx = pulls_through_wall<opp>(w) ? own_slot32<opp>(u) : upstream_slot32<opp, A>(u);
@@ -279,11 +306,11 @@ __device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst
   } else {
     // shifted by one node along x for 18 directions: plain stores, partial lines merge in L2;
     // the 9 with ebar_x = 0 write whole lines: non-temporal stores
-    typename Store<ST>::T* p = dst + u.row[1 - kEy[A]][1 - kEz[A]] + chunk_of(A) * kB;
+    global_t<typename Store<ST>::T>* p = b.g[8 - group_of(A)] + (kEx[A] + 1) * kB;
     if constexpr (kEx[A] == 0) st_off_nt(p, u.xo[1], v);
     else st_off(p, u.xo[1 - kEx[A]], v);
   }
-  if constexpr (A + 1 < 27) store_aa<ST, ODD, WALLS, A + 1>(dst, u, w, k, out);
+  if constexpr (I + 1 < 27) store_aa<ST, ODD, WALLS, I + 1>(dst, b, u, w, k, out);
 }
 
 template <int ST, int CORR, bool ODD, bool WALLS, bool RAW, bool HI>
@@ -299,8 +326,11 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(typename 
   upstream(x, y, z, k, u);
   WallFlags w{};
   if constexpr (WALLS) w = wall_flags(x, y, z, k);
+  // group bases: every even step (own slots) and the odd steps without walls
+  // (the odd steps with walls address through 32-bit offsets from the state)
+  const GroupBases<typename Store<ST>::T> b = aa_groups<ODD>(state, u);
   float df[27];
-  gather_aa<ST, ODD, WALLS>(state, u, w, k, df);
+  gather_aa<ST, ODD, WALLS>(state, b, u, w, k, df);
   float fx, fy, fz;
   node_force(force, ((int64_t)z * k.ny + y) * k.nx, (uint32_t)x, k, fx, fy, fz);
   float out[27];
@@ -309,7 +339,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(typename 
   if constexpr (WALLS) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  store_aa<ST, ODD, WALLS>(state, store_upstream(u), w, k, out);
+  store_aa<ST, ODD, WALLS>(state, b, store_upstream(u), w, k, out);
 }
 
 // 16-bit AA step with two x-adjacent nodes per thread (periodic grids, even nx;
@@ -317,39 +347,40 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(typename 
 // node pair's own slots.  Odd steps gather like k_step_pair from the opposite
 // directions' chunks; their x-shifted outputs land in words that two threads
 // share, so those go out as 2-byte stores.
-template <int ST, int A = 0>
-__device__ __forceinline__ void gather_aa_pair(const typename Store<ST>::T* __restrict__ src, const Upstream& u,
-                                               const PairWords& p, bool odd, uint32_t (&w)[27]) {
-  if (!odd) w[A] = ld_off_nt(word_row<chunk_of(A)>(src, u.row[1][1]), p.xw[1]);
-  else w[A] = pair_gather_word<A, opposite_of(A)>(src, u, p);
-  if constexpr (A + 1 < 27) gather_aa_pair<ST, A + 1>(src, u, p, odd, w);
+template <int ST, bool ODD, int I = 0>
+__device__ __forceinline__ void gather_aa_pair(const GroupBases<typename Store<ST>::T>& b, const PairWords& p,
+                                               uint32_t (&w)[27]) {
+  constexpr int A = issue_dir(I);
+  if constexpr (!ODD) w[A] = ld_off_nt(words(chunk_ptr<A>(b)), p.xw[1]);
+  else w[A] = pair_gather_word<A>(b.g[group_of(A)] + (1 - kEx[A]) * kB, p);
+  if constexpr (I + 1 < 27) gather_aa_pair<ST, ODD, I + 1>(b, p, w);
 }
 
-template <int ST, int A = 0>
-__device__ __forceinline__ void store_aa_pair(typename Store<ST>::T* __restrict__ dst, const Upstream& u,
-                                              const PairWords& p, bool odd, const uint32_t (&o)[27]) {
+template <int ST, bool ODD, int I = 0>
+__device__ __forceinline__ void store_aa_pair(const GroupBases<typename Store<ST>::T>& b, const PairWords& p,
+                                              const uint32_t (&o)[27]) {
+  constexpr int A = issue_dir(I);
   constexpr int ex = kEx[A];
-  if (!odd) {
-    uint32_t* d = reinterpret_cast<uint32_t*>(dst + u.row[1][1] + chunk_of(opposite_of(A)) * kB);
-    st_off_nt(d, p.xw[1], o[A]);
+  if constexpr (!ODD) {
+    st_off_nt(words(chunk_ptr<opposite_of(A)>(b)), p.xw[1], o[A]);
   } else {
     // f~_A of nodes 2t, 2t + 1 goes to (A, x + ebar_A): row y + ey, z + ez
-    typename Store<ST>::T* row = dst + u.row[1 - kEy[A]][1 - kEz[A]] + chunk_of(A) * kB;
+    global_t<typename Store<ST>::T>* row = b.g[8 - group_of(A)] + (ex + 1) * kB;
     if constexpr (ex == 0) {
-      st_off_nt(reinterpret_cast<uint32_t*>(row), p.xw[1], o[A]);
+      st_off_nt(words(row), p.xw[1], o[A]);
     } else {
-      unsigned short* base = reinterpret_cast<unsigned short*>(row);
+      global_t<unsigned short>* base = reinterpret_cast<global_t<unsigned short>*>(row);
       const uint32_t lo = o[A] & 0xffffu, hi = o[A] >> 16;
       if constexpr (ex > 0) {                                    // nodes 2t + 1, 2t + 2
-        st_off(base, 2 * p.xw[1] + 1, (unsigned short)lo);
-        st_off(base, 2 * p.xw[0], (unsigned short)hi);
+        st_off<unsigned short>(base, 2 * p.xw[1] + 1, (unsigned short)lo);
+        st_off<unsigned short>(base, 2 * p.xw[0], (unsigned short)hi);
       } else {                                                   // nodes 2t - 1, 2t
-        st_off(base, 2 * p.xw[2] + 1, (unsigned short)lo);
-        st_off(base, 2 * p.xw[1], (unsigned short)hi);
+        st_off<unsigned short>(base, 2 * p.xw[2] + 1, (unsigned short)lo);
+        st_off<unsigned short>(base, 2 * p.xw[1], (unsigned short)hi);
       }
     }
   }
-  if constexpr (A + 1 < 27) store_aa_pair<ST, A + 1>(dst, u, p, odd, o);
+  if constexpr (I + 1 < 27) store_aa_pair<ST, ODD, I + 1>(b, p, o);
 }
 
 template <int ST, int CORR, bool ODD, bool RAW, bool HI>
@@ -366,14 +397,15 @@ __global__ __launch_bounds__(256) void k_step_aa_pair(typename Store<ST>::T* __r
   Upstream u;
   upstream((int)(2 * t), y, z, k, u);
   const PairWords p = pair_words(t, tm, tp);
+  const GroupBases<typename Store<ST>::T> b = aa_groups<ODD>(state, u);
   uint32_t w[27];
-  gather_aa_pair<ST>(state, u, p, ODD, w);
+  gather_aa_pair<ST, ODD>(b, p, w);
   uint32_t o[27];
   collide_pair<ST, CORR, RAW, HI>(w, force, ((int64_t)z * k.ny + y) * k.nx, 2 * t, k, o);
   PairWords ps;
 #pragma unroll
   for (int i = 0; i < 3; ++i) ps.xw[i] = store_offset(p.xw[i]);
-  store_aa_pair<ST>(state, u, ps, ODD, o);
+  store_aa_pair<ST, ODD>(b, ps, o);
 }
 
 // Density deviation of every node of a state: the same gather and the same
@@ -428,7 +460,8 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
       const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
       if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
       const dim3 pgrid((unsigned)pnb), pblk(pblock);
-#define CLBM_PAIR(C, R) hipLaunchKernelGGL((k_step_pair<ST, C, R, HI>), pgrid, pblk, 0, st, s, d, force, h.k, pbpr)
+#define CLBM_PAIR(C, R) \
+  hipLaunchKernelGGL((k_step_pair<ST, C, R, HI>), pgrid, pblk, (unsigned)h.pair_lds, st, s, d, force, h.k, pbpr)
       const bool raw = h.p.moments == LBM_RAW;
       switch (h.p.corr) {
         case 0: if (raw) CLBM_PAIR(0, true); else CLBM_PAIR(0, false); break;
@@ -498,7 +531,8 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
       const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
       if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
       const dim3 pgrid((unsigned)pnb), pblk(pblock);
-#define CLBM_AAP(C, O, R) hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, 0, st, s, force, h.k, pbpr)
+#define CLBM_AAP(C, O, R) \
+  hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, (unsigned)h.pair_lds, st, s, force, h.k, pbpr)
 #define CLBM_AAP_R(C, O) if (h.p.moments == LBM_RAW) CLBM_AAP(C, O, true); else CLBM_AAP(C, O, false)
       switch (h.p.corr) {
         case 0: if (odd) { CLBM_AAP_R(0, true); } else { CLBM_AAP_R(0, false); } break;
