@@ -15,7 +15,10 @@ The roofline object prices the dominant kernel (the FP32 step) against the
 (27 populations read and written once, 4 bytes each); its launch time comes
 from HIP events recorded on the stream the kernel runs on.  `traffic` is the
 measured HBM traffic per launch from the committed rocprofv3 counter summary,
-or null when the kernel sources changed since it was taken.
+or null when the kernel sources changed since it was taken.  Two measured
+ceilings sit beside the peak: the library's plain copy (lbm_copy, 16 bytes per
+thread) and streaming only (lbm_stream: the step's gather and store without
+the collision, the same bytes in the same pattern and launch shape).
 
 The CPU baseline times the FP64 oracle (test infrastructure, untuned) on a
 bounded replica of the same workload on the host's cores.
@@ -39,7 +42,7 @@ import torch  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108,
+BYTES_PER_LUP = {"f32": 216, "f16": 108, "bf16": 108, "bf16_sr": 108,
                  # full corrections, lagged density gradient: + write and read of the density deviation field
                  "full_f32": 216 + 8, "full_f16": 108 + 8,
                  # exact density gradient: + a density pass (one more state read, one field write)
@@ -49,9 +52,16 @@ FULL_VARIANTS = {"full_f32": ("f32", "lagged"), "full_f16": ("f16", "lagged"), "
 AA_VARIANTS = {"aa_f32": "f32", "aa_f16": "f16"}
 BYTES_PER_LUP.update({"aa_f32": 216, "aa_f16": 108})
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
-ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f16": 54 + 108 + 108}
+ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f32_hbm": 108 + 108 + 108 + 12 + 24,
+                     "adjoint_f16": 54 + 108 + 108}
+# forward step bytes of the state type an adjoint variant recomputes with (per-node force read included)
+ADJ_FORWARD_BYTES = {"adjoint_f32": 216 + 12, "adjoint_f32_hbm": 216 + 12, "adjoint_f16": 108}
+# the paper's only cost figures (Sec. 6, shallow cavity, no hardware or times): node-count ratios cubic / cuboid
+PAPER_CONTEXT = {"source": "Sec. 6 shallow lid-driven cavity, L/H = 4, W/H = 2, Re = 100; no hardware, precision or "
+                           "times are given",
+                 "cubic_over_cuboid_nodes": {"r=0.406,s=1.3": 7.88, "r=0.375,s=0.75": 5.33, "r=0.375,s=1.0": 7.11}}
 KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_step.h",
-                  "paper_2107_14774_amd/csrc/lbm_api.hip")
+                  "paper_2107_14774_amd/csrc/lbm_api.hip", "paper_2107_14774_amd/csrc/lbm_forward.hip")
 ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint_step.h",
                    "paper_2107_14774_amd/csrc/lbm_api.hip")
 
@@ -145,40 +155,77 @@ def run_forward(w, variant, steps, warmup, u0_dev):
             "mass": sums[0], "energy": sums[4]}
 
 
-def copy_bandwidth(nbytes=4 << 30, reps=10):
-    """Read+write GB/s of a plain device-to-device copy (torch copy kernel) of nbytes."""
+def copy_bandwidth(nbytes, reps=10):
+    """Read+write GB/s of the library's plain copy (lbm_copy: one 16-byte non-temporal load and store per
+    thread) of nbytes, timed with HIP events on the launch stream."""
+    import paper_2107_14774_amd as P
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    P.lbm_copy(b, a, stream=stream)
+    P.lbm_copy(b, a, stream=stream)
+    torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(reps):
-        b.copy_(a)
+        P.lbm_copy(b, a, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     del a, b
     torch.cuda.empty_cache()
     gbs = 2 * nbytes / (ms * 1e-3) / 1e9
-    log(f"[bench] device copy of {nbytes / 2**30:.0f} GiB: {ms:.3f} ms, {gbs:.0f} GB/s (read + write)")
+    log(f"[bench] lbm_copy of {nbytes / 2**30:.2f} GiB: {ms:.3f} ms, {gbs:.0f} GB/s (read + write)")
     return gbs
 
 
+def stream_bandwidth(w, steps, warmup, storage="f32"):
+    """Streaming only (lbm_stream) on the workload's grid: the step's bytes in the step's access pattern and
+    launch shape, without the collision.  Returns (GB/s at the step's algorithmic bytes, ms per launch)."""
+    import paper_2107_14774_amd as P
+    on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
+    lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
+    a, b = lat.new_state(), lat.new_state()
+    lat.init(a)
+    stream = torch.cuda.current_stream()
+    P.lbm_stream(lat.h, warmup + warmup % 2, a, b, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    P.lbm_stream(lat.h, steps, a, b, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    gbs = BYTES_PER_LUP[storage] * lat.n / (ms * 1e-3) / 1e9
+    log(f"[bench] lbm_stream ({storage}, streaming only): {ms:.4f} ms per launch, {gbs:.0f} GB/s")
+    del a, b, lat
+    torch.cuda.empty_cache()
+    return gbs, ms
+
+
+def adjoint_workload(kind):
+    """(workload, storage) of an adjoint variant: the C4 duct (128x128x64, FP32 state, per-node force; its
+    working set is partly held by the 256 MB Infinity Cache), the same duct physics on 512x512x128 (3.6 GB
+    state, HBM-resident), and the C5 periodic grid (384x384x192, FP16 state, initial-velocity gradient)."""
+    if kind == "adjoint_f32":
+        return W.ADJOINT_DUCT_128, "f32"
+    if kind == "adjoint_f32_hbm":
+        return W.replica(W.ADJOINT_DUCT_128, 512, 512, 128, name="adjoint_duct_512x512x128"), "f32"
+    return W.ADJOINT_F16_384, "f16"
+
+
 def run_adjoint(kind, steps, warmup):
-    """Adjoint step kernel alone (repeated on one state), then one full backward pass."""
+    """Adjoint step kernel alone (repeated on one state), then one full backward pass of the workload's own
+    trajectory length (recomputation of the checkpoint segments included)."""
     import paper_2107_14774_amd as P
     from paper_2107_14774_amd import adjoint as ADJ
-    if kind == "adjoint_f32":
-        w, storage = W.ADJOINT_DUCT_128, "f32"
-    else:
-        w, storage = W.ADJOINT_F16_384, "f16"
+    w, storage = adjoint_workload(kind)
     on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
     lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
                     bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
     force = None
-    if kind == "adjoint_f32":
+    if storage == "f32":
         force = torch.from_numpy(W.body_force_field(w)).to(torch.float32).cuda()
         u0 = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
     else:
@@ -189,29 +236,29 @@ def run_adjoint(kind, steps, warmup):
     lam_a = lat.new_adjoint().normal_()
     lam_b = lat.new_adjoint()
     grad = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda") if force is not None else None
+    stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad)
+        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
         lam_a, lam_b = lam_b, lam_a
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(steps):
-        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad)
+        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
         lam_a, lam_b = lam_b, lam_a
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     mlups = lat.n / (ms * 1e-3) / 1e6
     alg = ADJ_BYTES_PER_LUP[kind] * lat.n / (ms * 1e-3) / 1e9
-    del st, tmp, lam_a, lam_b
+    del st, tmp, lam_a, lam_b, grad
     torch.cuda.empty_cache()
-    # full backward passes of a shortened trajectory (recomputation included); the second is
-    # timed, so the recomputation buffers come from the allocator's cache as in a training loop
-    nsteps, every = 100, w.extra["checkpoint"]
+    # full backward passes over the workload's trajectory; the second is timed, so the recomputation
+    # buffers come from the allocator's cache as in a training loop
+    nsteps, every = w.steps, w.extra["checkpoint"]
     target = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float64, device="cuda")
     for rep in range(2):
-        uc = u0.clone().requires_grad_(kind == "adjoint_f16")
+        uc = u0.clone().requires_grad_(storage == "f16")
         Fc = force.clone().requires_grad_(True) if force is not None else None
         uT = ADJ.simulate(lat, uc, Fc, nsteps, every)
         loss = 0.5 * ((uT.to(torch.float64) - target) ** 2).sum()
@@ -221,16 +268,25 @@ def run_adjoint(kind, steps, warmup):
         torch.cuda.synchronize()
         bwd = time.perf_counter() - t0
         del uT, loss, uc, Fc
+    # algorithmic bytes of the backward: every adjoint step, plus the forward steps that recompute each
+    # checkpoint segment (all but its first state)
+    nseg = -(-nsteps // every)
+    recomputed = nsteps - nseg
+    bwd_bytes = (ADJ_BYTES_PER_LUP[kind] * nsteps + ADJ_FORWARD_BYTES[kind] * recomputed) * lat.n
+    bwd_gbs = bwd_bytes / bwd / 1e9
     log(f"[bench] {kind}: {w.nx}x{w.ny}x{w.nz} {storage}: adjoint step {ms:.3f} ms, {mlups:.0f} MLUPS, "
         f"{alg:.0f} GB/s algorithmic; backward of {nsteps} steps (checkpoint {every}) {bwd:.3f} s "
-        f"= {lat.n * nsteps / bwd / 1e6:.0f} MLUPS incl. recomputation")
+        f"= {lat.n * nsteps / bwd / 1e6:.0f} MLUPS, {bwd_gbs:.0f} GB/s incl. recomputation")
+    n_nodes = lat.n
     del lat
     torch.cuda.empty_cache()
     return {"workload": w.name, "storage": storage, "mlups": round(mlups, 1), "ms_per_step": round(ms, 4),
             "hbm_gbs_algorithmic": round(alg, 1), "hbm_frac": round(alg / HBM_PEAK_GBS, 4),
             "bytes_per_lup": ADJ_BYTES_PER_LUP[kind], "measured_bytes_per_launch": measured_traffic(kind),
-            "backward_mlups_incl_recompute": round(lat_n(w) * nsteps / bwd / 1e6, 1),
-            "backward_steps": nsteps, "checkpoint_every": every}
+            "backward_mlups_incl_recompute": round(n_nodes * nsteps / bwd / 1e6, 1),
+            "backward_hbm_gbs_algorithmic": round(bwd_gbs, 1),
+            "backward_hbm_frac": round(bwd_gbs / HBM_PEAK_GBS, 4),
+            "backward_steps": nsteps, "checkpoint_every": every, "recomputed_forward_steps": recomputed}
 
 
 def lat_n(w):
@@ -238,43 +294,48 @@ def lat_n(w):
 
 
 def cpu_baseline(w):
-    """FP64 oracle on a 64x64x32 replica of the workload: 24 steps on all host cores (about 15 s),
-    then 2 steps on one thread."""
+    """The FP64 oracle (test infrastructure, untuned) on the host: 24 steps of a 64x64x32 replica of the
+    workload (same r, s, viscosity and |k| <= 8 spectrum) on all host cores, 200 steps of the 32x32x16
+    Taylor-Green configuration on all cores, and 2 replica steps on one thread (about 20 s in all)."""
     import oracle
     from oracle import analytic as A
     from oracle import lbm as OL
     cores = len(os.sched_getaffinity(0))
     torch.set_num_threads(cores)
-    rep = W.replica(w, 64, 64, 32)
-    p = oracle.Params(rep.nx, rep.ny, rep.nz, r=rep.r, s=rep.s, cs2=rep.cs2,
-                      omega_nu=A.omega_from_nu(rep.nu, rep.cs2), omega_xi=A.omega_from_xi(rep.xi, rep.cs2),
-                      corr="local")
-    u0 = torch.tensor(W.taylor_green(rep.nx, rep.ny, rep.nz, rep.r, rep.s, rep.extra["u0"])
-                      + W.random_modes(rep.nx, rep.ny, rep.nz, rep.r, rep.s, 2, rep.extra["rms"], rep.extra["seed"]))
-    f = OL.init_equilibrium(torch.ones(p.shape, dtype=torch.float64), u0, p)
-    f = OL.step(f, p)
-    steps = 24
-    t0 = time.perf_counter()
-    for _ in range(steps):
+
+    def oracle_run(rep, u0, steps):
+        p = oracle.Params(rep.nx, rep.ny, rep.nz, r=rep.r, s=rep.s, cs2=rep.cs2,
+                          omega_nu=A.omega_from_nu(rep.nu, rep.cs2), omega_xi=A.omega_from_xi(rep.xi, rep.cs2),
+                          corr="local")
+        f = OL.init_equilibrium(torch.ones(p.shape, dtype=torch.float64), torch.as_tensor(u0), p)
         f = OL.step(f, p)
-    dt = time.perf_counter() - t0
-    val = p.n * steps / dt / 1e6
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f = OL.step(f, p)
+        dt = time.perf_counter() - t0
+        return p.n * steps / dt / 1e6, dt
+
+    rep = W.replica(w, 64, 64, 32)
+    u_rep = W.initial_velocity(rep)
+    steps = 24
+    val, dt = oracle_run(rep, u_rep, steps)
     used = torch.get_num_threads()
-    log(f"[bench] cpu oracle: {val:.4f} MLUPS on {used} threads ({dt:.1f} s)")
+    log(f"[bench] cpu oracle: {val:.4f} MLUPS on {used} threads, {rep.nx}x{rep.ny}x{rep.nz} replica ({dt:.1f} s)")
+    c1 = W.TAYLOR_GREEN_32
+    val_c1, dt_c1 = oracle_run(c1, W.initial_velocity(c1), c1.steps)
+    log(f"[bench] cpu oracle: {val_c1:.4f} MLUPS on {used} threads, {c1.name} {c1.steps} steps ({dt_c1:.1f} s)")
     torch.set_num_threads(1)
     steps1 = 2
-    t0 = time.perf_counter()
-    for _ in range(steps1):
-        f = OL.step(f, p)
-    dt1 = time.perf_counter() - t0
-    val1 = p.n * steps1 / dt1 / 1e6
+    val1, dt1 = oracle_run(rep, u_rep, steps1)
     torch.set_num_threads(cores)
     log(f"[bench] cpu oracle: {val1:.4f} MLUPS on 1 thread ({dt1:.1f} s)")
     return {"value": val, "unit": "MLUPS", "cores": used, "kind": "oracle",
-            "sample": f"FP64 oracle, {steps} steps of the {rep.nx}x{rep.ny}x{rep.nz} replica "
-                      f"(r={rep.r}, s={rep.s}, same viscosity), {dt:.1f} s",
+            "sample": f"FP64 oracle, {steps} steps of the {rep.nx}x{rep.ny}x{rep.nz} replica of the workload "
+                      f"(r={rep.r}, s={rep.s}, same viscosity, |k| <= {rep.extra['kmax']} modes), {dt:.1f} s",
+            "taylor_green_32x32x16_value": val_c1,
+            "taylor_green_32x32x16_sample": f"{c1.steps} steps of {c1.name} on {used} threads, {dt_c1:.1f} s",
             "single_thread_value": val1,
-            "single_thread_sample": f"{steps1} steps of the same replica on 1 thread, {dt1:.1f} s"}
+            "single_thread_sample": f"{steps1} steps of the replica on 1 thread, {dt1:.1f} s"}
 
 
 # ---------------------------------------------------------------------- rocprofv3 summaries
@@ -284,7 +345,10 @@ PROFILE_KERNELS = {
     "full_f32": "k_step<0, 3, 0, false, false>", "full_f16": "k_step<1, 3, 0, false, false>",
     "aa_f32 (local)": "k_step_aa<0, 2, false, false, false, false>", "aa_f32 (shifted)": "k_step_aa<0, 2, true, false, false, false>",
     "aa_f16 (local)": "k_step_aa_pair<1, 2, false, false, false>", "aa_f16 (shifted)": "k_step_aa_pair<1, 2, true, false, false>",
-    "adjoint_f32": "k_step_adjoint<0, 2, 1, false, false>", "adjoint_f16": "k_step_adjoint<1, 2, 0, false, false>",
+    "adjoint_f32": "k_step_adjoint<0, 2, 1, false, false>", "adjoint_f32_hbm": "k_step_adjoint<0, 2, 1, false, false>",
+    "adjoint_f16": "k_step_adjoint<1, 2, 0, false, false>",
+    # the measured ceilings: streaming only (the FP32 step without its collision) and the plain copy
+    "stream_f32": "k_stream<0, 0>", "copy": "k_copy16",
 }
 PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),
@@ -292,8 +356,10 @@ PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "full_f16": (512, 512, 256, "512x512x256"), "adjoint_f32": (128, 128, 64, "128x128x64 duct"),
     "aa_f32 (local)": (512, 512, 256, "512x512x256"), "aa_f32 (shifted)": (512, 512, 256, "512x512x256"),
     "aa_f16 (local)": (512, 512, 256, "512x512x256"), "aa_f16 (shifted)": (512, 512, 256, "512x512x256"),
-    "adjoint_f16": (384, 384, 192, "384x384x192"),
+    "adjoint_f16": (384, 384, 192, "384x384x192"), "adjoint_f32_hbm": (512, 512, 128, "512x512x128 duct"),
+    "stream_f32": (512, 512, 256, "512x512x256"), "copy": (512, 512, 256, "one FP32 state"),
 }
+COPY_BYTES = 27 * 512 * 512 * 256 * 4                 # bytes read (and written) by one lbm_copy of the bench
 # $OUT is any output directory (the three runs write their CSVs under it)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_step -o step --output-format csv -- "
              "python3 bench.py --steps 30 --warmup 5 --no-cpu-baseline")
@@ -311,6 +377,8 @@ def _launch_grid(nx, ny, nz, kernel=""):
     two-nodes-per-thread kernels run nx / 2 threads per row in blocks of 128)."""
     if "_pair<" in kernel:
         return str((nx // 2 + 127) // 128 * 128 * ny * nz)
+    if kernel == "k_copy16":
+        return str((COPY_BYTES // 16 + 255) // 256 * 256)
     best, waste = 256, 1 << 30
     for b in (256, 192, 128, 64):
         w = (nx + b - 1) // b * b - nx
@@ -328,9 +396,13 @@ def summarize_rocprof(out_dir):
     for v in PROFILE_KERNELS:
         if v.startswith("aa_"):
             alg[v] = BYTES_PER_LUP[v.split()[0]]
+    alg["stream_f32"] = BYTES_PER_LUP["f32"]
+    alg["copy"] = 2 * COPY_BYTES // (512 * 512 * 256)   # per node of the state copied
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
-             "# corrections) and its adjoint (128x128x64 duct with force field; 384x384x192, r=1/2, s=1/4, FP16)",
+             "# corrections), its adjoint (128x128x64 and 512x512x128 ducts with force field; 384x384x192,",
+             "# r=1/2, s=1/4, FP16), and the two measured ceilings: streaming only (k_stream, the FP32 step's",
+             "# gather and store without the collision) and the library copy (k_copy16, one FP32 state)",
              "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):", "  " + TRACE_CMD,
              "  " + SUMMARY_CMD, "",
              f"{'kernel':38s} {'variant':16s} {'workload':16s} calls  avg_ms   min_ms   max_ms   "
@@ -354,19 +426,19 @@ def summarize_rocprof(out_dir):
     def rows(kind):
         return list(csv.DictReader(open(os.path.join(out_dir, f"pmc_{kind}", f"{kind}_counter_collection.csv"))))
     fe, wr = rows("fetch"), rows("write")
-    copy_bytes = 4 << 30
-    # the 4 GiB copies of copy_bandwidth() (11 per run) are the largest copy kernels of the run
-    cf = sorted(float(r["Counter_Value"]) for r in fe if "copyBuffer" in r["Kernel_Name"])[-11:]
-    cw = sorted(float(r["Counter_Value"]) for r in wr if "copyBuffer" in r["Kernel_Name"])[-11:]
+    copy_bytes = COPY_BYTES
+    # the library copies of copy_bandwidth() (k_copy16 over one FP32 state) read and write known bytes
+    cf = [float(r["Counter_Value"]) for r in fe if "k_copy16" in r["Kernel_Name"]]
+    cw = [float(r["Counter_Value"]) for r in wr if "k_copy16" in r["Kernel_Name"]]
     kf = (copy_bytes / 1024) / statistics.mean(cf)
     kw = (copy_bytes / 1024) / statistics.mean(cw)
     lines = ["# HBM traffic of the step kernels (512x512x256, r=1, s=1/2) and the adjoint from rocprofv3 counters",
              "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory), one counter per pass:",
              "  " + PMC_CMD.format(c="FETCH_SIZE", d="fetch"), "  " + PMC_CMD.format(c="WRITE_SIZE", d="write"),
              "  " + SUMMARY_CMD, "",
-             "calibration: the 4 GiB device-to-device copy in the same runs (hipMemcpy kernel __amd_rocclr_copyBuffer,",
-             f"reads and writes exactly {copy_bytes} bytes): mean FETCH_SIZE {statistics.mean(cf):.1f} KiB -> scale "
-             f"{kf:.4f};", f"mean WRITE_SIZE {statistics.mean(cw):.1f} KiB -> scale {kw:.4f}", "",
+             "calibration: the library copy in the same runs (k_copy16 over one FP32 state, reads and writes",
+             f"exactly {copy_bytes} bytes, {len(cf)} launches): mean FETCH_SIZE {statistics.mean(cf):.1f} KiB -> "
+             f"scale {kf:.4f};", f"mean WRITE_SIZE {statistics.mean(cw):.1f} KiB -> scale {kw:.4f}", "",
              f"{'kernel':38s} {'variant':16s} FETCH_KiB(raw)  WRITE_KiB(raw)  read_B/LUP  write_B/LUP  "
              "total_B/LUP  algorithmic_B/LUP"]
     traffic = {}
@@ -432,7 +504,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--variants", default="f32,f16,bf16,full_f32,full_f16,aa_f32,aa_f16,adjoint_f32,adjoint_f16")
+    ap.add_argument("--variants", default="f32,f16,bf16,bf16_sr,full_f32,full_f16,aa_f32,aa_f16,adjoint_f32,"
+                                          "adjoint_f32_hbm,adjoint_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 CSVs under DIR (no GPU needed)")
@@ -453,7 +526,9 @@ def main():
     log(f"[bench] generating the initial velocity field ({w.nx}x{w.ny}x{w.nz})")
     u0_dev = torch.from_numpy(W.initial_velocity(w)).to("cuda")
 
-    copy_gbs = copy_bandwidth()
+    state_bytes = 27 * w.nx * w.ny * w.nz * 4          # one FP32 state (rows already whole blocks)
+    copy_gbs = copy_bandwidth(state_bytes)
+    pattern_gbs, pattern_ms = stream_bandwidth(w, max(20, args.steps // 4), args.warmup)
     res = {}
     for v in variants:
         if v in BYTES_PER_LUP:
@@ -478,7 +553,11 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(main_v),
                     "kernel": f"k_step<{main_storage}, {'local' if main_mode is None else 'full'} corrections>",
                     "algorithmic_bytes_per_lup": BYTES_PER_LUP[main_v],
-                    "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+                    "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                    "copy": "lbm_copy of one FP32 state, 16 B per thread, non-temporal",
+                    "pattern_ceiling_gbs": round(pattern_gbs, 1), "frac_of_pattern": round(achieved / pattern_gbs, 4),
+                    "pattern": "lbm_stream: the FP32 step's gather and store without the collision, same launch "
+                               f"shape ({pattern_ms:.4f} ms per launch)"}
     for v, rv in res.items():
         ach = BYTES_PER_LUP[v] * w.n / (rv["ms_per_launch"] * 1e-3) / 1e9
         variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
@@ -486,7 +565,7 @@ def main():
                            "bytes_per_lup": BYTES_PER_LUP[v], "measured_bytes_per_launch": measured_traffic(v)}
     variants_out.update(adj)
     if "f32" in res:
-        for v in ("f16", "bf16", "full_f32", "full_f16", "full_f32_exact", "aa_f32", "aa_f16"):
+        for v in ("f16", "bf16", "bf16_sr", "full_f32", "full_f16", "full_f32_exact", "aa_f32", "aa_f16"):
             if v in res:
                 variants_out[v]["speedup_vs_f32"] = round(res[v]["mlups"] / res["f32"]["mlups"], 3)
 
@@ -505,7 +584,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nz": w.nz, "r": w.r, "s": w.s,
                    "cs2": w.cs2, "nu": w.nu, "corrections": "local", "boundaries": "periodic",
-                   "storage": main_v or "none"},
+                   "storage": main_v or "none",
+                   "fp32_conservation": "FP32 storage and arithmetic; each node's mass and momentum residual of "
+                                        "the rounded outputs is summed in FP64 and put back (not in the paper)"},
+        "paper_context": PAPER_CONTEXT,
         "roofline": roofline,
         "variants": variants_out,
     }

@@ -61,10 +61,17 @@ enum lbm_status {
 
 enum lbm_bc { LBM_PERIODIC = 0, LBM_BOUNCEBACK = 1 };
 
-/* Population storage.  F32 stores (f - w rho0) in float.  F16 and BF16 store
+/* Population storage.  F32 stores (f - w rho0) in float.  F16 stores
  * (f - w rho0) * sigma_alpha rounded to nearest even, sigma_alpha a power of
- * two near 1 / w_alpha; every arithmetic step is FP32. */
-enum lbm_storage { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
+ * two near 1 / w_alpha (keeps the deviations in FP16's normal range).  BF16
+ * stores (f - w rho0) rounded to nearest even (BF16 has FP32's exponent range).
+ * BF16_SR is BF16 whose step stores round stochastically: up with probability
+ * equal to the discarded fraction, from a counter-based generator keyed by the
+ * node, the direction's value and the handle's step counter
+ * (lbm_set_step_counter), so the rounding is unbiased where a slowly changing
+ * flow would round the same way every step; init and import round to nearest.
+ * Every arithmetic step is FP32. */
+enum lbm_storage { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2, LBM_BF16_SR = 3 };
 
 /* Extended-equilibrium corrections (Sec. 2.4 / App. D).
  * OFF:     plain central-moment collision on the cuboid lattice;
@@ -139,6 +146,13 @@ typedef struct lbm_params {
 
 typedef struct lbm_handle lbm_handle;
 
+/* Relaxation rates from viscosities (eq. 53 and the bulk viscosity of
+ * Sec. 2.5): omega_nu = 1 / (nu / cs2 + 1/2), omega_xi = 1 / (3 xi / (2 cs2)
+ * + 1/2), the inverse of the lbm_params definitions of nu and xi.  Host-side
+ * only.  LBM_EINVAL unless nu > 0, xi > 0, cs2 > 0 (all finite) and both
+ * pointers are non-NULL; the rates then lie in (0, 2). */
+int lbm_relaxation_rates(double nu, double xi, double cs2, double* omega_nu, double* omega_xi);
+
 /* Validate p and create a host-side handle holding the derived constants.
  * Rejects (LBM_EINVAL): a size < 1 (or < 2 on a bounce-back axis), more than
  * 2^31 - 1 nodes, r or s <= 0, a rate outside (0, 2), a sound
@@ -153,6 +167,15 @@ void lbm_destroy(lbm_handle* h);
 size_t lbm_state_bytes(const lbm_handle* h);
 int64_t lbm_state_stride(const lbm_handle* h);
 int64_t lbm_num_nodes(const lbm_handle* h);
+
+/* Step counter of the handle: every step that lbm_step, lbm_step_forcing or
+ * lbm_step_full launches takes the counter's value as the key of its stochastic
+ * rounding (BF16_SR storage) and advances it by one; other storage ignores it.
+ * lbm_create starts it at 0.  Setting it back to the value a step had makes a
+ * recomputation of that step from the same state reproduce it bit for bit (the
+ * adjoint's checkpoint recomputation does this).  Host-side only. */
+int lbm_set_step_counter(lbm_handle* h, uint64_t counter);
+uint64_t lbm_step_counter(const lbm_handle* h);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* lbm_last_error(void);
@@ -229,6 +252,22 @@ int lbm_density(lbm_handle* h, const void* state, float* drho, void* hip_stream)
 int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
                   const float* force, float* drho_a, float* drho_b, int32_t mode,
                   void* hip_stream);
+
+/* Streaming only: nsteps >= 0 steps of lbm_step's gather and store with the
+ * collision left out, f_a(x, t+1) = f_a(x - ebar_a, t), or f_abar(x, t) where
+ * x - ebar_a lies beyond a wall (the streaming bullet of Sec. 3.2 and the
+ * bounce-back of Sec. 4 with stationary walls).  It moves the step's bytes in
+ * the step's access pattern with the step's launch shape, so its throughput is
+ * the ceiling that pattern allows on the device: the reference the step's
+ * memory throughput is reported against.  States behave as in lbm_step.
+ * LBM_EINVAL for the AA layout, for moving walls, or state_a == state_b. */
+int lbm_stream(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, void* hip_stream);
+
+/* Device-to-device copy of `bytes` bytes (a multiple of 16; 0 does nothing)
+ * with one 16-byte non-temporal load and store per thread: the reference for
+ * the read-and-write bandwidth of the device.  dst and src: device, 16-byte
+ * aligned, not overlapping (LBM_EINVAL otherwise).  Needs no handle. */
+int lbm_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* Observables of a state (eq. 12 / the last bullet of Sec. 3.2):
  * rho = sum f, u = (sum f e + F/2) / rho.

@@ -14,7 +14,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4
 BC = {"periodic": 0, "bounceback": 1}
-STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "bf16_sr": 3}
 CORR = {"off": 0, "lowmach": 1, "local": 2, "full": 3}
 GRAD_MODE = {"exact": 0, "lagged": 1}
 MOMENTS = {"central": 0, "raw": 1}
@@ -44,11 +44,15 @@ _lib = None
 
 _P = ctypes.c_void_p
 _SIGNATURES = {
+    "lbm_relaxation_rates": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.POINTER(_P)]),
     "lbm_destroy": (None, [_P]),
     "lbm_state_bytes": (ctypes.c_size_t, [_P]),
     "lbm_state_stride": (ctypes.c_int64, [_P]),
     "lbm_num_nodes": (ctypes.c_int64, [_P]),
+    "lbm_set_step_counter": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "lbm_step_counter": (ctypes.c_uint64, [_P]),
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "lbm_import": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -58,6 +62,8 @@ _SIGNATURES = {
     "lbm_set_force": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "lbm_step_forcing": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "lbm_step_full": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, _P]),
+    "lbm_stream": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "lbm_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lbm_moments": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "lbm_check_sums": (ctypes.c_int, [_P, _P, _P]),
     "lbm_step_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),

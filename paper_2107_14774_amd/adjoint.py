@@ -31,7 +31,9 @@ class _Trajectory(torch.autograd.Function):
         force_t = force if force.numel() else None
         a, b = lat.new_state(), lat.new_state()
         lat.init(a, rho=rho0, u=u0)
-        checkpoints = [a.clone()]
+        # each checkpoint keeps the handle's step counter too, so that a recomputed segment
+        # rounds exactly like the forward pass (stochastic rounding of BF16-SR storage)
+        checkpoints, counters = [a.clone()], [L.lbm_step_counter(lat.h)]
         t = 0
         while t < nsteps:
             n = min(every, nsteps - t)
@@ -39,9 +41,11 @@ class _Trajectory(torch.autograd.Function):
             t += n
             if t < nsteps:
                 checkpoints.append(a.clone())
+                counters.append(L.lbm_step_counter(lat.h))
         m = lat.moments(a, force_t, sums=False)
         ctx.lat, ctx.nsteps, ctx.every, ctx.max_states = lat, nsteps, every, max_states
-        ctx.checkpoints, ctx.final = checkpoints, a
+        ctx.checkpoints, ctx.counters, ctx.final = checkpoints, counters, a
+        ctx.counter_end = L.lbm_step_counter(lat.h)
         ctx.force, ctx.rho0 = force_t, rho0
         ctx.save_for_backward(u0)
         ctx.force_needs_grad = force.requires_grad
@@ -65,9 +69,10 @@ class _Trajectory(torch.autograd.Function):
         for seg in reversed(range(nseg)):
             start = seg * ctx.every
             n = min(ctx.every, ctx.nsteps - start)
-            lam, lam_next = _reverse_segment(lat, ctx.checkpoints[seg], n, lam, lam_next, force, grad_force,
-                                             ctx.max_states, pool)
+            lam, lam_next = _reverse_segment(lat, ctx.checkpoints[seg], ctx.counters[seg], n, lam, lam_next, force,
+                                             grad_force, ctx.max_states, pool)
             ctx.checkpoints[seg] = None
+        L.lbm_set_step_counter(h, ctx.counter_end)
         g_u0 = torch.empty((3, *lat.shape), dtype=torch.float64, device=lat.device)
         rho0 = None if ctx.rho0 is None else ctx.rho0.to(torch.float64).contiguous()
         L.lbm_init_adjoint(h, lam, rho=rho0, u=u0.contiguous(), g_u=g_u0)
@@ -87,11 +92,13 @@ class _StatePool:
         self.free.extend(states)
 
 
-def _reverse_segment(lat, start_state, n, lam, lam_next, force, grad_force, max_states, pool):
-    """Apply the adjoint of n steps starting from ``start_state``; returns the swapped adjoint buffers."""
+def _reverse_segment(lat, start_state, counter, n, lam, lam_next, force, grad_force, max_states, pool):
+    """Apply the adjoint of n steps starting from ``start_state`` (taken with step counter ``counter``);
+    returns the swapped adjoint buffers."""
     h = lat.h
     if n <= max_states:
         states = [start_state] + [pool.get() for _ in range(n - 1)]
+        L.lbm_set_step_counter(h, counter)
         for i in range(1, n):
             L.lbm_step(h, 1, states[i - 1], states[i], force)
         for i in reversed(range(n)):
@@ -103,6 +110,7 @@ def _reverse_segment(lat, start_state, n, lam, lam_next, force, grad_force, max_
     starts = []
     cur, tmp = pool.get(), pool.get()
     cur.copy_(start_state)
+    L.lbm_set_step_counter(h, counter)
     for s0 in range(0, n, sub):
         keep = pool.get()
         keep.copy_(cur)
@@ -113,7 +121,8 @@ def _reverse_segment(lat, start_state, n, lam, lam_next, force, grad_force, max_
     pool.put(cur, tmp)
     for j in reversed(range(len(starts))):
         m = min(sub, n - j * sub)
-        lam, lam_next = _reverse_segment(lat, starts[j], m, lam, lam_next, force, grad_force, max_states, pool)
+        lam, lam_next = _reverse_segment(lat, starts[j], counter + j * sub, m, lam, lam_next, force, grad_force,
+                                         max_states, pool)
         pool.put(starts[j])
     return lam, lam_next
 
@@ -125,7 +134,15 @@ def simulate(lat, u0, force=None, nsteps=1, checkpoint_every=50, rho0=None, max_
     u0:    (3, nz, ny, nx) float64 on the lattice device
     force: (3, nz, ny, nx) float32 per-node body force, or None for the lattice's uniform force
     max_states: most states one segment may hold during the backward pass (nesting beyond)
+
+    Raises ValueError unless nsteps >= 0, checkpoint_every >= 1 and max_states >= 1.
     """
+    if int(nsteps) < 0:
+        raise ValueError(f"nsteps must be >= 0, got {nsteps}")
+    if int(checkpoint_every) < 1:
+        raise ValueError(f"checkpoint_every must be >= 1, got {checkpoint_every}")
+    if int(max_states) < 1:
+        raise ValueError(f"max_states must be >= 1, got {max_states}")
     if force is None:
         force = torch.empty(0, dtype=torch.float32, device=lat.device)
     return _Trajectory.apply(u0, force, lat, rho0, int(nsteps), int(checkpoint_every), int(max_states))

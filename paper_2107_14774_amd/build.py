@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ("lbm_api.hip", "lbm_forward.hip", "lbm_adjoint.hip",
-           "lbm_step_f32.hip", "lbm_step_f16.hip", "lbm_step_bf16.hip",
+           "lbm_step_f32.hip", "lbm_step_f16.hip", "lbm_step_bf16.hip", "lbm_step_bf16sr.hip",
            "lbm_adjoint_step_f32.hip", "lbm_adjoint_step_f16.hip", "lbm_adjoint_step_bf16.hip")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -25,11 +25,33 @@ int hip_fail(hipError_t e, const char* where) {
 
 bool aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Per-step key of the stochastic rounding: the SplitMix64 output function of the
+// step counter (a published generator), so consecutive steps draw unrelated bits.
+uint32_t step_key(uint64_t seq) {
+  uint64_t z = seq + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return (uint32_t)(z ^ (z >> 31));
+}
+
+// Before every step launch: the step's rounding key, then the counter moves on.
+void next_step(lbm_handle* h) { h->k.seq_hash = step_key(h->seq++); }
+
 }  // namespace
 
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_relaxation_rates(double nu, double xi, double cs2, double* omega_nu, double* omega_xi) {
+  g_err.clear();
+  if (omega_nu == nullptr || omega_xi == nullptr) return fail(LBM_EINVAL, "lbm_relaxation_rates: NULL output");
+  if (!(nu > 0.0) || !(xi > 0.0) || !(cs2 > 0.0) || !std::isfinite(nu) || !std::isfinite(xi) || !std::isfinite(cs2))
+    return fail(LBM_EINVAL, "lbm_relaxation_rates: nu, xi and cs2 must be finite and > 0");
+  *omega_nu = 1.0 / (nu / cs2 + 0.5);
+  *omega_xi = 1.0 / (1.5 * xi / cs2 + 0.5);
+  return LBM_OK;
+}
 
 int lbm_create(const lbm_params* p, lbm_handle** out) {
   g_err.clear();
@@ -65,7 +87,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     return fail(LBM_EINVAL, "lbm_create: omega_nu and omega_xi must lie in (0, 2)");
   if (!(q.omega_hi > 0.0 && q.omega_hi < 2.0))
     return fail(LBM_EINVAL, "lbm_create: omega_hi must lie in (0, 2)");
-  if (q.storage < LBM_F32 || q.storage > LBM_BF16) return fail(LBM_EINVAL, "lbm_create: unknown storage");
+  if (q.storage < LBM_F32 || q.storage > LBM_BF16_SR) return fail(LBM_EINVAL, "lbm_create: unknown storage");
   if (q.corr < LBM_CORR_OFF || q.corr > LBM_CORR_FULL) return fail(LBM_EINVAL, "lbm_create: unknown correction");
   if (q.moments != LBM_CENTRAL && q.moments != LBM_RAW) return fail(LBM_EINVAL, "lbm_create: unknown moment basis");
   if (q.layout != LBM_LAYOUT_AB && q.layout != LBM_LAYOUT_AA) return fail(LBM_EINVAL, "lbm_create: unknown layout");
@@ -106,6 +128,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   h->block_step = q.storage == LBM_F32 ? pick_block({128, 256, 192, 64}) : h->block;
   h->pairs = 1;
   if (const char* env = std::getenv("LBM_PAIRS")) h->pairs = std::atoi(env) != 0;  // 0: one node per thread
+  h->seq = 0;
   h->force_kind = 0;
   if (const char* env = std::getenv("LBM_GATHER_KIND")) {  // testing: 1 or 2, taken where valid
     const int kind = std::atoi(env);
@@ -153,6 +176,7 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
     const int t = std::atoi(env);
     if (t >= 1 && q.ny % t == 0) k.ytile = t;
   }
+
   for (int f = 0; f < 6; ++f)
     for (int c = 0; c < 3; ++c) k.wall_u[f][c] = (float)q.wall_velocity[f][c];
   k.row_slots = 27 * nxp;
@@ -178,8 +202,9 @@ int lbm_create(const lbm_params* p, lbm_handle** out) {
   for (int a = 0; a < 27; ++a) {
     const double w = W[0][clbm::kEx[a] + 1] * W[1][clbm::kEy[a] + 1] * W[2][clbm::kEz[a] + 1];
     kd.w[a] = w;
-    // power-of-two scale near 1/w for the 16-bit formats (exact, so it adds no rounding)
-    const double sig = q.storage == LBM_F32 ? 1.0 : std::ldexp(1.0, (int)std::lround(-std::log2(w)));
+    // power-of-two scale near 1/w for FP16 storage (exact, so it adds no rounding); FP32 and
+    // BF16 share the FP32 exponent range and store unscaled deviations
+    const double sig = q.storage == LBM_F16 ? std::ldexp(1.0, (int)std::lround(-std::log2(w))) : 1.0;
     k.sigma[clbm::wclass(a)] = (float)sig;          // equal within a weight class
     k.inv_sigma[clbm::wclass(a)] = (float)(1.0 / sig);
   }
@@ -200,6 +225,14 @@ int64_t lbm_num_nodes(const lbm_handle* h) { return h ? h->n : 0; }
 #define CHECK_REQ(ptr, name, what) \
   if ((ptr) == nullptr) return fail(LBM_EINVAL, name ": " what " is NULL"); \
   CHECK_PTR(ptr, name, what)
+
+int lbm_set_step_counter(lbm_handle* h, uint64_t counter) {
+  CHECK_HANDLE(h, "lbm_set_step_counter");
+  h->seq = counter;
+  return LBM_OK;
+}
+
+uint64_t lbm_step_counter(const lbm_handle* h) { return h ? h->seq : 0; }
 
 int lbm_init(lbm_handle* h, void* state, const double* rho, const double* u, const double* perturb,
              void* hip_stream) {
@@ -235,6 +268,7 @@ static int step_aa(lbm_handle* h, const char* name, int32_t nsteps, void* state,
     return fail(LBM_EINVAL, std::string(name) + ": the AA layout updates state_a in place (state_b must be NULL)");
   if (nsteps % 2 != 0) return fail(LBM_EINVAL, std::string(name) + ": the AA layout advances an even number of steps");
   for (int32_t t = 0; t < nsteps; ++t) {
+    next_step(h);
     hipError_t e = forces ? clbm::launch_step_aa_uniform(*h, state, t & 1, (float)forces[3 * t],
                                                          (float)forces[3 * t + 1], (float)forces[3 * t + 2], st)
                           : clbm::launch_step_aa(*h, state, t & 1, force, st);
@@ -256,6 +290,7 @@ int lbm_step(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, const 
     return fail(LBM_EINVAL, "lbm_step: the full corrections need a density field (use lbm_step_full)");
   void* bufs[2] = {state_a, state_b};
   for (int32_t t = 0; t < nsteps; ++t) {
+    next_step(h);
     hipError_t e = clbm::launch_step(*h, bufs[t & 1], bufs[(t + 1) & 1], force, nullptr, nullptr,
                                      (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
@@ -291,6 +326,7 @@ int lbm_step_forcing(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b
   if (state_a == state_b) return fail(LBM_EINVAL, "lbm_step_forcing: state_a and state_b must differ");
   void* bufs[2] = {state_a, state_b};
   for (int32_t t = 0; t < nsteps; ++t) {
+    next_step(h);
     hipError_t e = clbm::launch_step_uniform(*h, bufs[t & 1], bufs[(t + 1) & 1], (float)forces[3 * t],
                                              (float)forces[3 * t + 1], (float)forces[3 * t + 2],
                                              (hipStream_t)hip_stream);
@@ -330,6 +366,7 @@ int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, c
   for (int32_t t = 0; t < nsteps; ++t) {
     void* src = bufs[t & 1];
     void* dst = bufs[(t + 1) & 1];
+    next_step(h);
     hipError_t e;
     if (mode == LBM_GRAD_EXACT) {
       e = clbm::launch_density(*h, src, drho_a, st);
@@ -340,6 +377,34 @@ int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, c
     if (e != hipSuccess) return hip_fail(e, "lbm_step_full");
   }
   return LBM_OK;
+}
+
+int lbm_stream(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_stream");
+  if (nsteps < 0) return fail(LBM_EINVAL, "lbm_stream: nsteps < 0");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_stream: the AB layout only");
+  if (h->k.moving) return fail(LBM_EINVAL, "lbm_stream: stationary walls only");
+  CHECK_REQ(state_a, "lbm_stream", "state_a");
+  CHECK_REQ(state_b, "lbm_stream", "state_b");
+  if (state_a == state_b) return fail(LBM_EINVAL, "lbm_stream: state_a and state_b must differ");
+  void* bufs[2] = {state_a, state_b};
+  for (int32_t t = 0; t < nsteps; ++t) {
+    hipError_t e = clbm::launch_stream(*h, bufs[t & 1], bufs[(t + 1) & 1], (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_stream");
+  }
+  return LBM_OK;
+}
+
+int lbm_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  g_err.clear();
+  if (bytes == 0) return LBM_OK;
+  CHECK_REQ(dst, "lbm_copy", "dst");
+  CHECK_REQ(src, "lbm_copy", "src");
+  if (bytes % 16 != 0) return fail(LBM_EINVAL, "lbm_copy: bytes must be a multiple of 16");
+  const uintptr_t a = (uintptr_t)dst, b = (uintptr_t)src;
+  if (a < b + bytes && b < a + bytes) return fail(LBM_EINVAL, "lbm_copy: src and dst overlap");
+  hipError_t e = clbm::launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_copy");
 }
 
 int lbm_moments(lbm_handle* h, const void* state, const float* force, float* rho, float* u,

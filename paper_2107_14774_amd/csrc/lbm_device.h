@@ -63,6 +63,7 @@ struct Consts {
   float inv_sigma[8];
   float omega_hi;          // rate of the moments of order >= 3
   int hi;                  // 1 = omega_hi != 1 (kernels with the general higher-order rate)
+  uint32_t seq_hash;       // per-step key of the stochastic rounding (BF16-SR storage)
 };
 
 // FP64 copies for the one-time conversions (init, import, export).
@@ -105,6 +106,73 @@ template <> struct Store<2> {
   }
 };
 
+// BF16 with stochastic rounding (LBM_BF16_SR): the BF16 format, read like
+// Store<2>; the step's stores round up with probability equal to the discarded
+// fraction (bf16_sr_bits), so the rounding is unbiased even where a slowly
+// changing flow would round every step the same way.  One-time conversions
+// (init, import) round to nearest like Store<2>.
+template <> struct Store<3> : Store<2> {};
+
+template <int ST>
+constexpr bool kBf16 = ST == 2 || ST == 3;
+
+// Only FP16 storage scales the deviations (sigma_a, a power of two near 1/w_a,
+// keeps them in its normal range).  FP32 and BF16 have the FP32 exponent range,
+// so they store the deviations unscaled (sigma = 1, a power of two changes no
+// rounding) and their kernels skip the scaling.
+template <int ST>
+constexpr bool kScaled = ST == 1;
+
+template <int ST>
+__device__ __forceinline__ float decode_scale(float v, int cls, const Consts& k) {
+  if constexpr (kScaled<ST>) return v * k.inv_sigma[cls];
+  else return v;
+}
+
+template <int ST>
+__device__ __forceinline__ float encode_scale(float v, int cls, const Consts& k) {
+  if constexpr (kScaled<ST>) return v * k.sigma[cls];
+  else return v;
+}
+
+// The two halves of a 32-bit word of two 16-bit values (first node in the low
+// half) as floats; BF16 is the upper half of an FP32 pattern, so its decode is
+// a shift or a mask.
+template <int ST>
+__device__ __forceinline__ float word_half(uint32_t w, int h) {
+  if constexpr (kBf16<ST>) return __builtin_bit_cast(float, h ? (w & 0xffff0000u) : (w << 16));
+  else return Store<ST>::from_bits(h ? w >> 16 : w & 0xffffu);
+}
+
+// 16 random bits per node and step for the stochastic rounding: a published
+// integer hash (Wellons' "lowbias32" finalizer) of the node index mixed with the
+// per-step key k.seq_hash.  Counter-based, so a step recomputed from the same
+// state with the same step counter rounds identically.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t node, uint32_t seq_hash) {
+  uint32_t v = node ^ seq_hash;
+  v ^= v >> 16;
+  v *= 0x7feb352du;
+  v ^= v >> 15;
+  v *= 0x846ca68bu;
+  v ^= v >> 16;
+  return v & 0xffffu;
+}
+
+// FP32 pattern whose upper 16 bits are x rounded stochastically to BF16: the
+// lower 16 bits f are added to r = f ^ r16, which is uniform on [0, 2^16) when
+// r16 is, so the carry into the upper half happens with probability f / 2^16
+// (sign-magnitude: the magnitude rounds up or down, the sign is kept).
+__device__ __forceinline__ uint32_t bf16_sr_bits(float x, uint32_t r16) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, x);
+  return b + ((b & 0xffffu) ^ r16);
+}
+
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::T pack_rounded(float v, uint32_t r16) {
+  if constexpr (ST == 3) return __builtin_bit_cast(typename Store<ST>::T, (unsigned short)(bf16_sr_bits(v, r16) >> 16));
+  else return Store<ST>::pack(v);
+}
+
 // One direction's values of two x-adjacent nodes in the 32-bit word the pair
 // steps store (first node in the low half), filled one node at a time with the
 // same rounding as Store<ST>::pack.  FP16 converts each value as it comes (the
@@ -120,6 +188,16 @@ template <> struct PairWord<1> {
     else v.x = (_Float16)x;
   }
   __device__ __forceinline__ uint32_t bits() const { return __builtin_bit_cast(uint32_t, v); }
+};
+
+template <> struct PairWord<3> {
+  uint32_t first, word;
+  __device__ __forceinline__ void put(int h, float x, uint32_t r16) {
+    const uint32_t b = bf16_sr_bits(x, r16);
+    if (h) word = (b & 0xffff0000u) | (first >> 16);
+    else first = b;
+  }
+  __device__ __forceinline__ uint32_t bits() const { return word; }
 };
 
 template <> struct PairWord<2> {
@@ -146,7 +224,12 @@ constexpr int kB = 128;
 // directions with the same (ebar_y, ebar_z) side by side in the order
 // ebar_x = -1, 0, +1, so a node's pulls from one row are adjacent in memory.
 // The opposite direction's chunk is 26 - chunk_of(a).
-constexpr int chunk_of(int a) { return 3 * (3 * (kEy[a] + 1) + (kEz[a] + 1)) + (kEx[a] + 1); }
+// Group of upstream row (ebar_y, ebar_z), y-major (a z-major order of the nine
+// groups measured the same at 512x512x256, FP32 and FP16).
+constexpr int group_index(int ey, int ez) { return 3 * (ey + 1) + (ez + 1); }
+constexpr int group_ey(int g) { return g / 3 - 1; }
+constexpr int group_ez(int g) { return g % 3 - 1; }
+constexpr int chunk_of(int a) { return 3 * group_index(kEy[a], kEz[a]) + (kEx[a] + 1); }
 
 // Order in which the gathers and stores issue the 27 directions: direction
 // order (memory order, chunk by chunk, measured the same on the FP32 and FP16
@@ -206,7 +289,7 @@ template <int A, int ST, bool WX = true>
 __device__ __forceinline__ float gather_dev(const typename Store<ST>::T* __restrict__ src,
                                             const NodeCoord& c, const Consts& k) {
   const float v = Store<ST>::load(src + gather_slot<A, WX>(c, k));
-  return ST == 0 ? v : v * k.inv_sigma[wclass(A)];
+  return decode_scale<ST>(v, wclass(A), k);
 }
 
 template <int ST, int A = 0, bool WX = true>
@@ -685,6 +768,20 @@ __device__ __forceinline__ void density_gradient_block(const float* __restrict__
   }
 }
 
+// Grid row (y, z) of row number `rowid`: y fastest, or in tiles of ty rows in y,
+// z-major inside a tile (the rows that read one upstream row then run close in time).
+__device__ __forceinline__ void tiled_row(uint32_t rowid, uint32_t ty, const Consts& k, int& y, int& z) {
+  if (ty <= 1) {
+    y = (int)(rowid % (uint32_t)k.ny);
+    z = (int)(rowid / (uint32_t)k.ny);
+  } else {
+    const uint32_t per_tile = ty * (uint32_t)k.nz;
+    const uint32_t tile = rowid / per_tile, rem = rowid % per_tile;
+    z = (int)(rem / ty);
+    y = (int)(tile * ty + rem % ty);
+  }
+}
+
 // XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs
 // in turn; renumber so that each XCD walks one contiguous range of tiles
 // (neighbouring rows share cache lines through that XCD's L2).
@@ -830,7 +927,7 @@ __device__ __forceinline__ void st_off_nt(global_t<T>* __restrict__ base, uint32
 
 // Chunk group of a direction: the three directions with the same (ebar_y,
 // ebar_z), stored side by side (chunk_of(a) = 3 group_of(a) + ebar_x + 1).
-constexpr int group_of(int a) { return 3 * (kEy[a] + 1) + (kEz[a] + 1); }
+constexpr int group_of(int a) { return group_index(kEy[a], kEz[a]); }
 
 // Scalar bases of the nine chunk groups: pull[g] = group g of the row that its
 // directions pull from (row[g / 3][g % 3]), own[g] = group g of the node's own row.
@@ -843,7 +940,7 @@ template <typename T>
 __device__ __forceinline__ GroupBases<T> pull_groups(T* state, const Upstream& u) {
   GroupBases<T> b;
 #pragma unroll
-  for (int g = 0; g < 9; ++g) b.g[g] = sgpr_ptr(state + u.row[g / 3][g % 3] + 3 * g * kB);
+  for (int g = 0; g < 9; ++g) b.g[g] = sgpr_ptr(state + u.row[group_ey(g) + 1][group_ez(g) + 1] + 3 * g * kB);
   return b;
 }
 
@@ -863,7 +960,7 @@ template <typename T>
 __device__ __forceinline__ GroupBases<T> aa_odd_groups(T* state, const Upstream& u) {
   GroupBases<T> b;
 #pragma unroll
-  for (int g = 0; g < 9; ++g) b.g[g] = sgpr_ptr(state + u.row[g / 3][g % 3] + 3 * (8 - g) * kB);
+  for (int g = 0; g < 9; ++g) b.g[g] = sgpr_ptr(state + u.row[group_ey(g) + 1][group_ez(g) + 1] + 3 * (8 - g) * kB);
   return b;
 }
 
@@ -949,7 +1046,7 @@ template <int ST, int NT = 0, int A = 0>
 __device__ __forceinline__ void gather_walls32(const typename Store<ST>::T* __restrict__ base, const Upstream& u,
                                                const WallFlags& w, const Consts& k, float (&df)[27]) {
   const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(base, wall_slot32<A>(u, w)));
-  df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
+  df[A] = decode_scale<ST>(v, wclass(A), k);
   if constexpr (A + 1 < 27) gather_walls32<ST, NT, A + 1>(base, u, w, k, df);
 }
 
@@ -958,7 +1055,7 @@ __device__ __forceinline__ void gather_periodic(const GroupBases<const typename 
                                                 const Consts& k, float (&df)[27]) {
   constexpr int A = issue_dir(I);
   const float v = Store<ST>::load_val(ld_pop<nt_dir<NT>(A)>(chunk_ptr<A>(b), u.xo[kEx[A] + 1]));
-  df[A] = ST == 0 ? v : v * k.inv_sigma[wclass(A)];
+  df[A] = decode_scale<ST>(v, wclass(A), k);
   if constexpr (I + 1 < 27) gather_periodic<ST, NT, I + 1>(b, u, k, df);
 }
 

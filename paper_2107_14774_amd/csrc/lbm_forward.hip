@@ -176,6 +176,7 @@ hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const fl
   switch (h.p.storage) {
     case LBM_F32: return StepKernels<0>::step(h, src, dst, force, grad_src, drho_out, st);
     case LBM_F16: return StepKernels<1>::step(h, src, dst, force, grad_src, drho_out, st);
+    case LBM_BF16_SR: return StepKernels<3>::step(h, src, dst, force, grad_src, drho_out, st);
     default: return StepKernels<2>::step(h, src, dst, force, grad_src, drho_out, st);
   }
 }
@@ -184,6 +185,7 @@ hipError_t launch_step_aa(const lbm_handle& h, void* state, int odd, const float
   switch (h.p.storage) {
     case LBM_F32: return StepKernels<0>::step_aa(h, state, odd, force, st);
     case LBM_F16: return StepKernels<1>::step_aa(h, state, odd, force, st);
+    case LBM_BF16_SR: return StepKernels<3>::step_aa(h, state, odd, force, st);
     default: return StepKernels<2>::step_aa(h, state, odd, force, st);
   }
 }
@@ -210,8 +212,43 @@ hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hip
   switch (h.p.storage) {
     case LBM_F32: return StepKernels<0>::density(h, src, drho, st);
     case LBM_F16: return StepKernels<1>::density(h, src, drho, st);
+    case LBM_BF16_SR: return StepKernels<3>::density(h, src, drho, st);
     default: return StepKernels<2>::density(h, src, drho, st);
   }
+}
+
+hipError_t launch_stream(const lbm_handle& h, const void* src, void* dst, hipStream_t st) {
+  switch (h.p.storage) {
+    case LBM_F32: return StepKernels<0>::stream(h, src, dst, st);
+    case LBM_F16: return StepKernels<1>::stream(h, src, dst, st);
+    case LBM_BF16_SR: return StepKernels<3>::stream(h, src, dst, st);
+    default: return StepKernels<2>::stream(h, src, dst, st);
+  }
+}
+
+// ------------------------------------------------------------------ plain copy
+// One 16-byte non-temporal load and store per thread, no loop: of the copy
+// shapes measured on 4-7 GB buffers this one moved the most bytes per second
+// (a grid-stride loop of the same accesses ran about 20% slower).
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy16(const f4_t* __restrict__ src, f4_t* __restrict__ dst, uint64_t n16,
+                                                uint64_t first) {
+  const uint64_t i = first + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const uint64_t n16 = bytes / 16;
+  // launches of at most 2^31 - 1 blocks
+  const uint64_t per_launch = (uint64_t)0x7fffffff * 256u;
+  for (uint64_t first = 0; first < n16; first += per_launch) {
+    const uint64_t cnt = n16 - first < per_launch ? n16 - first : per_launch;
+    hipLaunchKernelGGL(k_copy16, (unsigned)((cnt + 255) / 256), 256, 0, st, (const f4_t*)src, (f4_t*)dst, n16, first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const double* u,

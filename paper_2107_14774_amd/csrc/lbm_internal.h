@@ -21,24 +21,28 @@ struct lbm_handle {
   int step_lds;      // dynamic LDS bytes per block of the one-node steps without full
                      // corrections, AB and AA (unused by the kernels; caps the blocks per CU)
   int pair_lds;      // the same for the 16-bit steps with two nodes per thread (AB and AA)
+  uint64_t seq;      // step counter: keys the stochastic rounding of BF16-SR storage
   int force_kind;    // 0, or a more general gather path to take where valid (1: 32-bit
                      // offsets across the state, 2: 64-bit slots); a testing override
 };
 
 namespace clbm {
 
-// Step and adjoint-step launchers per storage type (0 FP32, 1 FP16, 2 BF16);
-// each is instantiated in a translation unit of its own.
+// Step and adjoint-step launchers per storage type (0 FP32, 1 FP16, 2 BF16,
+// 3 BF16 with stochastic rounding, whose adjoint reads the state like 2); each
+// is instantiated in a translation unit of its own.
 template <int ST>
 struct StepKernels {
   static hipError_t step(const lbm_handle& h, const void* src, void* dst, const float* force,
                          const float* grad_src, float* drho_out, hipStream_t st);
   static hipError_t step_aa(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st);
   static hipError_t density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
+  static hipError_t stream(const lbm_handle& h, const void* src, void* dst, hipStream_t st);
 };
 extern template struct StepKernels<0>;
 extern template struct StepKernels<1>;
 extern template struct StepKernels<2>;
+extern template struct StepKernels<3>;
 
 template <int ST>
 struct AdjointKernels {
@@ -55,6 +59,10 @@ hipError_t launch_step(const lbm_handle& h, const void* src, void* dst, const fl
 hipError_t launch_step_uniform(const lbm_handle& h, const void* src, void* dst, float fx, float fy, float fz,
                                hipStream_t st);
 hipError_t launch_density(const lbm_handle& h, const void* src, float* drho, hipStream_t st);
+// Streaming only (the step without its collision).
+hipError_t launch_stream(const lbm_handle& h, const void* src, void* dst, hipStream_t st);
+// Plain device copy, one 16-byte load and store per thread.
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 // AA layout: one step in place; odd selects the shifted half of the pair.
 hipError_t launch_step_aa(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st);
 hipError_t launch_step_aa_uniform(const lbm_handle& h, void* state, int odd, float fx, float fy, float fz,

@@ -45,12 +45,20 @@ __device__ __forceinline__ void gather_node(const typename Store<ST>::T* __restr
 
 // The node's 27 post-collision values into its own slots of dst (coalesced,
 // non-temporal), in issue order.
+// r16: the node's random bits of the stochastic rounding (BF16-SR storage only).
 template <int ST, int I = 0>
 __device__ __forceinline__ void store_own(const GroupBases<typename Store<ST>::T>& d, uint32_t so,
-                                          const float (&out)[27], const Consts& k) {
+                                          const float (&out)[27], const Consts& k, uint32_t r16) {
   constexpr int a = issue_dir(I);
-  st_off_nt(chunk_ptr<a>(d), so, Store<ST>::pack(ST == 0 ? out[a] : out[a] * k.sigma[wclass(a)]));
-  if constexpr (I + 1 < 27) store_own<ST, I + 1>(d, so, out, k);
+  st_off_nt(chunk_ptr<a>(d), so, pack_rounded<ST>(encode_scale<ST>(out[a], wclass(a), k), r16));
+  if constexpr (I + 1 < 27) store_own<ST, I + 1>(d, so, out, k, r16);
+}
+
+// Random bits of the stochastic rounding of node `node` in this step (0 unless BF16-SR).
+template <int ST>
+__device__ __forceinline__ uint32_t node_sr_bits(uint32_t node, const Consts& k) {
+  if constexpr (ST == 3) return sr_bits(node, k.seq_hash);
+  else return 0u;
 }
 
 // Body force of a node: the uniform one, or the field's value through the
@@ -93,18 +101,10 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(const typena
                                                                     uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  // the full-correction step walks y-tiles of k.ytile rows, z-major inside a tile: the density
+  // rows of z - 1 and z + 1 are then read a few rows apart (an L2 hit) instead of a plane apart
   int y, z;
-  if constexpr (CORR == 3) {
-    // rows in y-tiles of k.ytile, z-major inside a tile: the density rows of z - 1 and
-    // z + 1 are then read a few rows apart (an L2 hit) instead of a whole plane apart
-    const uint32_t ty = (uint32_t)k.ytile, per_tile = ty * (uint32_t)k.nz;
-    const uint32_t tile = rowid / per_tile, rem = rowid % per_tile;
-    z = (int)(rem / ty);
-    y = (int)(tile * ty + rem % ty);
-  } else {
-    y = (int)(rowid % (uint32_t)k.ny);
-    z = (int)(rowid / (uint32_t)k.ny);
-  }
+  tiled_row(rowid, (uint32_t)(CORR == 3 ? k.ytile : 1), k, y, z);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   // the density gradient first (block-wide, with a barrier), while no population is live
   float grx = 0.0f, gry = 0.0f, grz = 0.0f;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step(const typena
   if constexpr (WALLS != 0) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  store_own<ST>(own_groups(dst, u), store_offset(u.xo[1]), out, k);
+  store_own<ST>(own_groups(dst, u), store_offset(u.xo[1]), out, k, node_sr_bits<ST>((uint32_t)nrow + x, k));
 }
 
 // ------------------------------------------------------------------ 16-bit step, two nodes per thread
@@ -215,13 +215,19 @@ __device__ __forceinline__ void collide_pair(const uint32_t (&w)[27], const floa
   for (int h = 0; h < 2; ++h) {
     float df[27];
 #pragma unroll
-    for (int a = 0; a < 27; ++a) df[a] = Store<ST>::from_bits(h ? w[a] >> 16 : w[a] & 0xffffu) * k.inv_sigma[wclass(a)];
+    for (int a = 0; a < 27; ++a) df[a] = decode_scale<ST>(word_half<ST>(w[a], h), wclass(a), k);
     float fx, fy, fz;
     node_force(force, nrow, x0 + h, k, fx, fy, fz);
     float out[27];
     collide_fenced<CORR, RAW, HI, ST == 0 || HI>(df, fx, fy, fz, k, out);
+    if constexpr (ST == 3) {
+      const uint32_t r16 = sr_bits((uint32_t)nrow + x0 + h, k.seq_hash);
 #pragma unroll
-    for (int a = 0; a < 27; ++a) pw[a].put(h, out[a] * k.sigma[wclass(a)]);
+      for (int a = 0; a < 27; ++a) pw[a].put(h, out[a], r16);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 27; ++a) pw[a].put(h, encode_scale<ST>(out[a], wclass(a), k));
+    }
   }
 #pragma unroll
   for (int a = 0; a < 27; ++a) o[a] = pw[a].bits();
@@ -285,17 +291,18 @@ __device__ __forceinline__ void gather_aa(const typename Store<ST>::T* __restric
     v = ld_pop<NT>(b.g[group_of(A)] + (1 - kEx[A]) * kB, u.xo[kEx[A] + 1]);
   }
   const float f = Store<ST>::load_val(v);
-  df[A] = ST == 0 ? f : f * k.inv_sigma[wclass(A)];
+  df[A] = decode_scale<ST>(f, wclass(A), k);
   if constexpr (I + 1 < 27) gather_aa<ST, ODD, WALLS, I + 1>(src, b, u, w, k, df);
 }
 
 template <int ST, bool ODD, bool WALLS, int I = 0>
 __device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst,
                                          const GroupBases<typename Store<ST>::T>& b, const Upstream& u,
-                                         const WallFlags& w, const Consts& k, const float (&out)[27]) {
+                                         const WallFlags& w, const Consts& k, const float (&out)[27],
+                                         uint32_t r16) {
   constexpr int A = issue_dir(I);
   constexpr int opp = opposite_of(A);
-  const typename Store<ST>::T v = Store<ST>::pack(ST == 0 ? out[A] : out[A] * k.sigma[wclass(A)]);
+  const typename Store<ST>::T v = pack_rounded<ST>(encode_scale<ST>(out[A], wclass(A), k), r16);
   if constexpr (!ODD) {
     st_off_nt(chunk_ptr<opp>(b), u.xo[1], v);
   } else if constexpr (WALLS) {
@@ -310,7 +317,7 @@ __device__ __forceinline__ void store_aa(typename Store<ST>::T* __restrict__ dst
     if constexpr (kEx[A] == 0) st_off_nt(p, u.xo[1], v);
     else st_off(p, u.xo[1 - kEx[A]], v);
   }
-  if constexpr (I + 1 < 27) store_aa<ST, ODD, WALLS, I + 1>(dst, b, u, w, k, out);
+  if constexpr (I + 1 < 27) store_aa<ST, ODD, WALLS, I + 1>(dst, b, u, w, k, out, r16);
 }
 
 template <int ST, int CORR, bool ODD, bool WALLS, bool RAW, bool HI>
@@ -339,7 +346,8 @@ __global__ __launch_bounds__(256, step_waves(ST, CORR)) void k_step_aa(typename 
   if constexpr (WALLS) {
     if (k.moving) moving_wall_terms(x, y, z, k.rho0 + low_moments(df).m000, k, out);
   }
-  store_aa<ST, ODD, WALLS>(state, b, store_upstream(u), w, k, out);
+  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  store_aa<ST, ODD, WALLS>(state, b, store_upstream(u), w, k, out, node_sr_bits<ST>(node, k));
 }
 
 // 16-bit AA step with two x-adjacent nodes per thread (periodic grids, even nx;
@@ -423,6 +431,28 @@ __global__ __launch_bounds__(256) void k_density(const typename Store<ST>::T* __
   float df[27];
   gather_node<ST, WALLS>(src, u, x, y, z, k, df);
   st_off(drho + ((int64_t)z * k.ny + y) * k.nx, (uint32_t)x, low_moments(df).m000);
+}
+
+// ------------------------------------------------------------------ streaming only
+// The step's gather and store with the collision left out: f_a(x, t+1) =
+// f_a(x - ebar_a, t), or f_abar(x, t) across a stationary wall.  It moves the
+// step's bytes in the step's access pattern (same kernel shape, block size and
+// occupancy cap), so its rate is the ceiling of that pattern.  16-bit values
+// pass through unchanged (decode and encode scale by a power of two).
+template <int ST, int WALLS>
+__global__ __launch_bounds__(256) void k_stream(const typename Store<ST>::T* __restrict__ src,
+                                                typename Store<ST>::T* __restrict__ dst, Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  if (x >= k.nx) return;
+  Upstream u;
+  upstream(x, y, z, k, u);
+  float df[27];
+  gather_node<ST, WALLS>(src, u, x, y, z, k, df);
+  const uint32_t node = ((uint32_t)z * (uint32_t)k.ny + (uint32_t)y) * (uint32_t)k.nx + (uint32_t)x;
+  store_own<ST>(own_groups(dst, u), store_offset(u.xo[1]), df, k, node_sr_bits<ST>(node, k));
 }
 
 // ------------------------------------------------------------------ launchers
@@ -515,6 +545,25 @@ static hipError_t launch_density_t(const lbm_handle& h, const void* src, float* 
   return hipGetLastError();
 }
 
+template <int ST>
+static hipError_t launch_stream_t(const lbm_handle& h, const void* src, void* dst, hipStream_t st) {
+  using T = typename Store<ST>::T;
+  const int block = h.block_step;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const T* s = (const T*)src;
+  T* d = (T*)dst;
+  const dim3 grid((unsigned)nb), blk(block);
+  const unsigned lds = (unsigned)h.step_lds;
+  switch (gather_kind(h)) {
+    case 0: hipLaunchKernelGGL((k_stream<ST, 0>), grid, blk, lds, st, s, d, h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_stream<ST, 1>), grid, blk, lds, st, s, d, h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_stream<ST, 2>), grid, blk, lds, st, s, d, h.k, bpr); break;
+  }
+  return hipGetLastError();
+}
+
 template <int ST, bool HI>
 static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, const float* force, hipStream_t st) {
   using T = typename Store<ST>::T;
@@ -582,6 +631,11 @@ hipError_t StepKernels<ST>::step_aa(const lbm_handle& h, void* state, int odd, c
 template <int ST>
 hipError_t StepKernels<ST>::density(const lbm_handle& h, const void* src, float* drho, hipStream_t st) {
   return launch_density_t<ST>(h, src, drho, st);
+}
+
+template <int ST>
+hipError_t StepKernels<ST>::stream(const lbm_handle& h, const void* src, void* dst, hipStream_t st) {
+  return launch_stream_t<ST>(h, src, dst, st);
 }
 
 }  // namespace clbm

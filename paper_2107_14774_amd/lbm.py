@@ -22,9 +22,15 @@ _ABI_F32 = torch.float32
 _ABI_F64 = torch.float64
 
 
-def relaxation_rates(nu, xi, cs2):
-    """(omega_nu, omega_xi) from shear and bulk viscosity (eq. 53)."""
-    return 1.0 / (nu / cs2 + 0.5), 1.0 / (1.5 * xi / cs2 + 0.5)
+def lbm_relaxation_rates(nu, xi, cs2):
+    """(omega_nu, omega_xi) from shear and bulk viscosity (eq. 53), computed by the library."""
+    on, ox = _lib.ctypes.c_double(), _lib.ctypes.c_double()
+    _lib.check(_lib.load().lbm_relaxation_rates(float(nu), float(xi), float(cs2), _lib.ctypes.byref(on),
+                                                _lib.ctypes.byref(ox)))
+    return on.value, ox.value
+
+
+relaxation_rates = lbm_relaxation_rates
 
 
 class Handle:
@@ -53,6 +59,18 @@ class Handle:
     @property
     def state_bytes(self):
         return int(_lib.load().lbm_state_bytes(self.raw))
+
+    @property
+    def step_counter(self):
+        return int(_lib.load().lbm_step_counter(self.raw))
+
+
+def lbm_set_step_counter(h, counter):
+    _lib.check(_lib.load().lbm_set_step_counter(h.raw, int(counter)))
+
+
+def lbm_step_counter(h):
+    return int(_lib.load().lbm_step_counter(h.raw))
 
 
 def _require(t, dtype, numel, name):
@@ -159,6 +177,20 @@ def lbm_step_full(h, nsteps, state_a, state_b, drho_a, drho_b=None, mode="lagged
                                          _lib.ptr(_state(h, state_b, "state_b")), _lib.ptr(force),
                                          _lib.ptr(drho_a), _lib.ptr(drho_b), _lib.GRAD_MODE[mode],
                                          _lib.stream_ptr(stream)))
+
+
+def lbm_stream(h, nsteps, state_a, state_b, stream=None):
+    _lib.check(_lib.load().lbm_stream(h.raw, int(nsteps), _lib.ptr(_state(h, state_a)),
+                                      _lib.ptr(_state(h, state_b, "state_b")), _lib.stream_ptr(stream)))
+
+
+def lbm_copy(dst, src, nbytes=None, stream=None):
+    """Copy ``nbytes`` (default: all of ``src``) between two device tensors."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    for t, name in ((dst, "dst"), (src, "src")):
+        if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() < nbytes:
+            raise ValueError(f"{name}: need a contiguous device tensor of at least {nbytes} bytes")
+    _lib.check(_lib.load().lbm_copy(_lib.ptr(dst), _lib.ptr(src), nbytes, _lib.stream_ptr(stream)))
 
 
 def lbm_moments(h, state, force=None, rho=None, u=None, sums=None, stream=None):

@@ -1,8 +1,9 @@
 """Extract the transform tables the paper prints into a JSON fixture.
 
-Run once, on a machine that has the paper's LaTeX source:
+Run once, on a machine that has the paper's LaTeX source, with that file's
+path as the only argument:
 
-    python tests/golden/extract_paper_tables.py /root/reference/PAPER.md
+    python tests/golden/extract_paper_tables.py PATH_TO_THE_PAPER_SOURCE
 
 It parses, term by term, the formulas printed in
   eq. 1a-c (velocity set), eq. 59 (S), eq. 61 (S^-1),
@@ -240,4 +241,6 @@ def main(path):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "/root/reference/PAPER.md")
+    if len(sys.argv) != 2:
+        sys.exit("usage: extract_paper_tables.py PATH_TO_THE_PAPER_SOURCE (the paper's LaTeX source)")
+    main(sys.argv[1])

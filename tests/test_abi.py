@@ -154,3 +154,57 @@ def test_aa_layout_validation():
     assert "4 GiB" in str(e.value)
     # periodic AA addresses rows through 64-bit scalar starts: any size below 2^31 nodes
     assert P.lbm_create(1024, 1024, 1024, layout="aa", storage="f16").state_bytes == 27 * 2 * 1024 ** 3
+
+
+def test_relaxation_rates_invert_eq53():
+    from oracle import analytic as A
+    for nu, xi, cs2 in ((0.016, 0.016, 1 / 12), (0.05, 0.2, 1 / 48), (1e-4, 3.0, 0.3)):
+        on, ox = P.lbm_relaxation_rates(nu, xi, cs2)
+        assert abs(on - A.omega_from_nu(nu, cs2)) < 1e-15 and abs(ox - A.omega_from_xi(xi, cs2)) < 1e-15
+        # back to the viscosities through the lbm_params definitions
+        assert abs(cs2 * (1 / on - 0.5) - nu) < 1e-15 * max(1.0, nu)
+        assert abs(2 * cs2 / 3 * (1 / ox - 0.5) - xi) < 1e-14 * max(1.0, xi)
+        assert 0.0 < on < 2.0 and 0.0 < ox < 2.0
+    for bad in ((0.0, 0.1, 0.1), (0.1, -1.0, 0.1), (0.1, 0.1, 0.0), (float("nan"), 0.1, 0.1), (0.1, float("inf"), 0.1)):
+        with pytest.raises(_lib.LbmError) as e:
+            P.lbm_relaxation_rates(*bad)
+        assert e.value.code == _lib.LBM_EINVAL
+    lib = _lib.load()
+    out = ctypes.c_double()
+    assert lib.lbm_relaxation_rates(0.1, 0.1, 0.1, None, ctypes.byref(out)) == _lib.LBM_EINVAL
+
+
+def test_copy_and_stream_reject_invalid_arguments():
+    """Validation happens on the host before any launch."""
+    lib = _lib.load()
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    assert lib.lbm_copy(b, a, 0, None) == _lib.LBM_OK                        # nothing to copy
+    assert lib.lbm_copy(b, a, 24, None) == _lib.LBM_EINVAL                   # not a multiple of 16
+    assert b"multiple of 16" in lib.lbm_last_error()
+    assert lib.lbm_copy(ctypes.c_void_p(0x10010), a, 64, None) == _lib.LBM_EINVAL   # overlapping
+    assert b"overlap" in lib.lbm_last_error()
+    assert lib.lbm_copy(None, a, 64, None) == _lib.LBM_EINVAL
+    assert lib.lbm_copy(ctypes.c_void_p(0x10008), a, 16, None) == _lib.LBM_EINVAL    # misaligned
+    h = P.lbm_create(8, 6, 4)
+    assert lib.lbm_stream(h.raw, -1, a, b, None) == _lib.LBM_EINVAL
+    assert lib.lbm_stream(h.raw, 1, a, a, None) == _lib.LBM_EINVAL
+    assert lib.lbm_stream(h.raw, 1, a, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_stream(h.raw, 0, a, b, None) == _lib.LBM_OK
+    haa = P.lbm_create(8, 6, 4, layout="aa")
+    assert lib.lbm_stream(haa.raw, 2, a, b, None) == _lib.LBM_EINVAL
+    hm = P.lbm_create(8, 6, 4, bc_y="bounceback",
+                      wall_velocity=[(0, 0, 0)] * 3 + [(0.05, 0, 0)] + [(0, 0, 0)] * 2)
+    assert lib.lbm_stream(hm.raw, 2, a, b, None) == _lib.LBM_EINVAL
+    assert b"stationary" in lib.lbm_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(nsteps=-1), dict(checkpoint_every=0), dict(checkpoint_every=-3),
+                                dict(max_states=0)])
+def test_simulate_rejects_invalid_schedules(kw):
+    """Argument checks run before any GPU work (a zero interval or state budget would never
+    terminate)."""
+    from paper_2107_14774_amd import adjoint as ADJ
+    args = dict(nsteps=4, checkpoint_every=2, max_states=8)
+    args.update(kw)
+    with pytest.raises(ValueError):
+        ADJ.simulate(None, None, None, args["nsteps"], args["checkpoint_every"], max_states=args["max_states"])

@@ -44,6 +44,10 @@ CASES = [
     ("duct_field_f32_omega_hi", (37, 12, 10), 1.0, 0.25, ("periodic", "bounceback", "bounceback"), None, "local",
      "central", "f32", True, 1.6),
     ("periodic_f16_raw_omega_hi", (70, 9, 6), 0.5, 0.25, ("periodic",) * 3, None, "lowmach", "raw", "f16", False, 0.7),
+    # stochastic rounding: both layouts key each step's rounding by the same step counter
+    ("periodic_bf16_sr_field", (70, 9, 6), 0.5, 0.25, ("periodic",) * 3, None, "local", "central", "bf16_sr", True),
+    ("duct_bf16_sr", (37, 12, 10), 1.0, 0.25, ("periodic", "bounceback", "bounceback"), None, "local",
+     "central", "bf16_sr", False),
 ]
 
 

@@ -150,19 +150,24 @@ def test_trajectory_gradient_matches_oracle_on_replica():
     assert eF < 1e-4 and eu < 1e-4
 
 
-def test_checkpoint_interval_does_not_change_gradient():
-    """Checkpoint intervals and nested recomputation (max_states < K) give bitwise-equal gradients."""
+@pytest.mark.parametrize("storage", ["f32", "bf16_sr"])
+def test_checkpoint_interval_does_not_change_gradient(storage):
+    """Checkpoint intervals and nested recomputation (max_states < K) give bitwise-equal gradients.
+    With stochastic rounding (BF16-SR) this also checks that every recomputed segment takes the step
+    counters of the forward pass, so it reproduces the forward states bit for bit."""
     w = W.ADJOINT_DUCT_128
     p = oracle_params(w, nx=24, ny=12, nz=10)
     g = np.random.Generator(np.random.PCG64(42))
     force = torch.tensor(1e-5 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda()
     target = torch.tensor(1e-3 * g.standard_normal((3, *p.shape))).cuda()
     u0 = torch.zeros((3, *p.shape), dtype=DT, device="cuda")
-    lat = gpu_lattice(p)
+    lat = gpu_lattice(p, storage=storage)
     grads = []
     for every, cap in ((1, 128), (7, 128), (40, 128), (40, 3), (25, 4)):
         Fc = force.clone().requires_grad_(True)
+        P.lbm_set_step_counter(lat.h, 1000)
         u = ADJ.simulate(lat, u0, Fc, 40, every, max_states=cap)
+        assert lat.h.step_counter == 1040                  # the backward leaves the counter where the forward did
         (0.5 * ((u.to(DT) - target) ** 2).sum()).backward()
         grads.append(Fc.grad.clone())
     for gr in grads[1:]:

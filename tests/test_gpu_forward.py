@@ -142,7 +142,7 @@ def test_taylor_green_fp32_within_1e5(taylor_green_oracle):
     assert abs(m.sums[0].item() - sums_o[0].item()) / sums_o[0].item() < 1e-10
 
 
-@pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 3e-2)])
+@pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 3e-2), ("bf16_sr", 3e-2)])
 def test_taylor_green_reduced_storage_error(taylor_green_oracle, storage, bound):
     """16-bit deviation storage: error against the FP64 oracle is stated, with a loose bound."""
     rho_o, u_o, sums_o = taylor_green_oracle

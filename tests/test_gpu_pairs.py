@@ -52,6 +52,7 @@ CASES = [
     ("raw_off_f16", (70, 8, 6), 1.0, 0.5, "off", "raw", 1.0, "f16", True),
     ("odd_words_f16", (130, 5, 4), 0.75, 1.0, "local", "central", 1.0, "f16", False),
     ("two_wide_bf16", (2, 7, 5), 1.0, 0.5, "local", "raw", 1.0, "bf16", True),
+    ("stochastic_bf16sr", (300, 6, 5), 1.0, 0.5, "local", "central", 1.0, "bf16_sr", True),
 ]
 
 
@@ -96,6 +97,7 @@ AA_CASES = [
     ("aa_ragged_local_f16", (300, 6, 5), 1.0, 0.5, "local", "central", 1.0, "f16", True),
     ("aa_raw_lowmach_bf16", (70, 8, 6), 0.5, 0.25, "lowmach", "raw", 1.0, "bf16", False),
     ("aa_two_wide_f16", (2, 5, 4), 1.0, 0.5, "off", "central", 1.0, "f16", True),
+    ("aa_stochastic_bf16sr", (70, 8, 6), 0.5, 0.25, "local", "central", 1.0, "bf16_sr", False),
 ]
 
 
