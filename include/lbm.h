@@ -26,10 +26,14 @@
  *   arrays are [27][n_nodes] (double unless stated), f_alpha(x, t) after
  *   streaming, i.e. the state from which eq. 12 reads rho and u.
  * - A "state" is opaque device memory of lbm_state_bytes() bytes holding one
- *   time level in the library's own layout: per direction an array of
- *   lbm_state_stride() elements (float, or 16-bit for the reduced-storage
- *   modes) holding scaled deviations from the rest equilibrium w_alpha rho0,
- *   placed so that the next step can gather them (pull scheme).
+ *   time level in the library's own layout: 27 * lbm_state_stride() elements
+ *   (float, or 16-bit for the reduced-storage modes) holding deviations from
+ *   the rest equilibrium w_alpha rho0 (scaled for F16), placed so that the next
+ *   step can gather them (pull scheme).  The layout is blocked: every x-row is
+ *   padded to a multiple of 128 nodes and cut into blocks of 128 nodes, and a
+ *   block holds the 27 directions of its nodes as 27 runs of 128 elements;
+ *   lbm_state_stride() is the padded node count.  Callers only allocate it and
+ *   pass it between calls; lbm_import/lbm_export convert natural populations.
  * - Memory: the caller allocates every device buffer (PyTorch in the Python
  *   binding); the library never allocates or frees device memory.  The only
  *   host allocation is the handle.  All pointers to device memory must be
@@ -104,9 +108,9 @@ enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
  *     Between calls the state holds the post-stream populations in natural
  *     order (slot (a, x) = f_a(x, t)), so every step call must advance an even
  *     number of steps.  Forward steps only: lbm_step, lbm_step_forcing (not
- *     the full corrections, not the adjoint).  It addresses through 32-bit
- *     offsets, so lbm_create returns LBM_EINVAL for 2^30 nodes or more, and
- *     with walls for a whole state of 4 GiB or more. */
+ *     the full corrections, not the adjoint).  With walls it addresses the
+ *     state through 32-bit offsets, so lbm_create returns LBM_EINVAL for a
+ *     walled AA state of 4 GiB or more. */
 enum lbm_layout { LBM_LAYOUT_AB = 0, LBM_LAYOUT_AA = 1 };
 
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
@@ -162,8 +166,9 @@ int lbm_relaxation_rates(double nu, double xi, double cs2, double* omega_nu, dou
 int lbm_create(const lbm_params* p, lbm_handle** out);
 void lbm_destroy(lbm_handle* h);
 
-/* Bytes of one state (27 * stride * element size) and the per-direction
- * stride in elements (>= n_nodes, padded). */
+/* Bytes of one state (27 * stride * element size) and the slots per direction
+ * (the node count with every x-row padded to a multiple of 128 nodes); an
+ * adjoint array (below) has 27 * stride floats. */
 size_t lbm_state_bytes(const lbm_handle* h);
 int64_t lbm_state_stride(const lbm_handle* h);
 int64_t lbm_num_nodes(const lbm_handle* h);
@@ -288,13 +293,14 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  * The step maps a state h(t) to h(t+1) = C(S(h(t)); F): S streams (a
  * permutation of the population slots), C collides every node.  The adjoint
  * step is lambda(t) = [dh(t+1)/dh(t)]^T lambda(t+1), with lambda(t) indexed
- * like the state's slots (float[27][stride], not scaled) and taken with
+ * like the state's slots (float[27 * stride] in the state's layout, not
+ * scaled) and taken with
  * respect to the real-valued populations (the rounding of 16-bit storage is
  * not differentiated).
  *
  *   state_t:    the state h(t) before the step (read)
- *   adj_in:     lambda(t+1), device float[27][stride] (read)
- *   adj_out:    lambda(t),   device float[27][stride] (written; != adj_in)
+ *   adj_in:     lambda(t+1), device float[27 * stride] (read)
+ *   adj_out:    lambda(t),   device float[27 * stride] (written; != adj_in)
  *   force:      as in lbm_step
  *   grad_force: device float[3][n_nodes] or NULL: += (dh(t+1)/dF)^T lambda(t+1)
  *               for a per-node force field
@@ -310,7 +316,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
 /* lambda(T) from cotangents of the observables of a state (the transpose of
  * lbm_moments' rho/u map):
  *   g_rho: device float[n_nodes] or NULL;  g_u: device float[3][n_nodes] or NULL
- *   adj:   device float[27][stride], written (overwritten, not accumulated)
+ *   adj:   device float[27 * stride], written (overwritten, not accumulated)
  *   grad_force: device float[3][n_nodes] or NULL, += d(u)/dF^T g_u (the F/2 of eq. 12). */
 int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force,
                         const float* g_rho, const float* g_u, float* adj,
@@ -318,7 +324,7 @@ int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force,
 
 /* Cotangents of the initial fields from lambda(0) (transpose of lbm_init's
  * f_eq(rho, u) map at the given rho, u):
- *   adj:   device float[27][stride] (read)
+ *   adj:   device float[27 * stride] (read)
  *   rho, u: as in lbm_init (NULL = rho0 / zero)
  *   g_rho: device double[n_nodes] or NULL, written
  *   g_u:   device double[3][n_nodes] or NULL, written */

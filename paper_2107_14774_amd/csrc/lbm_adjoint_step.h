@@ -23,6 +23,9 @@
 #ifndef LBM_ADJ_WAVES_16
 #define LBM_ADJ_WAVES_16 3
 #endif
+#ifndef LBM_ADJ_WAVES_32
+#define LBM_ADJ_WAVES_32 1
+#endif
 
 namespace clbm {
 
@@ -308,7 +311,7 @@ __device__ __forceinline__ void load_own(const GroupBases<const float>& b, uint3
 // WALLS: 0 periodic (row addresses, any size), 1 walls with 32-bit offsets
 // across the whole state and adjoint (both below 4 GiB), 2 general (64-bit slots).
 template <int ST, int CORR, int WALLS, bool RAW, bool HI>
-__global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k_step_adjoint(
+__global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ_WAVES_16)) void k_step_adjoint(
     const typename Store<ST>::T* __restrict__ state, const float* __restrict__ lin, float* __restrict__ lout,
     const float* __restrict__ force, float* __restrict__ grad_force, double* __restrict__ grad_uniform, Consts k,
     uint32_t bpr) {
@@ -343,7 +346,9 @@ __global__ __launch_bounds__(256, (ST == 0 || HI) ? 1 : LBM_ADJ_WAVES_16) void k
     if constexpr (WALLS == 2) {
       scatter_all<true>(lout, make_coord(x, y, z, k), k, mu);
     } else if constexpr (WALLS == 1) {
-      scatter_walls32(lout, u, w, mu);
+      // offsets computed anew from fresh copies of the x offsets: reusing the gather's 27
+      // offsets would keep them live through the whole transposed collision (185 VGPRs)
+      scatter_walls32(lout, store_upstream(u), w, mu);
     } else {
       scatter_periodic(pull_groups(lout, u), u, mu);
     }
