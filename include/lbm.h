@@ -201,6 +201,15 @@ int lbm_init(lbm_handle* h, void* state, const double* rho, const double* u,
 int lbm_import(lbm_handle* h, void* state, const double* f, void* hip_stream);
 int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream);
 
+/* Natural populations of `count` listed nodes (a sampled lbm_export, for
+ * states too large to export whole):
+ *   nodes: device int64[count], node indices n = (z ny + y) nx + x; an index
+ *          outside [0, n_nodes) yields NaN in all 27 of its values
+ *   f:     device double[27][count], f[alpha][i] = f_alpha at nodes[i]
+ * count = 0 does nothing; LBM_EINVAL for count < 0 or a NULL pointer. */
+int lbm_export_nodes(lbm_handle* h, const void* state, const int64_t* nodes, int64_t count, double* f,
+                     void* hip_stream);
+
 /* Advance nsteps >= 0 collide-and-stream steps (Sec. 3.2).  The current state
  * is in state_a on entry; state_b is scratch of the same size (must differ
  * from state_a).  On return the current state is in state_a when nsteps is

@@ -57,6 +57,7 @@ _SIGNATURES = {
     "lbm_init": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "lbm_import": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbm_export": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbm_export_nodes": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P]),
     "lbm_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "lbm_density": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbm_set_force": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),

@@ -261,6 +261,18 @@ int lbm_export(lbm_handle* h, const void* state, double* f, void* hip_stream) {
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_export");
 }
 
+int lbm_export_nodes(lbm_handle* h, const void* state, const int64_t* nodes, int64_t count, double* f,
+                     void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_export_nodes");
+  if (count < 0) return fail(LBM_EINVAL, "lbm_export_nodes: count < 0");
+  if (count == 0) return LBM_OK;
+  CHECK_REQ(state, "lbm_export_nodes", "state");
+  CHECK_REQ(nodes, "lbm_export_nodes", "nodes");
+  CHECK_REQ(f, "lbm_export_nodes", "f");
+  hipError_t e = clbm::launch_export_nodes(*h, state, nodes, count, f, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_export_nodes");
+}
+
 // AA layout: one buffer, steps in pairs (local, shifted).
 static int step_aa(lbm_handle* h, const char* name, int32_t nsteps, void* state, void* state_b,
                    const float* force, const double* forces, hipStream_t st) {

@@ -82,12 +82,38 @@ __device__ __forceinline__ void export_load(const typename Store<ST>::T* __restr
   if constexpr (A + 1 < 27) export_load<ST, A + 1>(src, c, node, f, k, kd);
 }
 
+template <int ST, int A = 0>
+__device__ __forceinline__ void export_node(const typename Store<ST>::T* __restrict__ src, const NodeCoord& c,
+                                            const Consts& k, const ConstsD& kd, double (&f)[27]) {
+  f[A] = kd.w[A] * kd.rho0 + (double)Store<ST>::load(src + gather_slot<A>(c, k)) / (double)k.sigma[wclass(A)];
+  if constexpr (A + 1 < 27) export_node<ST, A + 1>(src, c, k, kd, f);
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_export(const typename Store<ST>::T* __restrict__ src,
                                                 double* __restrict__ f, Consts k, ConstsD kd) {
   for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
        node += (int64_t)gridDim.x * blockDim.x) {
     export_load<ST>(src, coord_of(node, k), node, f, k, kd);
+  }
+}
+
+// Natural populations of listed nodes (a sampled export): f[A][i] for node
+// nodes[i]; an index outside [0, n) gives NaN for all 27 values.
+template <int ST>
+__global__ __launch_bounds__(256) void k_export_nodes(const typename Store<ST>::T* __restrict__ src,
+                                                      const int64_t* __restrict__ nodes, int64_t count,
+                                                      double* __restrict__ f, Consts k, ConstsD kd) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = nodes[i];
+    if (node < 0 || node >= k.n) {
+      for (int a = 0; a < 27; ++a) f[a * count + i] = __builtin_nan("");
+      continue;
+    }
+    double tmp[27];
+    const NodeCoord c = coord_of(node, k);
+    export_node<ST>(src, c, k, kd, tmp);
+    for (int a = 0; a < 27; ++a) f[a * count + i] = tmp[a];
   }
 }
 
@@ -278,6 +304,24 @@ hipError_t launch_export(const lbm_handle& h, const void* src, double* f, hipStr
     case LBM_F32: hipLaunchKernelGGL(k_export<0>, g, 256, 0, st, (const float*)src, f, h.k, h.kd); break;
     case LBM_F16: hipLaunchKernelGGL(k_export<1>, g, 256, 0, st, (const Store<1>::T*)src, f, h.k, h.kd); break;
     default: hipLaunchKernelGGL(k_export<2>, g, 256, 0, st, (const Store<2>::T*)src, f, h.k, h.kd); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export_nodes(const lbm_handle& h, const void* src, const int64_t* nodes, int64_t count, double* f,
+                              hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int g = grid_for(count, 256, 65536);
+  switch (h.p.storage) {
+    case LBM_F32:
+      hipLaunchKernelGGL(k_export_nodes<0>, g, 256, 0, st, (const float*)src, nodes, count, f, h.k, h.kd);
+      break;
+    case LBM_F16:
+      hipLaunchKernelGGL(k_export_nodes<1>, g, 256, 0, st, (const Store<1>::T*)src, nodes, count, f, h.k, h.kd);
+      break;
+    default:
+      hipLaunchKernelGGL(k_export_nodes<2>, g, 256, 0, st, (const Store<2>::T*)src, nodes, count, f, h.k, h.kd);
+      break;
   }
   return hipGetLastError();
 }

@@ -71,6 +71,8 @@ hipError_t launch_init(const lbm_handle& h, void* dst, const double* rho, const 
                        const double* perturb, hipStream_t st);
 hipError_t launch_import(const lbm_handle& h, void* dst, const double* f, hipStream_t st);
 hipError_t launch_export(const lbm_handle& h, const void* src, double* f, hipStream_t st);
+hipError_t launch_export_nodes(const lbm_handle& h, const void* src, const int64_t* nodes, int64_t count, double* f,
+                              hipStream_t st);
 hipError_t launch_moments(const lbm_handle& h, const void* src, const float* force, float* rho,
                           float* u, double* sums, hipStream_t st);
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in,

@@ -134,6 +134,15 @@ def lbm_export(h, state, f, stream=None):
     _lib.check(_lib.load().lbm_export(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(f), _lib.stream_ptr(stream)))
 
 
+def lbm_export_nodes(h, state, nodes, f, stream=None):
+    """``nodes``: device int64 [count]; ``f``: device float64 [27, count]."""
+    count = nodes.numel()
+    _require(nodes, torch.int64, count, "nodes")
+    _require(f, _ABI_F64, 27 * count, "f")
+    _lib.check(_lib.load().lbm_export_nodes(h.raw, _lib.ptr(_state(h, state)), _lib.ptr(nodes), count, _lib.ptr(f),
+                                            _lib.stream_ptr(stream)))
+
+
 def _state_b(h, t):
     """state_b: a buffer, or None in the AA layout (one buffer updated in place)."""
     return None if t is None and h.params.layout == _lib.LAYOUT["aa"] else _state(h, t, "state_b")
