@@ -341,29 +341,32 @@ def cpu_baseline(w):
 # ---------------------------------------------------------------------- rocprofv3 summaries
 PROFILE_KERNELS = {
     "f32": "k_step<0, 2, 0, false, false>", "f16": "k_step_pair<1, 2, false, false>",
-    "bf16": "k_step_pair<2, 2, false, false>",
+    "bf16": "k_step_pair<2, 2, false, false>", "bf16_sr": "k_step_pair<3, 2, false, false>",
     "full_f32": "k_step<0, 3, 0, false, false>", "full_f16": "k_step<1, 3, 0, false, false>",
     "aa_f32 (local)": "k_step_aa<0, 2, false, false, false, false>", "aa_f32 (shifted)": "k_step_aa<0, 2, true, false, false, false>",
     "aa_f16 (local)": "k_step_aa_pair<1, 2, false, false, false>", "aa_f16 (shifted)": "k_step_aa_pair<1, 2, true, false, false>",
     "adjoint_f32": "k_step_adjoint<0, 2, 1, false, false>", "adjoint_f32_hbm": "k_step_adjoint<0, 2, 1, false, false>",
     "adjoint_f16": "k_step_adjoint<1, 2, 0, false, false>",
-    # the measured ceilings: streaming only (the FP32 step without its collision) and the plain copy
-    "stream_f32": "k_stream<0, 0>", "copy": "k_copy16",
+    # the measured ceilings: streaming only (the FP32 step and the FP16 pair step without their
+    # collisions) and the plain copy
+    "stream_f32": "k_stream<0, 0>", "stream_f16": "k_stream_pair<1>", "copy": "k_copy16",
 }
 PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),
-    "bf16": (512, 512, 256, "512x512x256"), "full_f32": (512, 512, 256, "512x512x256"),
+    "bf16": (512, 512, 256, "512x512x256"), "bf16_sr": (512, 512, 256, "512x512x256"),
+    "full_f32": (512, 512, 256, "512x512x256"),
     "full_f16": (512, 512, 256, "512x512x256"), "adjoint_f32": (128, 128, 64, "128x128x64 duct"),
     "aa_f32 (local)": (512, 512, 256, "512x512x256"), "aa_f32 (shifted)": (512, 512, 256, "512x512x256"),
     "aa_f16 (local)": (512, 512, 256, "512x512x256"), "aa_f16 (shifted)": (512, 512, 256, "512x512x256"),
     "adjoint_f16": (384, 384, 192, "384x384x192"), "adjoint_f32_hbm": (512, 512, 128, "512x512x128 duct"),
-    "stream_f32": (512, 512, 256, "512x512x256"), "copy": (512, 512, 256, "one FP32 state"),
+    "stream_f32": (512, 512, 256, "512x512x256"), "stream_f16": (512, 512, 256, "512x512x256"),
+    "copy": (512, 512, 256, "one FP32 state"),
 }
 COPY_BYTES = 27 * 512 * 512 * 256 * 4                 # bytes read (and written) by one lbm_copy of the bench
 # $OUT is any output directory (the three runs write their CSVs under it)
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_step -o step --output-format csv -- "
              "python3 bench.py --steps 30 --warmup 5 --no-cpu-baseline")
-PMC_CMD = ("timeout -s KILL 240 rocprofv3 --pmc {c} -d $OUT/pmc_{d} -o {d} --output-format csv -- "
+PMC_CMD = ("timeout -s KILL 600 rocprofv3 --pmc {c} -d $OUT/pmc_{d} -o {d} --output-format csv -- "
            "python3 bench.py --steps 4 --warmup 1 --no-cpu-baseline")
 SUMMARY_CMD = "python3 bench.py --summarize-rocprof $OUT"
 TRACE_SUMMARY = "profiles/k_step_and_adjoint_kernel_trace.txt"
@@ -397,12 +400,14 @@ def summarize_rocprof(out_dir):
         if v.startswith("aa_"):
             alg[v] = BYTES_PER_LUP[v.split()[0]]
     alg["stream_f32"] = BYTES_PER_LUP["f32"]
+    alg["stream_f16"] = BYTES_PER_LUP["f16"]
     alg["copy"] = 2 * COPY_BYTES // (512 * 512 * 256)   # per node of the state copied
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
              "# corrections), its adjoint (128x128x64 and 512x512x128 ducts with force field; 384x384x192,",
-             "# r=1/2, s=1/4, FP16), and the two measured ceilings: streaming only (k_stream, the FP32 step's",
-             "# gather and store without the collision) and the library copy (k_copy16, one FP32 state)",
+             "# r=1/2, s=1/4, FP16), and the measured ceilings: streaming only (k_stream and k_stream_pair, the",
+             "# FP32 and FP16 steps' gathers and stores without the collisions) and the library copy (k_copy16,",
+             "# one FP32 state)",
              "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):", "  " + TRACE_CMD,
              "  " + SUMMARY_CMD, "",
              f"{'kernel':38s} {'variant':16s} {'workload':16s} calls  avg_ms   min_ms   max_ms   "
@@ -529,6 +534,9 @@ def main():
     state_bytes = 27 * w.nx * w.ny * w.nz * 4          # one FP32 state (rows already whole blocks)
     copy_gbs = copy_bandwidth(state_bytes)
     pattern_gbs, pattern_ms = stream_bandwidth(w, max(20, args.steps // 4), args.warmup)
+    pattern16 = None
+    if any(v in ("f16", "bf16", "bf16_sr") for v in variants):   # the 16-bit steps' own pattern
+        pattern16 = stream_bandwidth(w, max(20, args.steps // 4), args.warmup, "f16")
     res = {}
     for v in variants:
         if v in BYTES_PER_LUP:
@@ -563,6 +571,9 @@ def main():
         variants_out[v] = {"mlups": round(rv["mlups"], 1), "ms_per_step": round(rv["wall_s"] / args.steps * 1e3, 4),
                            "hbm_gbs_algorithmic": round(ach, 1), "hbm_frac": round(ach / HBM_PEAK_GBS, 4),
                            "bytes_per_lup": BYTES_PER_LUP[v], "measured_bytes_per_launch": measured_traffic(v)}
+        if v in ("f16", "bf16", "bf16_sr") and pattern16:
+            variants_out[v]["pattern_ceiling_gbs"] = round(pattern16[0], 1)
+            variants_out[v]["frac_of_pattern"] = round(ach / pattern16[0], 4)
     variants_out.update(adj)
     if "f32" in res:
         for v in ("f16", "bf16", "bf16_sr", "full_f32", "full_f16", "full_f32_exact", "aa_f32", "aa_f16"):

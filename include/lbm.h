@@ -271,7 +271,8 @@ int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
  * collision left out, f_a(x, t+1) = f_a(x - ebar_a, t), or f_abar(x, t) where
  * x - ebar_a lies beyond a wall (the streaming bullet of Sec. 3.2 and the
  * bounce-back of Sec. 4 with stationary walls).  It moves the step's bytes in
- * the step's access pattern with the step's launch shape, so its throughput is
+ * the step's access pattern with the step's launch shape (two nodes per thread
+ * where the 16-bit step uses them), so its throughput is
  * the ceiling that pattern allows on the device: the reference the step's
  * memory throughput is reported against.  States behave as in lbm_step.
  * LBM_EINVAL for the AA layout, for moving walls, or state_a == state_b. */

@@ -455,6 +455,27 @@ __global__ __launch_bounds__(256) void k_stream(const typename Store<ST>::T* __r
   store_own<ST>(own_groups(dst, u), store_offset(u.xo[1]), df, k, node_sr_bits<ST>(node, k));
 }
 
+// Streaming only in the pair step's shape (16-bit periodic storage, even nx, two
+// nodes per thread): the pair gather and word stores without the collisions.
+template <int ST>
+__global__ __launch_bounds__(256) void k_stream_pair(const typename Store<ST>::T* __restrict__ src,
+                                                     typename Store<ST>::T* __restrict__ dst, Consts k, uint32_t bpr) {
+  static_assert(ST != 0, "two nodes per thread is the 16-bit path");
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const uint32_t tpr = (uint32_t)k.nx / 2;
+  const uint32_t t = bxi * blockDim.x + threadIdx.x;
+  if (t >= tpr) return;
+  const uint32_t tm = t == 0 ? tpr - 1 : t - 1, tp = t + 1 == tpr ? 0 : t + 1;
+  Upstream u;
+  upstream((int)(2 * t), y, z, k, u);
+  const PairWords p = pair_words(t, tm, tp);
+  uint32_t w[27];
+  gather_pair<ST>(pull_groups(src, u), p, w);
+  store_pair_own<ST>(own_groups(dst, u), store_offset(p.xw[1]), w);
+}
+
 // ------------------------------------------------------------------ launchers
 // Gather path: 0 periodic (row addresses, any size); 1 walls, 32-bit offsets
 // across the whole state (below 4 GiB); 2 general, 64-bit slots (walls above
@@ -554,6 +575,17 @@ static hipError_t launch_stream_t(const lbm_handle& h, const void* src, void* ds
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const T* s = (const T*)src;
   T* d = (T*)dst;
+  if constexpr (ST != 0) {  // the launch shape of the pair step
+    if (gather_kind(h) == 0 && h.pairs && h.p.nx % 2 == 0) {
+      constexpr int pblock = 128;
+      const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);
+      const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
+      if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_stream_pair<ST>), dim3((unsigned)pnb), dim3(pblock), (unsigned)h.pair_lds, st, s, d,
+                         h.k, pbpr);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid((unsigned)nb), blk(block);
   const unsigned lds = (unsigned)h.step_lds;
   switch (gather_kind(h)) {

@@ -27,6 +27,9 @@ CASES = [
     ("box_f16", (14, 10, 8), ("bounceback",) * 3, "f16"),
     ("periodic_bf16", (130, 5, 4), ("periodic",) * 3, "bf16"),
     ("duct_bf16_sr", (64, 8, 6), ("periodic", "bounceback", "bounceback"), "bf16_sr"),
+    # even nx, periodic, 16-bit: the two-nodes-per-thread shape of the step
+    ("periodic_f16_pairs", (258, 5, 3), ("periodic",) * 3, "f16"),
+    ("periodic_bf16_sr_pairs", (130, 4, 5), ("periodic",) * 3, "bf16_sr"),
 ]
 
 
