@@ -302,11 +302,14 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
 /* ---------------------------------------------------------------- adjoint
  * The step maps a state h(t) to h(t+1) = C(S(h(t)); F): S streams (a
  * permutation of the population slots), C collides every node.  The adjoint
- * step is lambda(t) = [dh(t+1)/dh(t)]^T lambda(t+1), with lambda(t) indexed
- * like the state's slots (float[27 * stride] in the state's layout, not
- * scaled) and taken with
- * respect to the real-valued populations (the rounding of 16-bit storage is
- * not differentiated).
+ * step is lambda(t) = [dh(t+1)/dh(t)]^T lambda(t+1), taken with respect to
+ * the real-valued populations (the rounding of 16-bit storage is not
+ * differentiated; values not scaled).  An adjoint array is float[27 * stride]
+ * in the state's blocked layout, in gathered-population order: the element
+ * of slot (a, x) holds the cotangent of the population that the next step
+ * gathers as f_a at node x, i.e. of the slot (a, x - ebar_a), or (opp(a), x)
+ * across a wall.  In this order the step stores its results at each node's
+ * own slots and reads lambda(t+1) in the shape of the forward gather.
  *
  *   state_t:    the state h(t) before the step (read)
  *   adj_in:     lambda(t+1), device float[27 * stride] (read)
@@ -341,9 +344,10 @@ int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force,
 int lbm_init_adjoint(lbm_handle* h, const float* adj, const double* rho,
                      const double* u, double* g_rho, double* g_u, void* hip_stream);
 
-/* Reorder a slot-indexed float array (an adjoint) into natural order and
- * back: natural[alpha][n] is the slot that the next step gathers as
- * f_alpha at node n.  natural is device double[27][n_nodes]. */
+/* Reorder an adjoint array into natural order and back: natural[alpha][n]
+ * is its element of slot (alpha, n), the cotangent of the population that
+ * the next step gathers as f_alpha at node n.  natural is device
+ * double[27][n_nodes]. */
 int lbm_adjoint_to_natural(lbm_handle* h, const float* slots, double* natural, void* hip_stream);
 int lbm_adjoint_from_natural(lbm_handle* h, const double* natural, float* slots, void* hip_stream);
 

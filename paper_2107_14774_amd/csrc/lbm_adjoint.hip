@@ -5,23 +5,26 @@
 
 namespace clbm {
 
+// The adjoint arrays are in gathered-population order (lbm_adjoint_step.h):
+// the element of slot (a, x) is the cotangent of what node x gathers as f_a.
+
 // Transpose of the moving-wall terms of the forward store, -rho d_A with rho
-// the sum of the node's gathered populations: every slot the node gathered
-// gains -sum_A lam_A d_A.  A separate pass after k_step_adjoint (it touches
-// only nodes on a moving face; each slot belongs to one node, so no races),
-// which keeps the main adjoint kernel's registers unchanged.
+// the sum of the node's gathered populations: the cotangent of every
+// population the node gathered gains -sum_A lam_A d_A.  A separate pass after
+// k_step_adjoint (it touches only nodes on a moving face and only their own
+// elements, so no races), which keeps the main adjoint kernel's registers
+// unchanged.
 template <int A = 0>
-__device__ __forceinline__ void add_to_gathered(float* __restrict__ dst, const NodeCoord& c, const Consts& k, float v) {
-  dst[gather_slot<A>(c, k)] += v;
-  if constexpr (A + 1 < 27) add_to_gathered<A + 1>(dst, c, k, v);
+__device__ __forceinline__ void add_to_own(float* __restrict__ dst, int x, int y, int z, const Consts& k, float v) {
+  dst[slot_of<A>(x, y, z, k)] += v;
+  if constexpr (A + 1 < 27) add_to_own<A + 1>(dst, x, y, z, k, v);
 }
 
-// The values of a slot-indexed float array at the node's own slots (a, x).
 template <int A = 0>
-__device__ __forceinline__ void own_slots(const float* __restrict__ src, int x, int y, int z, const Consts& k,
-                                          float (&v)[27]) {
-  v[A] = src[slot_of<A>(x, y, z, k)];
-  if constexpr (A + 1 < 27) own_slots<A + 1>(src, x, y, z, k, v);
+__device__ __forceinline__ void store_own_all(float* __restrict__ dst, int x, int y, int z, const Consts& k,
+                                              const float (&v)[27]) {
+  dst[slot_of<A>(x, y, z, k)] = v[A];
+  if constexpr (A + 1 < 27) store_own_all<A + 1>(dst, x, y, z, k, v);
 }
 
 __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __restrict__ adj_in, float* __restrict__ adj_out,
@@ -36,9 +39,9 @@ __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __rest
                            (k.bb_z && (((k.moving & 16) && z == 0) || ((k.moving & 32) && z == k.nz - 1)));
     if (!on_moving) continue;
     float lam[27];
-    own_slots(adj_in, x, y, z, k, lam);
+    load_next_all(adj_in, make_coord(x, y, z, k), k, lam);   // lambda(t+1) of the node's own slots
     const float c = moving_wall_vjp(x, y, z, k, lam);
-    add_to_gathered(adj_out, make_coord(x, y, z, k), k, -c);
+    add_to_own(adj_out, x, y, z, k, -c);
   }
 }
 
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(256) void k_moments_adjoint(const typename Store<ST
       if (kEz[a] != 0) v += kEz[a] * bj[2];
       mu[a] = v;
     }
-    scatter_all<true>(adj, c, k, mu);
+    store_own_all(adj, c.x, c.y, c.z, k, mu);
     if (grad_force != nullptr) {
       grad_force[node] += 0.5f * gx * irho;
       grad_force[k.n + node] += 0.5f * gy * irho;
@@ -90,10 +93,10 @@ __global__ __launch_bounds__(256) void k_moments_adjoint(const typename Store<ST
 
 // ------------------------------------------------------------------ init adjoint (FP64)
 template <int A = 0>
-__device__ __forceinline__ void gather_adj(const float* __restrict__ adj, const NodeCoord& c, const Consts& k,
-                                           double (&l)[27]) {
-  l[A] = (double)adj[gather_slot<A>(c, k)];
-  if constexpr (A + 1 < 27) gather_adj<A + 1>(adj, c, k, l);
+__device__ __forceinline__ void own_adj(const float* __restrict__ adj, const NodeCoord& c, const Consts& k,
+                                        double (&l)[27]) {
+  l[A] = (double)adj[slot_of<A>(c.x, c.y, c.z, k)];
+  if constexpr (A + 1 < 27) own_adj<A + 1>(adj, c, k, l);
 }
 
 __global__ __launch_bounds__(256) void k_init_adjoint(const float* __restrict__ adj, const double* __restrict__ rho,
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(256) void k_init_adjoint(const float* __restrict__ 
     const int64_t t = node / k.nx;
     const NodeCoord c = make_coord(x, (int)(t % k.ny), (int)(t / k.ny), k);
     double l[27];
-    gather_adj(adj, c, k, l);
+    own_adj(adj, c, k, l);
     const double rn = rho ? rho[node] : kd.rho0;
     const double uu[3] = {u ? u[node] : 0.0, u ? u[k.n + node] : 0.0, u ? u[2 * k.n + node] : 0.0};
     double E[3][3], A1[3][3];
@@ -150,14 +153,14 @@ __global__ __launch_bounds__(256) void k_init_adjoint(const float* __restrict__ 
 template <int A = 0>
 __device__ __forceinline__ void slots_to_nat(const float* __restrict__ s, const NodeCoord& c, int64_t node,
                                              double* __restrict__ nat, const Consts& k) {
-  nat[A * k.n + node] = (double)s[gather_slot<A>(c, k)];
+  nat[A * k.n + node] = (double)s[slot_of<A>(c.x, c.y, c.z, k)];
   if constexpr (A + 1 < 27) slots_to_nat<A + 1>(s, c, node, nat, k);
 }
 
 template <int A = 0>
 __device__ __forceinline__ void nat_to_slots(const double* __restrict__ nat, const NodeCoord& c, int64_t node,
                                              float* __restrict__ s, const Consts& k) {
-  s[gather_slot<A>(c, k)] = (float)nat[A * k.n + node];
+  s[slot_of<A>(c.x, c.y, c.z, k)] = (float)nat[A * k.n + node];
   if constexpr (A + 1 < 27) nat_to_slots<A + 1>(nat, c, node, s, k);
 }
 

@@ -5,10 +5,11 @@
 // The step maps the state h(t) to h(t+1) = C(S(h(t)); F) where S is the
 // streaming permutation of slots and C the per-node collision.  The adjoint
 // step gathers the node's populations from h(t) (as the forward did),
-// recomputes the collision, applies the transpose of its Jacobian to the
-// node's lambda(t+1) (read from the slots the forward wrote, coalesced) and
-// scatters the result to the slots it gathered from: S is a permutation, so
-// every slot of lambda(t) is written exactly once and no atomics are needed.
+// recomputes the collision and applies the transpose of its Jacobian to the
+// cotangents of the node's outputs, lambda(t+1); the result belongs to the
+// slots the node gathered from.  S is a permutation, so with the adjoint
+// arrays in gathered-population order (below) every element of lambda(t) is
+// written exactly once, at the node's own slots, and no atomics are needed.
 // The transpose is derived by hand from the factorised collision of
 // lbm_device.h; along each axis the vectors satisfy dE/du = dD/du = dA0/du =
 // A1 and dA1/du = 2 A2, which keeps the velocity derivatives short.
@@ -267,45 +268,51 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
 }
 
 // ------------------------------------------------------------------ adjoint step
-template <bool WX, int A = 0>
-__device__ __forceinline__ void scatter_all(float* __restrict__ dst, const NodeCoord& c, const Consts& k,
-                                            const float (&mu)[27]) {
-  dst[gather_slot<A, WX>(c, k)] = mu[A];
-  if constexpr (A + 1 < 27) scatter_all<WX, A + 1>(dst, c, k, mu);
-}
-
+// The adjoint arrays are in gathered-population order: the element of slot
+// (a, x) holds the cotangent of the value that node x gathers as f_a (the slot
+// the forward read it from).  The node's collision-input cotangents mu are then
+// stored at its own slots (aligned, as the forward stores), and the cotangents
+// of its collision outputs, lambda(t+1) at its own slots (b, x), are read from
+// the slots that gather them next: (b, x + ebar_b), or (opp(b), x) where that
+// neighbour lies beyond a wall.  That read has the forward gather's shape
+// (x-shifted loads are free there), where storing mu at the gather sources
+// would need x-shifted stores (measured 12% slower on the FP16 adjoint).
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-template <int A = 0>
-__device__ __forceinline__ void scatter_walls32(float* __restrict__ base, const Upstream& u, const WallFlags& w,
-                                                const float (&mu)[27]) {
-  const uint32_t idx = wall_slot32<A>(u, w);
-  if constexpr (kEx[A] == 0) st_off_nt(base, idx, mu[A]);
-  else st_off(base, idx, mu[A]);
-  if constexpr (A + 1 < 27) scatter_walls32<A + 1>(base, u, w, mu);
+// lambda(t+1) of the node's own slots, periodic: direction A's group base in
+// aa_odd_groups points at the row x + ebar_opp(A) lies in, at the chunk of opp(A).
+template <int I = 0>
+__device__ __forceinline__ void load_next_periodic(const GroupBases<const float>& b, const Upstream& u,
+                                                   float (&lam)[27]) {
+  constexpr int A = issue_dir(I);
+  lam[opposite_of(A)] = ld_pop<kEx[A] == 0>(b.g[group_of(A)] + (1 - kEx[A]) * kB, u.xo[kEx[A] + 1]);
+  if constexpr (I + 1 < 27) load_next_periodic<I + 1>(b, u, lam);
 }
 
-template <int I = 0>
-__device__ __forceinline__ void scatter_periodic(const GroupBases<float>& b, const Upstream& u,
-                                                 const float (&mu)[27]) {
-  // the x-shifted scatter writes partial lines that L2 merges with the neighbours' (plain
-  // stores); the directions with ebar_x = 0 write whole lines (non-temporal stores)
-  constexpr int A = issue_dir(I);
-  if constexpr (kEx[A] == 0) st_off_nt(chunk_ptr<A>(b), u.xo[1], mu[A]);
-  else st_off(chunk_ptr<A>(b), u.xo[kEx[A] + 1], mu[A]);
-  if constexpr (I + 1 < 27) scatter_periodic<I + 1>(b, u, mu);
+template <int B = 0>
+__device__ __forceinline__ void load_next_walls32(const float* __restrict__ base, const Upstream& u,
+                                                  const WallFlags& w, float (&lam)[27]) {
+  lam[B] = ld_pop<kEx[B] == 0>(base, downstream_slot32<B>(u, w));
+  if constexpr (B + 1 < 27) load_next_walls32<B + 1>(base, u, w, lam);
 }
 
-// lambda(t+1) at the node's own slots only: non-temporal loads (FP32 duct adjoint +15%).
+template <int B = 0>
+__device__ __forceinline__ void load_next_all(const float* __restrict__ base, const NodeCoord& c, const Consts& k,
+                                              float (&lam)[27]) {
+  lam[B] = base[downstream_slot<B>(c, k)];
+  if constexpr (B + 1 < 27) load_next_all<B + 1>(base, c, k, lam);
+}
+
+// mu at the node's own slots: whole aligned lines, non-temporal stores.
 template <int I = 0>
-__device__ __forceinline__ void load_own(const GroupBases<const float>& b, uint32_t xo, float (&lam)[27]) {
+__device__ __forceinline__ void store_own_adj(const GroupBases<float>& d, uint32_t so, const float (&mu)[27]) {
   constexpr int A = issue_dir(I);
-  lam[A] = ld_off_nt(chunk_ptr<A>(b), xo);
-  if constexpr (I + 1 < 27) load_own<I + 1>(b, xo, lam);
+  st_off_nt(chunk_ptr<A>(d), so, mu[A]);
+  if constexpr (I + 1 < 27) store_own_adj<I + 1>(d, so, mu);
 }
 
 // WALLS: 0 periodic (row addresses, any size), 1 walls with 32-bit offsets
@@ -333,7 +340,13 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
     } else {
       gather_periodic<ST>(pull_groups(state, u), u, k, df);
     }
-    load_own(own_groups(lin, u), u.xo[1], lam);
+    if constexpr (WALLS == 2) {
+      load_next_all(lin, make_coord(x, y, z, k), k, lam);
+    } else if constexpr (WALLS == 1) {
+      load_next_walls32(lin, u, w, lam);
+    } else {
+      load_next_periodic(aa_odd_groups(lin, u), u, lam);
+    }
     const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
     float fx = k.fx, fy = k.fy, fz = k.fz;
     if (force != nullptr) {
@@ -343,15 +356,7 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
       fz = ld_off(f + 2 * k.n, (uint32_t)x);
     }
     collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
-    if constexpr (WALLS == 2) {
-      scatter_all<true>(lout, make_coord(x, y, z, k), k, mu);
-    } else if constexpr (WALLS == 1) {
-      // offsets computed anew from fresh copies of the x offsets: reusing the gather's 27
-      // offsets would keep them live through the whole transposed collision (185 VGPRs)
-      scatter_walls32(lout, store_upstream(u), w, mu);
-    } else {
-      scatter_periodic(pull_groups(lout, u), u, mu);
-    }
+    store_own_adj(own_groups(lout, u), store_offset(u.xo[1]), mu);
     if (grad_force != nullptr) {
       float* g = grad_force + nrow;
       g[x] += gfx;

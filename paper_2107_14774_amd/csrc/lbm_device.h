@@ -285,6 +285,24 @@ __device__ __forceinline__ int64_t gather_slot(const NodeCoord& c, const Consts&
   return wall ? slot_of<opp>(c.x, c.y, c.z, k) : slot_of<A>(xs, ys, zs, k);
 }
 
+// Slot that the next step gathers the node's own slot (B, x) from: (B, x + ebar_B), or,
+// where x + ebar_B lies beyond a wall, the node's own (opp(B), x) (bounce-back).  In the
+// adjoint arrays (gathered-population order) it holds the cotangent of (B, x).  64-bit
+// element index; not for the AA layout.
+template <int B, bool WX = true>
+__device__ __forceinline__ int64_t downstream_slot(const NodeCoord& c, const Consts& k) {
+  constexpr int ex = kEx[B], ey = kEy[B], ez = kEz[B];
+  constexpr int opp = opposite_of(B);
+  const int xs = ex == 0 ? c.x : (ex > 0 ? c.xp : c.xm);
+  const int ys = ey == 0 ? c.y : (ey > 0 ? c.yp : c.ym);
+  const int zs = ez == 0 ? c.z : (ez > 0 ? c.zp : c.zm);
+  bool wall = false;
+  if (WX && ex != 0) wall |= k.bb_x && (ex > 0 ? c.x == k.nx - 1 : c.x == 0);
+  if (ey != 0) wall |= k.bb_y && (ey > 0 ? c.y == k.ny - 1 : c.y == 0);
+  if (ez != 0) wall |= k.bb_z && (ez > 0 ? c.z == k.nz - 1 : c.z == 0);
+  return wall ? slot_of<opp>(c.x, c.y, c.z, k) : slot_of<B>(xs, ys, zs, k);
+}
+
 template <int A, int ST, bool WX = true>
 __device__ __forceinline__ float gather_dev(const typename Store<ST>::T* __restrict__ src,
                                             const NodeCoord& c, const Consts& k) {
@@ -1031,6 +1049,14 @@ __device__ __forceinline__ uint32_t upstream_slot32(const Upstream& u) {
 template <int A>
 __device__ __forceinline__ uint32_t wall_slot32(const Upstream& u, const WallFlags& w) {
   return pulls_through_wall<A>(w) ? own_slot32<opposite_of(A)>(u) : upstream_slot32<A, A>(u);
+}
+
+// 32-bit form of downstream_slot: (B, x + ebar_B), or the own (opp(B), x) where
+// x + ebar_B lies beyond a wall (exactly where opp(B) pulls through one).
+template <int B>
+__device__ __forceinline__ uint32_t downstream_slot32(const Upstream& u, const WallFlags& w) {
+  constexpr int O = opposite_of(B);
+  return pulls_through_wall<O>(w) ? own_slot32<O>(u) : upstream_slot32<O, B>(u);
 }
 
 // NT: 0 plain loads; 1 non-temporal loads; 2 non-temporal loads for the
