@@ -1,6 +1,6 @@
 // Adjoint entry points: the reverse step (kernels in lbm_adjoint_step.h, one
 // translation unit per storage type), the moving-wall terms, and the adjoint
-// ends (observables, initialisation, slot order).
+// ends (observables, initialisation, natural order).
 #include "lbm_adjoint_step.h"
 
 namespace clbm {

@@ -9,7 +9,8 @@ handle with state allocation for convenience.
 Tensor conventions (see include/lbm.h): fields are [3, nz, ny, nx] / [nz, ny,
 nx] (SoA, x fastest), natural populations [27, nz, ny, nx] float64, states
 are opaque uint8 tensors of ``lbm_state_bytes`` bytes, adjoints float32
-[27 * stride] in the state's slot order.
+[27 * stride] in the state's blocked layout, in gathered-population order
+(the element of slot (a, x) is the cotangent of what node x gathers as f_a).
 """
 
 from dataclasses import dataclass
