@@ -364,7 +364,9 @@ __device__ __forceinline__ void gather_aa_pair(const GroupBases<typename Store<S
   if constexpr (I + 1 < 27) gather_aa_pair<ST, ODD, I + 1>(b, p, w);
 }
 
-template <int ST, bool ODD, int I = 0>
+// WS (odd steps, every wave within one row: nx a multiple of 128): the x-shifted
+// outputs as whole 32-bit words assembled across lanes instead of 2-byte stores.
+template <int ST, bool ODD, bool WS, int I = 0>
 __device__ __forceinline__ void store_aa_pair(const GroupBases<typename Store<ST>::T>& b, const PairWords& p,
                                               const uint32_t (&o)[27]) {
   constexpr int A = issue_dir(I);
@@ -379,7 +381,25 @@ __device__ __forceinline__ void store_aa_pair(const GroupBases<typename Store<ST
     } else {
       global_t<unsigned short>* base = reinterpret_cast<global_t<unsigned short>*>(row);
       const uint32_t lo = o[A] & 0xffffu, hi = o[A] >> 16;
-      if constexpr (ex > 0) {                                    // nodes 2t + 1, 2t + 2
+      if constexpr (WS) {
+        // Whole words: the half that completes this lane's word comes from the
+        // neighbouring lane (a wavefront shift); the two halves without a partner in
+        // the wave (lane 0's and lane 63's) are 2-byte stores of one instruction.
+        const uint32_t lane = threadIdx.x & 63u;
+        if constexpr (ex > 0) {  // word t = (node 2t: hi of lane - 1, node 2t + 1: lo of this lane)
+          const uint32_t prev = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, 0x138, 0xf, 0xf, false);
+          if (lane != 0) st_off(words(row), p.xw[1], prev | (lo << 16));
+          if (lane == 0 || lane == 63)
+            st_off<unsigned short>(base, lane == 0 ? 2 * p.xw[1] + 1 : 2 * p.xw[0],
+                                   (unsigned short)(lane == 0 ? lo : hi));
+        } else {                 // word t = (node 2t: hi of this lane, node 2t + 1: lo of lane + 1)
+          const uint32_t next = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, 0x130, 0xf, 0xf, false);
+          if (lane != 63) st_off(words(row), p.xw[1], hi | (next << 16));
+          if (lane == 0 || lane == 63)
+            st_off<unsigned short>(base, lane == 63 ? 2 * p.xw[1] : 2 * p.xw[2] + 1,
+                                   (unsigned short)(lane == 63 ? hi : lo));
+        }
+      } else if constexpr (ex > 0) {                              // nodes 2t + 1, 2t + 2
         st_off<unsigned short>(base, 2 * p.xw[1] + 1, (unsigned short)lo);
         st_off<unsigned short>(base, 2 * p.xw[0], (unsigned short)hi);
       } else {                                                   // nodes 2t - 1, 2t
@@ -388,10 +408,10 @@ __device__ __forceinline__ void store_aa_pair(const GroupBases<typename Store<ST
       }
     }
   }
-  if constexpr (I + 1 < 27) store_aa_pair<ST, ODD, I + 1>(b, p, o);
+  if constexpr (I + 1 < 27) store_aa_pair<ST, ODD, WS, I + 1>(b, p, o);
 }
 
-template <int ST, int CORR, bool ODD, bool RAW, bool HI>
+template <int ST, int CORR, bool ODD, bool RAW, bool HI, bool WS>
 __global__ __launch_bounds__(256) void k_step_aa_pair(typename Store<ST>::T* __restrict__ state,
                                                       const float* __restrict__ force, Consts k, uint32_t bpr) {
   static_assert(ST != 0, "two nodes per thread is the 16-bit path");
@@ -413,7 +433,7 @@ __global__ __launch_bounds__(256) void k_step_aa_pair(typename Store<ST>::T* __r
   PairWords ps;
 #pragma unroll
   for (int i = 0; i < 3; ++i) ps.xw[i] = store_offset(p.xw[i]);
-  store_aa_pair<ST, ODD>(b, ps, o);
+  store_aa_pair<ST, ODD, WS>(b, ps, o);
 }
 
 // Density deviation of every node of a state: the same gather and the same
@@ -612,9 +632,17 @@ static hipError_t launch_step_aa_t(const lbm_handle& h, void* state, int odd, co
       const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
       if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
       const dim3 pgrid((unsigned)pnb), pblk(pblock);
-#define CLBM_AAP(C, O, R) \
-  hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI>), pgrid, pblk, (unsigned)h.pair_lds, st, s, force, h.k, pbpr)
-#define CLBM_AAP_R(C, O) if (h.p.moments == LBM_RAW) CLBM_AAP(C, O, true); else CLBM_AAP(C, O, false)
+      // whole-word stores of the odd step need every wave inside one row (lane 0 starts a
+      // 64-pair segment): nx a multiple of 128
+      const bool ws = h.p.nx % 128 == 0;
+#define CLBM_AAP(C, O, R)                                                                                     \
+  if (O && ws)                                                                                                \
+    hipLaunchKernelGGL((k_step_aa_pair<ST, C, true, R, HI, true>), pgrid, pblk, (unsigned)h.pair_lds, st, s,   \
+                       force, h.k, pbpr);                                                                     \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_step_aa_pair<ST, C, O, R, HI, false>), pgrid, pblk, (unsigned)h.pair_lds, st, s,     \
+                       force, h.k, pbpr)
+#define CLBM_AAP_R(C, O) if (h.p.moments == LBM_RAW) { CLBM_AAP(C, O, true); } else { CLBM_AAP(C, O, false); }
       switch (h.p.corr) {
         case 0: if (odd) { CLBM_AAP_R(0, true); } else { CLBM_AAP_R(0, false); } break;
         case 1: if (odd) { CLBM_AAP_R(1, true); } else { CLBM_AAP_R(1, false); } break;

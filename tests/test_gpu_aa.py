@@ -48,6 +48,10 @@ CASES = [
     ("periodic_bf16_sr_field", (70, 9, 6), 0.5, 0.25, ("periodic",) * 3, None, "local", "central", "bf16_sr", True),
     ("duct_bf16_sr", (37, 12, 10), 1.0, 0.25, ("periodic", "bounceback", "bounceback"), None, "local",
      "central", "bf16_sr", False),
+    # nx a multiple of 128: the odd step of two nodes per thread stores whole words across lanes
+    ("periodic_f16_words_field", (256, 5, 4), 1.0, 0.5, ("periodic",) * 3, None, "local", "central", "f16", True),
+    ("periodic_bf16_sr_words", (128, 6, 5), 0.5, 0.25, ("periodic",) * 3, None, "lowmach", "raw", "bf16_sr", False),
+    ("periodic_bf16_words", (384, 3, 4), 1.0, 0.5, ("periodic",) * 3, None, "local", "central", "bf16", True),
 ]
 
 
