@@ -17,7 +17,9 @@
 * 384x384x192 FP16 adjoint (r = 1/2, s = 1/4): gradient of the final-velocity
   loss with respect to the initial velocity after 1000 steps (checkpoint every
   100), FP16 storage against FP32 storage (stated error), and the FP16 path
-  against the FP64 oracle on a small replica (stated error).
+  against the FP64 oracle on a small replica (stated error); the same physics
+  on a 32x32x16 replica over the full 1000 steps against the FP64 oracle's
+  gradient stored in tests/golden, in every storage format.
 """
 
 import sys
@@ -249,6 +251,47 @@ def test_fp16_gradient_vs_oracle_replica():
          + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
     assert out["f32"] < 1e-4
     assert out["f16"] < 1e-3 and out["bf16"] < 1e-2
+
+
+def test_fp16_workload_gradient_1000_steps_against_oracle():
+    """The FP16 adjoint workload's physics on a 32x32x16 replica over its 1000 steps (checkpoint every
+    100): the loss and dL/du0 at 1024 seeded nodes against the FP64 oracle's run stored by
+    tests/golden/make_c5_gradient_fixture.py, in every storage format."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_gradient_replica_32x32x16.json")
+    with open(path) as fh:
+        ref = json.load(fh)
+    w = W.ADJOINT_F16_384
+    nx, ny, nz = ref["grid"]
+    p = oracle_params(w, nx=nx, ny=ny, nz=nz)
+    u0 = torch.from_numpy(W.random_modes(nx, ny, nz, p.r, p.s, ref["kmax"], ref["u0"]["rms"], ref["u0"]["seed"]))
+    target = torch.from_numpy(W.random_modes(nx, ny, nz, p.r, p.s, ref["kmax"], ref["target"]["rms"],
+                                             ref["target"]["seed"]))
+    nodes = torch.tensor(ref["sample_nodes"], dtype=torch.int64)
+    want = torch.tensor(ref["grad_u0_sample"], dtype=DT)                       # (samples, 3)
+    out = {}
+    for storage in ("f32", "f16", "bf16", "bf16_sr"):
+        lat = gpu_lattice(p, storage=storage)
+        uc = u0.cuda().requires_grad_(True)
+        u = ADJ.simulate(lat, uc, None, ref["steps"], 100)
+        loss = 0.5 * ((u.to(DT) - target.cuda()) ** 2).sum()
+        loss.backward()
+        got = uc.grad.reshape(3, -1)[:, nodes.cuda()].T.cpu().to(DT)
+        dg = float((got - want).norm() / want.norm())
+        dl = abs(float(loss.detach()) - ref["loss"]) / ref["loss"]
+        out[storage] = (dg, dl)
+        _say(f"replica 32x32x16 {storage}, {ref['steps']} steps: dL/du0 rel L2 vs FP64 oracle {dg:.3e}, "
+             f"loss {dl:.3e}")
+        del lat, uc, u
+        torch.cuda.empty_cache()
+    for storage, (bg, bl) in GRAD_BOUND.items():
+        assert out[storage][0] < bg and out[storage][1] < bl, (storage, out[storage])
+
+
+# (gradient, loss) bounds of the 1000-step replica gradient against the oracle, about twice the
+# measured errors (f32 3.4e-5 / 2.4e-10, f16 2.3e-4 / 1.7e-6, bf16 1.9e-2 / 1.4e-4, bf16_sr 1.2e-3 / 5.2e-5)
+GRAD_BOUND = {"f32": (7e-5, 1e-9), "f16": (5e-4, 4e-6), "bf16": (4e-2, 3e-4), "bf16_sr": (2.5e-3, 1.2e-4)}
 
 
 def _replica_fixture():
