@@ -342,7 +342,7 @@ def cpu_baseline(w):
 PROFILE_KERNELS = {
     "f32": "k_step<0, 2, 0, false, false>", "f16": "k_step_pair<1, 2, false, false>",
     "bf16": "k_step_pair<2, 2, false, false>", "bf16_sr": "k_step_pair<3, 2, false, false>",
-    "full_f32": "k_step<0, 3, 0, false, false>", "full_f16": "k_step<1, 3, 0, false, false>",
+    "full_f32": "k_step<0, 3, 0, false, false>", "full_f16": "k_step_full_pair<1, false>",
     "aa_f32 (local)": "k_step_aa<0, 2, false, false, false, false>", "aa_f32 (shifted)": "k_step_aa<0, 2, true, false, false, false>",
     "aa_f16 (local)": "k_step_aa_pair<1, 2, false, false, false, false>",
     "aa_f16 (shifted)": "k_step_aa_pair<1, 2, true, false, false, true>",

@@ -786,6 +786,42 @@ __device__ __forceinline__ void density_gradient_block(const float* __restrict__
   }
 }
 
+// The same gradient for two nodes per thread (nodes x0 = 2t and x0 + 1 of a row
+// segment of 2 blockDim.x nodes): each thread reduces its two columns, the first
+// and last thread the halo columns, and the neighbours come from LDS
+// (lds[c][2 blockDim.x + 2]).  The per-node arithmetic is that of
+// density_gradient_block.  Every thread of the block must call it.
+__device__ __forceinline__ void density_gradient_pair_block(const float* __restrict__ drho, int x0, int y, int z,
+                                                            bool active, const Consts& k, float (&lds)[3][258],
+                                                            float (&g)[2][3]) {
+  const int t = (int)threadIdx.x;
+  const TransverseRows rows = transverse_rows(drho, y, z, k);
+  if (active) {
+    const ColumnSums c0 = column_sums(rows, x0, k), c1 = column_sums(rows, x0 + 1, k);
+    lds[0][2 * t + 1] = c0.T; lds[1][2 * t + 1] = c0.U; lds[2][2 * t + 1] = c0.V;
+    lds[0][2 * t + 2] = c1.T; lds[1][2 * t + 2] = c1.U; lds[2][2 * t + 2] = c1.V;
+    if (t == 0) {
+      const ColumnSums h = column_sums(rows, x0 == 0 ? (k.bb_x ? 0 : k.nx - 1) : x0 - 1, k);
+      lds[0][0] = h.T; lds[1][0] = h.U; lds[2][0] = h.V;
+    }
+    if (t == (int)blockDim.x - 1 || x0 + 1 == k.nx - 1) {
+      const ColumnSums h = column_sums(rows, x0 + 1 == k.nx - 1 ? (k.bb_x ? x0 + 1 : 0) : x0 + 2, k);
+      lds[0][2 * t + 3] = h.T; lds[1][2 * t + 3] = h.U; lds[2][2 * t + 3] = h.V;
+    }
+  }
+  __syncthreads();
+  if (active) {
+    const float wc = k.w0c[0], ws = k.w0s[0];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * t + h;  // the node's left neighbour column in LDS
+      g[h][0] = 0.5f * (lds[0][i + 2] - lds[0][i]);
+      g[h][1] = 0.5f * k.ic[1] * (ws * lds[1][i] + wc * lds[1][i + 1] + ws * lds[1][i + 2]);
+      g[h][2] = 0.5f * k.ic[2] * (ws * lds[2][i] + wc * lds[2][i + 1] + ws * lds[2][i + 2]);
+    }
+  }
+}
+
 // Grid row (y, z) of row number `rowid`: y fastest, or in tiles of ty rows in y,
 // z-major inside a tile (the rows that read one upstream row then run close in time).
 __device__ __forceinline__ void tiled_row(uint32_t rowid, uint32_t ty, const Consts& k, int& y, int& z) {

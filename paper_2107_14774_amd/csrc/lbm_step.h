@@ -22,8 +22,8 @@ namespace clbm {
 // the source row plus a per-lane offset (any state size); with walls the slot
 // rule of gather_slot applies, as 32-bit offsets from the start of the state
 // below 4 GiB (wall_slot32) and as 64-bit slots above.  Periodic 16-bit grids
-// with even nx run k_step_pair below instead, unless they use the full
-// corrections.  With the full corrections (CORR 3) the density gradient comes
+// with even nx run k_step_pair (or, with the full corrections,
+// k_step_full_pair) below instead.  With the full corrections (CORR 3) the density gradient comes
 // from the density-deviation field grad_src, and drho_out (if not NULL)
 // receives the node's own density deviation.
 // HI: general rate of the moments of order >= 3 (k.omega_hi); false compiles
@@ -252,6 +252,60 @@ __global__ __launch_bounds__(256) void k_step_pair(const typename Store<ST>::T* 
   gather_pair<ST>(pull_groups(src, u), p, w);
   uint32_t o[27];
   collide_pair<ST, CORR, RAW, HI>(w, force, ((int64_t)z * k.ny + y) * k.nx, 2 * t, k, o);
+  store_pair_own<ST>(own_groups(dst, u), store_offset(p.xw[1]), o);
+}
+
+// Full corrections (CORR 3) with two nodes per thread: the pair gather and word
+// stores of k_step_pair, the density gradient of both nodes from the block's
+// column sums (density_gradient_pair_block), and, if drho_out is not NULL, both
+// nodes' density deviations.  Same values as k_step<ST, 3, 0> bit for bit.
+template <int ST, bool RAW>
+__global__ __launch_bounds__(256) void k_step_full_pair(const typename Store<ST>::T* __restrict__ src,
+                                                        typename Store<ST>::T* __restrict__ dst,
+                                                        const float* __restrict__ force,
+                                                        const float* __restrict__ grad_src,
+                                                        float* __restrict__ drho_out, Consts k, uint32_t bpr) {
+  static_assert(ST != 0, "two nodes per thread is the 16-bit path");
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  int y, z;
+  tiled_row(rowid, (uint32_t)k.ytile, k, y, z);
+  const uint32_t tpr = (uint32_t)k.nx / 2;
+  const uint32_t t = bxi * blockDim.x + threadIdx.x;
+  __shared__ float lds[3][258];
+  float g[2][3];
+  density_gradient_pair_block(grad_src, (int)(2 * t), y, z, t < tpr, k, lds, g);
+  if (t >= tpr) return;
+  const uint32_t tm = t == 0 ? tpr - 1 : t - 1, tp = t + 1 == tpr ? 0 : t + 1;
+  Upstream u;
+  upstream((int)(2 * t), y, z, k, u);
+  const PairWords p = pair_words(t, tm, tp);
+  uint32_t w[27];
+  gather_pair<ST>(pull_groups(src, u), p, w);
+  const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
+  PairWord<ST> pw[27];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float df[27];
+#pragma unroll
+    for (int a = 0; a < 27; ++a) df[a] = decode_scale<ST>(word_half<ST>(w[a], h), wclass(a), k);
+    float fx, fy, fz;
+    node_force(force, nrow, 2 * t + h, k, fx, fy, fz);
+    float out[27];
+    collide_fenced<3, RAW, false, false>(df, fx, fy, fz, k, out, g[h][0], g[h][1], g[h][2]);
+    if (drho_out != nullptr) st_off(drho_out + nrow, 2 * t + h, low_moments(df).m000);
+    if constexpr (ST == 3) {
+      const uint32_t r16 = sr_bits((uint32_t)nrow + 2 * t + h, k.seq_hash);
+#pragma unroll
+      for (int a = 0; a < 27; ++a) pw[a].put(h, out[a], r16);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 27; ++a) pw[a].put(h, encode_scale<ST>(out[a], wclass(a), k));
+    }
+  }
+  uint32_t o[27];
+#pragma unroll
+  for (int a = 0; a < 27; ++a) o[a] = pw[a].bits();
   store_pair_own<ST>(own_groups(dst, u), store_offset(p.xw[1]), o);
 }
 
@@ -525,6 +579,19 @@ static hipError_t launch_step_t(const lbm_handle& h, const void* src, void* dst,
   // fuses differently from the one-node kernel, so the results would differ in
   // the last bit)
   if constexpr (ST != 0 && !HI) {
+    if (kind == 0 && h.pairs && h.p.corr == LBM_CORR_FULL && h.p.nx % 2 == 0) {
+      constexpr int pblock = 128;                               // lds of 2 * 128 + 2 columns
+      const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);
+      const int64_t pnb = (int64_t)pbpr * h.p.ny * h.p.nz;
+      if (pnb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+      if (h.p.moments == LBM_RAW)
+        hipLaunchKernelGGL((k_step_full_pair<ST, true>), dim3((unsigned)pnb), dim3(pblock), 0, st, s, d, force,
+                           grad_src, drho_out, h.k, pbpr);
+      else
+        hipLaunchKernelGGL((k_step_full_pair<ST, false>), dim3((unsigned)pnb), dim3(pblock), 0, st, s, d, force,
+                           grad_src, drho_out, h.k, pbpr);
+      return hipGetLastError();
+    }
     if (kind == 0 && h.pairs && h.p.corr != LBM_CORR_FULL && h.p.nx % 2 == 0) {
       constexpr int pblock = 128;                               // measured best of 64 / 128 / 256
       const uint32_t pbpr = (uint32_t)((h.p.nx / 2 + pblock - 1) / pblock);

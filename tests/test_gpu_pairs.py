@@ -127,3 +127,42 @@ def test_aa_pair_step_equals_one_node_step(case):
         f1, f2 = one.export_populations(s1), two.export_populations(s2)
         _say(f"{name}: max |pairs - one node| = {(f1 - f2).abs().max().item():.3e}")
         assert torch.equal(f1, f2)
+
+
+FULL_CASES = [
+    # name, grid, r, s, moments, storage, force field, mode
+    ("full_lagged_f16_field", (256, 6, 5), 1.0, 0.5, "central", "f16", True, "lagged"),
+    ("full_exact_bf16", (130, 5, 4), 0.5, 0.25, "central", "bf16", False, "exact"),
+    ("full_lagged_raw_bf16sr", (300, 4, 6), 1.0, 0.5, "raw", "bf16_sr", True, "lagged"),
+    ("full_lagged_two_wide_f16", (2, 7, 5), 0.75, 1.0, "central", "f16", False, "lagged"),
+]
+
+
+@pytest.mark.parametrize("case", FULL_CASES, ids=[c[0] for c in FULL_CASES])
+def test_full_pair_step_equals_one_node_step(case):
+    """The full-correction step with two nodes per thread (the pairs' column sums and density output)
+    against its one-node kernel, in both time levels of the density gradient: states and density
+    fields bit for bit."""
+    name, (nx, ny, nz), r, s, moments, storage, field, mode = case
+    _say("case", name)
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.4, omega_xi=1.15, corr="full", moments=moments)
+    f0 = random_state(p, 75)
+    g = np.random.Generator(np.random.PCG64(76))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda() if field else None
+    uniform = (1e-5, -2e-6, 3e-6)
+    one = _lattice(p, storage, uniform, pairs=False)
+    two = _lattice(p, storage, uniform, pairs=True)
+    a1, b1 = one.new_state(), one.new_state()
+    a2, b2 = two.new_state(), two.new_state()
+    one.import_populations(a1, f0.cuda())
+    two.import_populations(a2, f0.cuda())
+    d1, e1 = one.density(a1), one.field(1)
+    d2, e2 = two.density(a2), two.field(1)
+    for n in (1, 4):
+        a1, b1, d1, e1 = one.step_full(a1, b1, n, d1, e1, mode, force)
+        a2, b2, d2, e2 = two.step_full(a2, b2, n, d2, e2, mode, force)
+        f1, f2 = one.export_populations(a1), two.export_populations(a2)
+        _say(f"{name}: max |pairs - one node| = {(f1 - f2).abs().max().item():.3e}")
+        assert torch.equal(f1, f2)
+        if mode == "lagged":
+            assert torch.equal(d1, d2)
