@@ -1,6 +1,10 @@
 """Benchmark of the fused cuboid D3Q27 collide-and-stream step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--variants f32,f16,bf16,adjoint]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--variants f32,f16,...] [--no-cpu-baseline]
+
+Variants: f32, f16, bf16, bf16_sr (the step per storage format), full_f32,
+full_f16 (full corrections, lagged gradient), aa_f32, aa_f16 (in-place AA
+layout), adjoint_f32, adjoint_f32_hbm, adjoint_f16 (the adjoint workloads).
 
 Workload: the decaying Taylor-Green + random-mode flow on the periodic
 512x512x256 cuboid grid (r = 1, s = 1/2, Re 1600), inputs resident in HBM
