@@ -1,9 +1,10 @@
 """GPU checks at the workloads' full sizes and launch configurations.
 
 * 512x512x256 (r = 1, s = 1/2): one step of the throughput workload in FP32,
-  FP16 and BF16 storage, compared element by element with the FP64 oracle on
-  64 seeded nodes; the oracle collides the 27 upstream neighbours of each
-  sampled node (from the stored start) and streams them into it.  The AA
+  FP16, BF16 and BF16-SR storage, and with the full corrections in FP32 and
+  FP16, compared element by element with the FP64 oracle on 64 seeded nodes;
+  the oracle collides the 27 upstream neighbours of each sampled node (from
+  the stored start) and streams them into it.  The AA
   layout equals the two-buffer layout bit for bit after two steps.
 * 512x512x256, 1000 steps: FP16 and BF16 deviation storage against FP32
   storage (velocity and kinetic-energy error, stated), and a 32x32x16 replica
@@ -55,7 +56,7 @@ def decaying_u0():
     return W.initial_velocity(W.DECAYING_512)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "bf16_sr"])
 def test_throughput_workload_one_step_sampled(decaying_u0, storage):
     """One step in the launch configuration bench.py times (for 16-bit storage the
     two-nodes-per-thread kernel), sampled nodes against the oracle from the stored start."""
@@ -93,8 +94,64 @@ def test_throughput_workload_one_step_sampled(decaying_u0, storage):
     if storage == "f32":
         assert err < 2e-7
     else:
-        # rounding of the stored deviation: 11 (FP16) or 8 (BF16) significand bits
+        # rounding of the stored deviation: 11 (FP16) or 8 (BF16; stochastic: up to one unit) significand bits
         assert err < (2e-3 if storage == "f16" else 1.6e-2) * dev
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_full_corrections_one_step_sampled(decaying_u0, storage):
+    """The full corrections at 512x512x256 in the launch configuration bench.py times (lagged time
+    level, whose first step takes the gradient of its own input's density; for FP16 the
+    two-nodes-per-thread kernel): 64 sampled nodes against the oracle from the stored start.  Each
+    upstream neighbour's density gradient comes from the oracle's stencil on the 5x5x5 patch of
+    densities around the sampled node (the patch's wrap never reaches the 3x3x3 centre it is read at)."""
+    w = W.DECAYING_512
+    p = oracle_params(w, corr="full")
+    lat = gpu_lattice(p, storage=storage)
+    a, b = lat.new_state(), lat.new_state()
+    lat.init(a, u=torch.from_numpy(decaying_u0).cuda())
+    start = lat.export_populations(a)
+    d_a, d_b = lat.density(a), lat.field(1)
+    cur, _, _, _ = lat.step_full(a, b, 1, d_a, d_b, "lagged")
+    del a
+    samples = W.sample_indices(64, p.n, 79)
+    zs, ys, xs = np.unravel_index(samples, p.shape)
+    full = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_export(lat.h, cur, full)
+    idx = torch.from_numpy(np.stack([zs, ys, xs])).cuda()
+    f_gpu = full[:, idx[0], idx[1], idx[2]].cpu()
+    del full
+    # densities of the 5x5x5 patch around every sampled node, from the stored start
+    off = np.arange(-2, 3)
+    pz = (zs[:, None, None, None] + off[None, :, None, None]) % p.nz
+    py = (ys[:, None, None, None] + off[None, None, :, None]) % p.ny
+    px = (xs[:, None, None, None] + off[None, None, None, :]) % p.nx
+    shape5 = (len(samples), 5, 5, 5)
+    pidx = torch.from_numpy(np.stack([np.broadcast_to(v, shape5).ravel() for v in (pz, py, px)])).cuda()
+    rho5 = start[:, pidx[0], pidx[1], pidx[2]].sum(0).reshape(shape5).cpu()
+    p5 = oracle.Params(5, 5, 5, r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi, corr="full")
+    eb = LT.ebar().numpy()
+    grads = []
+    for i in range(len(samples)):
+        g5 = OL.density_gradient(rho5[i], p5)                        # (3, 5, 5, 5)
+        # upstream neighbour x - ebar_a sits at patch index 2 - ebar_a
+        grads.append(torch.stack([g5[:, 2 - int(eb[a_, 2]), 2 - int(eb[a_, 1]), 2 - int(eb[a_, 0])]
+                                  for a_ in range(27)]))             # (27, 3)
+    grad_nb = torch.stack(grads, 1).reshape(27 * len(samples), 3)    # same order as f_nb below
+    nb_z = (zs[None, :] - eb[:, 2:3]) % p.nz
+    nb_y = (ys[None, :] - eb[:, 1:2]) % p.ny
+    nb_x = (xs[None, :] - eb[:, 0:1]) % p.nx
+    idx = torch.from_numpy(np.stack([nb_z.ravel(), nb_y.ravel(), nb_x.ravel()])).cuda()
+    f_nb = start[:, idx[0], idx[1], idx[2]].T.cpu()                  # (27 * samples, 27)
+    del start
+    ft = C.collide(f_nb, torch.zeros(f_nb.shape[0], 3, dtype=DT), p, grad_rho=grad_nb)
+    ft = ft.reshape(27, len(samples), 27)
+    want = torch.stack([ft[a_, :, a_] for a_ in range(27)])
+    err = (f_gpu - want).abs().max().item()
+    dev = (want - EQ.rest_weights(p.r, p.s, p.cs2)[:, None]).abs().max().item()
+    _say(f"512x512x256 full corrections {storage} one step, 64 sampled nodes: max |f_gpu - f_oracle| = "
+         f"{err:.3e} (max deviation {dev:.2e})")
+    assert err < (2e-7 if storage == "f32" else 2e-3 * dev)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
