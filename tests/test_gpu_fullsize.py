@@ -15,6 +15,8 @@
   checkpoint, the 16-bit formats within stated bounds.
 * 64x128x32 duct (r = 1, s = 1/4, walls in y and z): 20,000 steps to steady
   state against the rectangular-duct series.
+* One adjoint step on the 512x512x128 duct (force field) and the 384x384x192
+  FP16 grid, sampled nodes (walls included) against the oracle's collision VJP.
 * 384x384x192 FP16 adjoint (r = 1/2, s = 1/4): gradient of the final-velocity
   loss with respect to the initial velocity after 1000 steps (checkpoint every
   100), FP16 storage against FP32 storage (stated error), and the FP16 path
@@ -349,6 +351,84 @@ def test_fp16_workload_gradient_1000_steps_against_oracle():
 # (gradient, loss) bounds of the 1000-step replica gradient against the oracle, about twice the
 # measured errors (f32 3.4e-5 / 2.4e-10, f16 2.3e-4 / 1.7e-6, bf16 1.9e-2 / 1.4e-4, bf16_sr 1.2e-3 / 5.2e-5)
 GRAD_BOUND = {"f32": (7e-5, 1e-9), "f16": (5e-4, 4e-6), "bf16": (4e-2, 3e-4), "bf16_sr": (2.5e-3, 1.2e-4)}
+
+
+ADJ_FULL_CASES = [
+    # name, workload, storage, per-node force field
+    ("duct_512x512x128_f32_field", "duct", "f32", True),
+    ("periodic_384x384x192_f16", "f16", "f16", False),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_FULL_CASES, ids=[c[0] for c in ADJ_FULL_CASES])
+def test_adjoint_step_full_size_sampled(case):
+    """One adjoint step on the bench's adjoint grids (the HBM-resident duct with a force field, the FP16
+    periodic workload) in its launch configuration, 64 seeded nodes plus 8 on the duct walls' faces,
+    edges and corners against the oracle: the VJP of the
+    oracle's collision at the node, with the cotangents of its outputs taken where the next step
+    gathers them (x + ebar_b, or the node's opposite slot across a wall)."""
+    name, which, storage, field = case
+    _say("case", name)
+    w = W.replica(W.ADJOINT_DUCT_128, 512, 512, 128) if which == "duct" else W.ADJOINT_F16_384
+    p = oracle_params(w)
+    dev_ = torch.device("cuda")
+    gen = torch.Generator(device=dev_).manual_seed(83)
+    lat = gpu_lattice(p, storage=storage)
+    st, tmp = lat.new_state(), lat.new_state()
+    lat.init(st, u=0.03 * torch.randn((3, *p.shape), dtype=DT, device=dev_, generator=gen))
+    force = (1e-4 * torch.randn((3, *p.shape), device=dev_, generator=gen)) if field else None
+    st, tmp = lat.step(st, tmp, 2, force)                      # a state away from equilibrium
+    del tmp
+    start = lat.export_populations(st)                          # the gathered (natural) values, decoded
+    lam_nat = torch.randn((27, *p.shape), dtype=DT, device=dev_, generator=gen)
+    lam_in, lam_out = lat.new_adjoint(), lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam_nat, lam_in)
+    lam_nat = lam_nat.to(torch.float32).to(DT)                  # the values the kernel reads
+    gF = torch.zeros((3, *p.shape), dtype=torch.float32, device=dev_) if field else None
+    P.lbm_step_adjoint(lat.h, st, lam_in, lam_out, force, gF)
+    got_nat = torch.empty((27, *p.shape), dtype=DT, device=dev_)
+    P.lbm_adjoint_to_natural(lat.h, lam_out, got_nat)
+    samples = W.sample_indices(64, p.n, 85)
+    zi, yi, xi = np.unravel_index(samples, p.shape)
+    # and the walls' faces, edges and corners (the duct's walls lie in y and z), x at both row ends
+    yb, zb = [0, p.ny - 1, 0, p.ny - 1, 0, p.ny - 1, p.ny // 2, p.ny // 3], [0, 0, p.nz - 1, p.nz - 1, p.nz // 2,
+                                                                            p.nz // 3, 0, p.nz - 1]
+    xb = [0, p.nx - 1, 1, p.nx // 2, p.nx - 2, 3, p.nx - 1, 0]
+    zs, ys, xs = (torch.from_numpy(np.concatenate([a_, b_])).to(dev_) for a_, b_ in ((zi, zb), (yi, yb), (xi, xb)))
+    samples = np.concatenate([samples, np.ravel_multi_index((zb, yb, xb), p.shape)])
+    got = got_nat[:, zs, ys, xs].T.cpu()                        # (samples, 27)
+    del got_nat
+    # cotangent of output b of node x: lambda(t+1) where the next step gathers it
+    eb = LT.ebar()
+    opp = LT.opposite()
+    lam_own = torch.empty((len(samples), 27), dtype=DT)
+    for b_ in range(27):
+        ex, ey, ez = (int(v) for v in eb[b_])
+        yy, zz = ys + ey, zs + ez
+        wall = torch.zeros_like(yy, dtype=torch.bool)
+        if p.bc_y == "bounceback":
+            wall |= (yy < 0) | (yy >= p.ny)
+        if p.bc_z == "bounceback":
+            wall |= (zz < 0) | (zz >= p.nz)
+        xx = (xs + ex) % p.nx
+        down = lam_nat[b_, zz % p.nz, yy % p.ny, xx]
+        own_opp = lam_nat[int(opp[b_]), zs, ys, xs]
+        lam_own[:, b_] = torch.where(wall, own_opp, down).cpu()
+    f_nodes = start[:, zs, ys, xs].T.cpu().clone().requires_grad_(True)
+    del start, lam_nat
+    F_nodes = (force[:, zs, ys, xs].T.cpu().to(DT) if field else torch.zeros(len(samples), 3, dtype=DT))
+    F_nodes = F_nodes.clone().requires_grad_(True)
+    out = C.collide(f_nodes, F_nodes, p)
+    want, want_F = torch.autograd.grad(out, (f_nodes, F_nodes), grad_outputs=lam_own)
+    err = (got - want).abs().max().item() / want.abs().max().item()
+    msg = f"{name}: one adjoint step, {len(samples)} sampled nodes: rel max err {err:.2e}"
+    if field:
+        gF_s = gF[:, zs, ys, xs].T.cpu().to(DT)
+        errF = (gF_s - want_F).abs().max().item() / want_F.abs().max().item()
+        msg += f", force gradient {errF:.2e}"
+        assert errF < 2e-5
+    _say(msg)
+    assert err < 2e-6
 
 
 def _replica_fixture():
