@@ -320,11 +320,28 @@ int lbm_check_sums(const double* sums_device, double* out_host, void* hip_stream
  *   grad_force_uniform: device double[3] or NULL: += the same summed over
  *               nodes (gradient with respect to the uniform force).
  * Moving walls (their terms depend on the node's density), the raw-moment
- * scheme and a general omega_hi are included.  Not implemented for the full corrections or the AA
- * layout (LBM_EINVAL; also for the other adjoint entry points below). */
+ * scheme and a general omega_hi are included.  The full corrections take
+ * lbm_step_adjoint_full (below; LBM_EINVAL here); the AA layout has no adjoint
+ * (LBM_EINVAL; also for the other adjoint entry points below). */
 int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);
+
+/* The adjoint step of the full corrections at the exact time level (one step
+ * of lbm_step_full with LBM_GRAD_EXACT; App. D's lambda and e_rho terms and
+ * the density gradient of the isotropic stencil of lbm_step_full).  Arguments
+ * as in lbm_step_adjoint (the handle's corrections must be LBM_CORR_FULL,
+ * LBM_EINVAL otherwise), plus two work fields the caller provides (the library
+ * allocates nothing), overwritten, contents unspecified afterwards:
+ *   drho_work: device float[n_nodes]     (the density deviation of state_t)
+ *   grad_work: device float[3][n_nodes]  (the cotangent of the density gradient)
+ * Besides the collision's transpose at every node, the gradient's cotangent
+ * flows back through the stencil to the densities it read, and from there to
+ * every population those nodes gathered. */
+int lbm_step_adjoint_full(lbm_handle* h, const void* state_t, const float* adj_in,
+                          float* adj_out, const float* force, float* grad_force,
+                          double* grad_force_uniform, float* drho_work, float* grad_work,
+                          void* hip_stream);
 
 /* lambda(T) from cotangents of the observables of a state (the transpose of
  * lbm_moments' rho/u map):

@@ -45,6 +45,64 @@ __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __rest
   }
 }
 
+// Transpose of the full corrections' density gradient (density_gradient_block:
+// grad rho(x) = sum_a c_a rho(nb(x, a)), nb the neighbour x + ebar_a with each
+// axis clamped at a wall), followed by d rho / d f = 1: every population node y
+// gathered gains g_rho(y) = sum_a sum_{x : nb(x, a) = y} c_a . gg(x), gg the
+// cotangent of the gradient that k_step_adjoint wrote.  Per axis the sources of
+// y are y - e (periodic: wrapped), plus y itself at a wall the shift points out of.
+__device__ __forceinline__ int stencil_sources(int v, int e, int n, bool wall, int (&out)[2]) {
+  if (e == 0) { out[0] = v; return 1; }
+  if (!wall) { out[0] = (v - e + n) % n; return 1; }
+  int c = 0;
+  if (v - e >= 0 && v - e < n) out[c++] = v - e;
+  if ((e < 0 && v == 0) || (e > 0 && v == n - 1)) out[c++] = v;
+  return c;
+}
+
+template <int A = 0>
+__device__ __forceinline__ void add_to_own_all(float* __restrict__ dst, int x, int y, int z, const Consts& k,
+                                               float v) {
+  dst[slot_of<A>(x, y, z, k)] += v;
+  if constexpr (A + 1 < 27) add_to_own_all<A + 1>(dst, x, y, z, k, v);
+}
+
+__global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ gg, float* __restrict__ adj, Consts k) {
+  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(node % k.nx);
+    const int64_t t = node / k.nx;
+    const int y = (int)(t % k.ny), z = (int)(t / k.ny);
+    float acc = 0.0f;
+    for (int ez = -1; ez <= 1; ++ez) {
+      int sz[2];
+      const int cz = stencil_sources(z, ez, k.nz, k.bb_z, sz);
+      const float wz = ez == 0 ? k.w0c[2] : k.w0s[2];
+      for (int ey = -1; ey <= 1; ++ey) {
+        int sy[2];
+        const int cy = stencil_sources(y, ey, k.ny, k.bb_y, sy);
+        const float wy = ey == 0 ? k.w0c[1] : k.w0s[1];
+        for (int ex = -1; ex <= 1; ++ex) {
+          int sx[2];
+          const int cx = stencil_sources(x, ex, k.nx, k.bb_x, sx);
+          const float wx = ex == 0 ? k.w0c[0] : k.w0s[0];
+          // the factorised stencil's coefficients (density_gradient_block)
+          const float c0 = 0.5f * (float)ex * wy * wz;
+          const float c1 = 0.5f * k.ic[1] * (float)ey * wx * wz;
+          const float c2 = 0.5f * k.ic[2] * (float)ez * wx * wy;
+          for (int iz = 0; iz < cz; ++iz)
+            for (int iy = 0; iy < cy; ++iy)
+              for (int ix = 0; ix < cx; ++ix) {
+                const int64_t src = ((int64_t)sz[iz] * k.ny + sy[iy]) * k.nx + sx[ix];
+                acc += c0 * gg[src] + c1 * gg[k.n + src] + c2 * gg[2 * k.n + src];
+              }
+        }
+      }
+    }
+    add_to_own_all(adj, x, y, z, k, acc);
+  }
+}
+
 // ------------------------------------------------------------------ observables adjoint
 template <int ST>
 __global__ __launch_bounds__(256) void k_moments_adjoint(const typename Store<ST>::T* __restrict__ state,
@@ -184,18 +242,33 @@ static int grid_cap(int64_t n, int cap) {
 }
 
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
-                               const float* force, float* grad_force, double* grad_force_uniform, hipStream_t st) {
-  hipError_t e;
+                               const float* force, float* grad_force, double* grad_force_uniform, float* drho,
+                               float* grad_rho, hipStream_t st) {
+  const bool full = h.p.corr == LBM_CORR_FULL;
+  hipError_t e = hipSuccess;
+  if (full) e = launch_density(h, state, drho, st);  // the density field the step's gradient came from
+  if (e != hipSuccess) return e;
   switch (h.p.storage) {
-    case LBM_F32: e = AdjointKernels<0>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
-    case LBM_F16: e = AdjointKernels<1>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
-    default: e = AdjointKernels<2>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, st); break;
+    case LBM_F32: e = AdjointKernels<0>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
+                                              grad_rho, st); break;
+    case LBM_F16: e = AdjointKernels<1>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
+                                              grad_rho, st); break;
+    default: e = AdjointKernels<2>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
+                                         grad_rho, st); break;
   }
-  if (e != hipSuccess || !h.k.moving) return e;
+  if (e != hipSuccess) return e;
   int64_t g = (h.n + 255) / 256;
   if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_moving_wall_adjoint, (unsigned)g, 256, 0, st, adj_in, adj_out, h.k);
-  return hipGetLastError();
+  if (h.k.moving) {
+    hipLaunchKernelGGL(k_moving_wall_adjoint, (unsigned)g, 256, 0, st, adj_in, adj_out, h.k);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (full) {
+    hipLaunchKernelGGL(k_density_vjp, (unsigned)g, 256, 0, st, grad_rho, adj_out, h.k);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force, const float* g_rho,

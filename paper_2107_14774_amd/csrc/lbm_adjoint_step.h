@@ -36,10 +36,13 @@ namespace clbm {
 // carry no velocity dependence and their cotangents come from lam directly.
 // HI: general higher-order rate w (collide_node): the equilibrium part scales
 // by w, the source and second-order factors change, and mu gains (1 - w) lam.
+// CORR 3 (full corrections): grx, gry, grz is the node's density gradient, and
+// bgrad receives lam^T dC/d(grad rho) (the cotangent of the gradient).
 template <int CORR, bool RAW = false, bool HI = false>
 __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, float fy, float fz, const Consts& k,
                                             const float (&lam)[27], float (&mu)[27], float& gfx, float& gfy,
-                                            float& gfz) {
+                                            float& gfz, float grx = 0.0f, float gry = 0.0f, float grz = 0.0f,
+                                            float* bgrad = nullptr) {
   // ---------------------------------------------------------------- forward recomputation
   const LowMoments M = low_moments(df);
   const float r = k.r, s = k.s, cs2 = k.cs2, rho0 = k.rho0;
@@ -59,24 +62,37 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
   const float kxz = Pxz - rho * ux * uz + 0.5f * (ux * fz + uz * fx);
   const float kyz = Pyz - rho * uy * uz + 0.5f * (uy * fz + uz * fy);
   const float wn = k.omega_nu, wx = k.omega_xi;
-  const float g = (CORR == 2) ? 1.5f : 0.0f, g3 = 2.0f * g;
+  const float g = (CORR >= 2) ? 1.5f : 0.0f, g3 = 2.0f * g;
   const float hn = 1.0f / wn - 0.5f, hx = 1.0f / wx - 0.5f;
   float csx = 0, cbx = 0, csy = 1, cby = 0, csz = 1, cbz = 0, det = 1, gx = 0, gy = 0, gz = 0, tx = 0, ty = 0, tz = 0;
   float c2d1 = 0.0f, c2d2 = 0.0f, c2s = 0.0f;
+  // the solve's right-hand sides: Rs1, Rs2, Rb plus the density-gradient terms e_sr1,
+  // e_sr2, e_br of App. D with the full corrections (as in collide_node)
+  float Rs1e = Rs1, Rs2e = Rs2, Rbe = Rb, es1 = 0.0f, es2 = 0.0f, eb = 0.0f;
+  const float ax = 0.5f * (3.0f * cs2 - 1.0f), ay = 0.5f * (3.0f * cs2 - k.c2[1]), az = 0.5f * (3.0f * cs2 - k.c2[2]);
   if constexpr (CORR != 0) {
     const float inw = 2.0f * cs2 / wn, inx = 2.0f * cs2 / wx;
-    const float ax = 0.5f * (3.0f * cs2 - 1.0f), ay = 0.5f * (3.0f * cs2 - k.c2[1]), az = 0.5f * (3.0f * cs2 - k.c2[2]);
     csx = -inw + ax + g * uxx; cbx = -inx + ax + g * uxx;
     csy = inw - ay - g * uyy; cby = -inx + ay + g * uyy;
     csz = inw - az - g * uzz; cbz = -inx + az + g * uzz;
     det = -csx * csz * cby - csy * (csx * cbz - csz * cbx);
-    gx = (-csz * cby * Rs1 - csy * (cbz * Rs2 - csz * Rb)) * __builtin_amdgcn_rcpf(det);
-    gy = (Rs1 - csx * gx) * __builtin_amdgcn_rcpf(csy);
-    gz = (Rs2 - csx * gx) * __builtin_amdgcn_rcpf(csz);
+    if constexpr (CORR == 3) {
+      const float tA = ax * ux * grx, tB = ay * uy * gry, tC = az * uz * grz;
+      es1 = tB - tA;
+      es2 = tC - tA;
+      eb = -(tA + tB + tC);
+      Rs1e += es1;
+      Rs2e += es2;
+      Rbe += eb;
+    }
+    gx = (-csz * cby * Rs1e - csy * (cbz * Rs2e - csz * Rbe)) * __builtin_amdgcn_rcpf(det);
+    gy = (Rs1e - csx * gx) * __builtin_amdgcn_rcpf(csy);
+    gz = (Rs2e - csx * gx) * __builtin_amdgcn_rcpf(csz);
     tx = -(g3 * uxx + 2.0f * ax); ty = -(g3 * uyy + 2.0f * ay); tz = -(g3 * uzz + 2.0f * az);
-    c2d1 = hn * (tx * gx - ty * gy);
-    c2d2 = hn * (tx * gx - tz * gz);
-    c2s = hx * (tx * gx + ty * gy + tz * gz);
+    // the lambda terms equal twice the e terms (collide_node)
+    c2d1 = hn * (tx * gx - ty * gy + 2.0f * es1);
+    c2d2 = hn * (tx * gx - tz * gz + 2.0f * es2);
+    c2s = hx * (tx * gx + ty * gy + tz * gz + 2.0f * eb);
   }
   const float wh = HI ? k.omega_hi : 1.0f;
   const float D2s = (wh - wx) * Rb + wx * c2s;
@@ -200,26 +216,39 @@ __device__ __forceinline__ void collide_vjp(const float (&df)[27], float fx, flo
     float bgx = tx * sx;
     const float bgy = ty * sy, bgz = tz * sz;
     const float icsy = __builtin_amdgcn_rcpf(csy), icsz = __builtin_amdgcn_rcpf(csz);
-    bRs1 += bgy * icsy;
-    bRs2 += bgz * icsz;
     float bcsx = -(bgy * icsy + bgz * icsz) * gx;
     bgx -= (bgy * icsy + bgz * icsz) * csx;
     float bcsy = -bgy * gy * icsy;
     float bcsz = -bgz * gz * icsz;
     const float idet = __builtin_amdgcn_rcpf(det);
     const float bN = bgx * idet, bdet = -bgx * gx * idet;
-    bRs1 -= csz * cby * bN;
-    bRs2 -= csy * cbz * bN;
-    bRb += csy * csz * bN;
-    bcsz += (-cby * Rs1 + csy * Rb) * bN + (-csx * cby + csy * cbx) * bdet;
-    const float bcby = -csz * Rs1 * bN - csx * csz * bdet;
-    bcsy += (-cbz * Rs2 + csz * Rb) * bN + (-csx * cbz + csz * cbx) * bdet;
-    const float bcbz = -csy * Rs2 * bN - csy * csx * bdet;
+    // cotangents of the solve's right-hand sides (they reach Rs1, Rs2, Rb, and the e terms)
+    const float sRs1 = bgy * icsy - csz * cby * bN;
+    const float sRs2 = bgz * icsz - csy * cbz * bN;
+    const float sRb = csy * csz * bN;
+    bRs1 += sRs1;
+    bRs2 += sRs2;
+    bRb += sRb;
+    bcsz += (-cby * Rs1e + csy * Rbe) * bN + (-csx * cby + csy * cbx) * bdet;
+    const float bcby = -csz * Rs1e * bN - csx * csz * bdet;
+    bcsy += (-cbz * Rs2e + csz * Rbe) * bN + (-csx * cbz + csz * cbx) * bdet;
+    const float bcbz = -csy * Rs2e * bN - csy * csx * bdet;
     bcsx += (-csz * cby - csy * cbz) * bdet;
     const float bcbx = csy * csz * bdet;
     buxx += g * (bcsx + bcbx);
     buyy += g * (bcby - bcsy);
     buzz += g * (bcbz - bcsz);
+    if constexpr (CORR == 3) {
+      // e_sr1 = tB - tA, e_sr2 = tC - tA, e_br = -(tA + tB + tC), tA = a_x u_x d_x rho, ...
+      const float bes1 = 2.0f * hn * bc2d1 + sRs1, bes2 = 2.0f * hn * bc2d2 + sRs2, beb = 2.0f * hx * bc2s + sRb;
+      const float btA = -(bes1 + bes2 + beb), btB = bes1 - beb, btC = bes2 - beb;
+      bux += btA * ax * grx;
+      buy += btB * ay * gry;
+      buz += btC * az * grz;
+      bgrad[0] = btA * ax * ux;
+      bgrad[1] = btB * ay * uy;
+      bgrad[2] = btC * az * uz;
+    }
   }
   // non-equilibrium second moments
   const float sR = bRb + bRs1 + bRs2, tRy = bRb - bRs1, tRz = bRb - bRs2;
@@ -320,13 +349,20 @@ __device__ __forceinline__ void store_own_adj(const GroupBases<float>& d, uint32
 template <int ST, int CORR, int WALLS, bool RAW, bool HI>
 __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ_WAVES_16)) void k_step_adjoint(
     const typename Store<ST>::T* __restrict__ state, const float* __restrict__ lin, float* __restrict__ lout,
-    const float* __restrict__ force, float* __restrict__ grad_force, double* __restrict__ grad_uniform, Consts k,
-    uint32_t bpr) {
+    const float* __restrict__ force, float* __restrict__ grad_force, double* __restrict__ grad_uniform,
+    const float* __restrict__ drho_src, float* __restrict__ grad_rho_out, Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   float gfx = 0.0f, gfy = 0.0f, gfz = 0.0f;
+  // full corrections: the node's density gradient from the density field of h(t), as the step
+  // computed it (block-wide, with a barrier)
+  float grx = 0.0f, gry = 0.0f, grz = 0.0f;
+  if constexpr (CORR == 3) {
+    __shared__ float lds[3][258];
+    density_gradient_block(drho_src, x, y, z, x < k.nx, k, lds, grx, gry, grz);
+  }
   if (x < k.nx) {
     Upstream u;
     upstream(x, y, z, k, u);
@@ -355,8 +391,15 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
       fy = ld_off(f + k.n, (uint32_t)x);
       fz = ld_off(f + 2 * k.n, (uint32_t)x);
     }
-    collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz);
+    float bgrad[3];
+    collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz, grx, gry, grz, bgrad);
     store_own_adj(own_groups(lout, u), store_offset(u.xo[1]), mu);
+    if constexpr (CORR == 3) {  // the cotangent of the node's density gradient, for k_density_vjp
+      float* go = grad_rho_out + nrow;
+      st_off(go, (uint32_t)x, bgrad[0]);
+      st_off(go + k.n, (uint32_t)x, bgrad[1]);
+      st_off(go + 2 * k.n, (uint32_t)x, bgrad[2]);
+    }
     if (grad_force != nullptr) {
       float* g = grad_force + nrow;
       g[x] += gfx;
@@ -381,7 +424,8 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
 // ------------------------------------------------------------------ launcher
 template <int ST, bool HI>
 static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
-                                        const float* force, float* grad_force, double* grad_uniform, hipStream_t st) {
+                                        const float* force, float* grad_force, double* grad_uniform,
+                                        const float* drho, float* grad_rho, hipStream_t st) {
   using T = typename Store<ST>::T;
   const int block = h.block;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
@@ -396,12 +440,13 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_ADJ(C, W, R)                                                                              \
   hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R, HI>), grid, blk, 0, st, s, adj_in, adj_out, force, grad_force, \
-                     grad_uniform, h.k, bpr)
+                     grad_uniform, drho, grad_rho, h.k, bpr)
 #define CLBM_ADJ_CORR(W, R)                  \
   switch (h.p.corr) {                        \
     case 0: CLBM_ADJ(0, W, R); break;        \
     case 1: CLBM_ADJ(1, W, R); break;        \
-    default: CLBM_ADJ(2, W, R); break;       \
+    case 2: CLBM_ADJ(2, W, R); break;        \
+    default: CLBM_ADJ(3, W, R); break;       \
   }
   const bool raw = h.p.moments == LBM_RAW;
   if (kind == 2) {
@@ -418,9 +463,12 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
 
 template <int ST>
 hipError_t AdjointKernels<ST>::step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
-                                    const float* force, float* grad_force, double* grad_uniform, hipStream_t st) {
-  return h.k.hi ? launch_step_adjoint_t<ST, true>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, st)
-                : launch_step_adjoint_t<ST, false>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, st);
+                                    const float* force, float* grad_force, double* grad_uniform, const float* drho,
+                                    float* grad_rho, hipStream_t st) {
+  return h.k.hi ? launch_step_adjoint_t<ST, true>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, drho,
+                                                  grad_rho, st)
+                : launch_step_adjoint_t<ST, false>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, drho,
+                                                   grad_rho, st);
 }
 
 }  // namespace clbm

@@ -46,8 +46,11 @@ extern template struct StepKernels<3>;
 
 template <int ST>
 struct AdjointKernels {
+  // drho, grad_rho: the full corrections' density field of the state and the field that receives
+  // the cotangent of its gradient (NULL otherwise)
   static hipError_t step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
-                         const float* force, float* grad_force, double* grad_uniform, hipStream_t st);
+                         const float* force, float* grad_force, double* grad_uniform, const float* drho,
+                         float* grad_rho, hipStream_t st);
 };
 extern template struct AdjointKernels<0>;
 extern template struct AdjointKernels<1>;
@@ -75,9 +78,10 @@ hipError_t launch_export_nodes(const lbm_handle& h, const void* src, const int64
                               hipStream_t st);
 hipError_t launch_moments(const lbm_handle& h, const void* src, const float* force, float* rho,
                           float* u, double* sums, hipStream_t st);
+// With the full corrections drho (float[n]) and grad_rho (float[3 n]) are the caller's work fields.
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in,
                                float* adj_out, const float* force, float* grad_force,
-                               double* grad_force_uniform, hipStream_t st);
+                               double* grad_force_uniform, float* drho, float* grad_rho, hipStream_t st);
 hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force,
                                   const float* g_rho, const float* g_u, float* adj,
                                   float* grad_force, hipStream_t st);

@@ -106,6 +106,16 @@ def test_full_corrections_need_the_density_field_entry_point():
     hl = P.lbm_create(4, 4, 4, corr="local")
     assert lib.lbm_step_full(hl.raw, 1, a, b, None, d1, d2, 1, None) == _lib.LBM_EINVAL
     assert b"LBM_CORR_FULL" in lib.lbm_last_error()
+    # the adjoint of the full corrections: its own entry point with two work fields
+    c = ctypes.c_void_p(0x30000)
+    assert lib.lbm_step_adjoint(hf.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
+    assert b"lbm_step_adjoint_full" in lib.lbm_last_error()
+    assert lib.lbm_step_adjoint_full(hl.raw, a, b, c, None, None, None, d1, d2, None) == _lib.LBM_EINVAL
+    assert b"LBM_CORR_FULL" in lib.lbm_last_error()
+    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, None, d2, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, d1, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, d1, d1, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, a, b, b, None, None, None, d1, d2, None) == _lib.LBM_EINVAL
 
 
 def test_adjoint_rejects_what_it_does_not_differentiate():
