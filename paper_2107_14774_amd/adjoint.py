@@ -7,7 +7,9 @@ and returns u(T) as a differentiable tensor.  Its backward pass runs the
 hand-written adjoint kernels of the library: lbm_moments_adjoint for the
 observables, lbm_step_adjoint once per step in reverse order, and
 lbm_init_adjoint for the initial velocity; the force gradient accumulates
-inside the adjoint step kernel.
+inside the adjoint step kernel.  With the full corrections the trajectory
+steps at the exact time level of the density gradient (lbm_step_full, mode
+"exact") and reverses through lbm_step_adjoint_full.
 
 Memory: the forward keeps one state every ``checkpoint_every`` steps; the
 backward recomputes one segment at a time from its checkpoint, holding that
@@ -22,13 +24,46 @@ import math
 
 import torch
 
+from . import _lib
 from . import lbm as L
+
+
+class _Steps:
+    """Forward steps and adjoint steps of a lattice: plain, or with the full corrections at the exact
+    time level (whose work fields this holds)."""
+
+    def __init__(self, lat):
+        self.lat = lat
+        self.full = lat.h.params.corr == _lib.CORR["full"]
+        self.drho = lat.field(1) if self.full else None
+        self.grad = None
+
+    def advance(self, a, b, n, force):
+        if self.full:
+            a, b, _, _ = self.lat.step_full(a, b, n, self.drho, None, "exact", force)
+            return a, b
+        return self.lat.step(a, b, n, force)
+
+    def step(self, src, dst, force):
+        if self.full:
+            L.lbm_step_full(self.lat.h, 1, src, dst, self.drho, None, "exact", force)
+        else:
+            L.lbm_step(self.lat.h, 1, src, dst, force)
+
+    def adjoint(self, state, lam, lam_next, force, grad_force):
+        if self.full:
+            if self.grad is None:
+                self.grad = self.lat.field(3)
+            L.lbm_step_adjoint_full(self.lat.h, state, lam, lam_next, self.drho, self.grad, force, grad_force)
+        else:
+            L.lbm_step_adjoint(self.lat.h, state, lam, lam_next, force, grad_force)
 
 
 class _Trajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, force, lat, rho0, nsteps, every, max_states):
         force_t = force if force.numel() else None
+        steps = _Steps(lat)
         a, b = lat.new_state(), lat.new_state()
         lat.init(a, rho=rho0, u=u0)
         # each checkpoint keeps the handle's step counter too, so that a recomputed segment
@@ -37,7 +72,7 @@ class _Trajectory(torch.autograd.Function):
         t = 0
         while t < nsteps:
             n = min(every, nsteps - t)
-            a, b = lat.step(a, b, n, force_t)
+            a, b = steps.advance(a, b, n, force_t)
             t += n
             if t < nsteps:
                 checkpoints.append(a.clone())
@@ -46,7 +81,7 @@ class _Trajectory(torch.autograd.Function):
         ctx.lat, ctx.nsteps, ctx.every, ctx.max_states = lat, nsteps, every, max_states
         ctx.checkpoints, ctx.counters, ctx.final = checkpoints, counters, a
         ctx.counter_end = L.lbm_step_counter(lat.h)
-        ctx.force, ctx.rho0 = force_t, rho0
+        ctx.force, ctx.rho0, ctx.steps = force_t, rho0, steps
         ctx.save_for_backward(u0)
         ctx.force_needs_grad = force.requires_grad
         return m.u
@@ -69,8 +104,8 @@ class _Trajectory(torch.autograd.Function):
         for seg in reversed(range(nseg)):
             start = seg * ctx.every
             n = min(ctx.every, ctx.nsteps - start)
-            lam, lam_next = _reverse_segment(lat, ctx.checkpoints[seg], ctx.counters[seg], n, lam, lam_next, force,
-                                             grad_force, ctx.max_states, pool)
+            lam, lam_next = _reverse_segment(ctx.steps, ctx.checkpoints[seg], ctx.counters[seg], n, lam, lam_next,
+                                             force, grad_force, ctx.max_states, pool)
             ctx.checkpoints[seg] = None
         L.lbm_set_step_counter(h, ctx.counter_end)
         g_u0 = torch.empty((3, *lat.shape), dtype=torch.float64, device=lat.device)
@@ -92,17 +127,17 @@ class _StatePool:
         self.free.extend(states)
 
 
-def _reverse_segment(lat, start_state, counter, n, lam, lam_next, force, grad_force, max_states, pool):
+def _reverse_segment(steps, start_state, counter, n, lam, lam_next, force, grad_force, max_states, pool):
     """Apply the adjoint of n steps starting from ``start_state`` (taken with step counter ``counter``);
     returns the swapped adjoint buffers."""
-    h = lat.h
+    h = steps.lat.h
     if n <= max_states:
         states = [start_state] + [pool.get() for _ in range(n - 1)]
         L.lbm_set_step_counter(h, counter)
         for i in range(1, n):
-            L.lbm_step(h, 1, states[i - 1], states[i], force)
+            steps.step(states[i - 1], states[i], force)
         for i in reversed(range(n)):
-            L.lbm_step_adjoint(h, states[i], lam, lam_next, force, grad_force)
+            steps.adjoint(states[i], lam, lam_next, force, grad_force)
             lam, lam_next = lam_next, lam
         pool.put(*states[1:])
         return lam, lam_next
@@ -117,11 +152,11 @@ def _reverse_segment(lat, start_state, counter, n, lam, lam_next, force, grad_fo
         starts.append(keep)
         m = min(sub, n - s0)
         if s0 + m < n:
-            cur, tmp = lat.step(cur, tmp, m, force)
+            cur, tmp = steps.advance(cur, tmp, m, force)
     pool.put(cur, tmp)
     for j in reversed(range(len(starts))):
         m = min(sub, n - j * sub)
-        lam, lam_next = _reverse_segment(lat, starts[j], counter + j * sub, m, lam, lam_next, force, grad_force,
+        lam, lam_next = _reverse_segment(steps, starts[j], counter + j * sub, m, lam, lam_next, force, grad_force,
                                          max_states, pool)
         pool.put(starts[j])
     return lam, lam_next

@@ -271,3 +271,35 @@ def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
     assert err < 2e-6 and share > 50 * err
     assert errF < 2e-5
     assert errU < 1e-4
+
+
+@pytest.mark.parametrize("max_states", [128, 2])
+def test_full_corrections_trajectory_gradient_matches_oracle(max_states):
+    """dL/dF and dL/du0 through 18 steps with the full corrections (exact time level) on a 12x10x8 replica
+    of the adjoint duct, from a start with a density variation so that the density-gradient terms
+    matter; with max_states = 2 the backward pass nests its recomputation."""
+    w = W.ADJOINT_DUCT_128
+    p = oracle_params(w, corr="full", nx=12, ny=10, nz=8)
+    p_loc = oracle_params(w, corr="local", nx=12, ny=10, nz=8)
+    g = np.random.Generator(np.random.PCG64(43))
+    force = torch.tensor(1e-5 * g.standard_normal((3, *p.shape))).to(torch.float32)
+    u0 = torch.tensor(0.02 * g.standard_normal((3, *p.shape)))
+    rho0 = torch.tensor(1.0 + 0.02 * g.standard_normal(p.shape))
+    target = torch.tensor(1e-3 * g.standard_normal((3, *p.shape)))
+    nsteps = 18
+    L_o, gF_o, gu_o = G.loss_and_gradients(p, rho0, u0, force.to(DT), target, nsteps)
+    _, gF_l, gu_l = G.loss_and_gradients(p_loc, rho0, u0, force.to(DT), target, nsteps)
+    lat = gpu_lattice(p)
+    uc = u0.cuda().requires_grad_(True)
+    Fc = force.cuda().requires_grad_(True)
+    u = ADJ.simulate(lat, uc, Fc, nsteps, 6, rho0=rho0.cuda(), max_states=max_states)
+    L_g = 0.5 * ((u.to(DT) - target.cuda()) ** 2).sum()
+    L_g.backward()
+    eF = rel_l2(Fc.grad.cpu(), gF_o)
+    eu = rel_l2(uc.grad.cpu(), gu_o)
+    shareF, shareu = rel_l2(gF_l, gF_o), rel_l2(gu_l, gu_o)
+    _say(f"full-correction trajectory (max_states {max_states}): loss rel err "
+         f"{abs(float(L_g.detach()) - L_o.item()) / L_o.item():.2e}, dL/dF rel L2 {eF:.2e} "
+         f"(local corrections differ by {shareF:.2e}), dL/du0 rel L2 {eu:.2e} (local: {shareu:.2e})")
+    assert eF < 1e-4 and eu < 1e-4
+    assert shareF > 20 * eF and shareu > 20 * eu
