@@ -4,7 +4,8 @@
 
 Variants: f32, f16, bf16, bf16_sr (the step per storage format), full_f32,
 full_f16 (full corrections, lagged gradient), aa_f32, aa_f16 (in-place AA
-layout), adjoint_f32, adjoint_f32_hbm, adjoint_f16 (the adjoint workloads).
+layout), adjoint_f32, adjoint_f32_hbm, adjoint_f16 (the adjoint workloads),
+adjoint_full_f32 (the adjoint of the full corrections on the 512x512x128 duct).
 
 Workload: the decaying Taylor-Green + random-mode flow on the periodic
 512x512x256 cuboid grid (r = 1, s = 1/2, Re 1600), inputs resident in HBM
@@ -57,9 +58,15 @@ AA_VARIANTS = {"aa_f32": "f32", "aa_f16": "f16"}
 BYTES_PER_LUP.update({"aa_f32": 216, "aa_f16": 108})
 # adjoint step: state gather + lambda(t+1) read + lambda(t) write (+ force read, force-gradient update)
 ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f32_hbm": 108 + 108 + 108 + 12 + 24,
-                     "adjoint_f16": 54 + 108 + 108}
-# forward step bytes of the state type an adjoint variant recomputes with (per-node force read included)
-ADJ_FORWARD_BYTES = {"adjoint_f32": 216 + 12, "adjoint_f32_hbm": 216 + 12, "adjoint_f16": 108}
+                     "adjoint_f16": 54 + 108 + 108,
+                     # full corrections: the density pass (state read, density written), the adjoint step
+                     # (as above plus the density read and the gradient cotangent written), the stencil's
+                     # transpose (cotangent read, the node's 27 adjoint values read and written)
+                     "adjoint_full_f32": (108 + 4) + (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108)}
+# forward step bytes of the state type an adjoint variant recomputes with (per-node force read included;
+# the full corrections' exact time level adds a density pass and the density read)
+ADJ_FORWARD_BYTES = {"adjoint_f32": 216 + 12, "adjoint_f32_hbm": 216 + 12, "adjoint_f16": 108,
+                     "adjoint_full_f32": (108 + 4) + 216 + 12 + 4}
 # the paper's only cost figures (Sec. 6, shallow cavity, no hardware or times): node-count ratios cubic / cuboid
 PAPER_CONTEXT = {"source": "Sec. 6 shallow lid-driven cavity, L/H = 4, W/H = 2, Re = 100; no hardware, precision or "
                            "times are given",
@@ -216,6 +223,8 @@ def adjoint_workload(kind):
         return W.ADJOINT_DUCT_128, "f32"
     if kind == "adjoint_f32_hbm":
         return W.replica(W.ADJOINT_DUCT_128, 512, 512, 128, name="adjoint_duct_512x512x128"), "f32"
+    if kind == "adjoint_full_f32":
+        return W.replica(W.ADJOINT_DUCT_128, 512, 512, 128, name="adjoint_duct_512x512x128_full"), "f32"
     return W.ADJOINT_F16_384, "f16"
 
 
@@ -225,9 +234,10 @@ def run_adjoint(kind, steps, warmup):
     import paper_2107_14774_amd as P
     from paper_2107_14774_amd import adjoint as ADJ
     w, storage = adjoint_workload(kind)
+    full = kind == "adjoint_full_f32"
     on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
     lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
-                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="local")
+                    bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="full" if full else "local")
     force = None
     if storage == "f32":
         force = torch.from_numpy(W.body_force_field(w)).to(torch.float32).cuda()
@@ -236,19 +246,30 @@ def run_adjoint(kind, steps, warmup):
         u0 = torch.from_numpy(W.initial_velocity(w)).cuda()
     st, tmp = lat.new_state(), lat.new_state()
     lat.init(st, u=u0)
-    st, tmp = lat.step(st, tmp, 10, force)
+    if full:
+        drho, gwork = lat.field(1), lat.field(3)
+        st, tmp, _, _ = lat.step_full(st, tmp, 10, drho, None, "exact", force)
+    else:
+        st, tmp = lat.step(st, tmp, 10, force)
     lam_a = lat.new_adjoint().normal_()
     lam_b = lat.new_adjoint()
     grad = torch.zeros((3, w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda") if force is not None else None
     stream = torch.cuda.current_stream()
+
+    def adjoint_step(la, lb):
+        if full:  # density pass, adjoint step, the stencil's transpose
+            P.lbm_step_adjoint_full(lat.h, st, la, lb, drho, gwork, force, grad, stream=stream)
+        else:
+            P.lbm_step_adjoint(lat.h, st, la, lb, force, grad, stream=stream)
+
     for _ in range(warmup):
-        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
+        adjoint_step(lam_a, lam_b)
         lam_a, lam_b = lam_b, lam_a
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(steps):
-        P.lbm_step_adjoint(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
+        adjoint_step(lam_a, lam_b)
         lam_a, lam_b = lam_b, lam_a
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -515,7 +536,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--variants", default="f32,f16,bf16,bf16_sr,full_f32,full_f16,aa_f32,aa_f16,adjoint_f32,"
-                                          "adjoint_f32_hbm,adjoint_f16")
+                                          "adjoint_f32_hbm,adjoint_f16,adjoint_full_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 CSVs under DIR (no GPU needed)")

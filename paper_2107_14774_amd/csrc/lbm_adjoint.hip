@@ -60,47 +60,91 @@ __device__ __forceinline__ int stencil_sources(int v, int e, int n, bool wall, i
   return c;
 }
 
-template <int A = 0>
-__device__ __forceinline__ void add_to_own_all(float* __restrict__ dst, int x, int y, int z, const Consts& k,
-                                               float v) {
-  dst[slot_of<A>(x, y, z, k)] += v;
-  if constexpr (A + 1 < 27) add_to_own_all<A + 1>(dst, x, y, z, k, v);
+// The stencil's coefficients factorise like the forward's (density_gradient_block):
+//   c_a = (0.5 ex Wy Wz, 0.5 ic_y ey Wx Wz, 0.5 ic_z ez Wx Wy),
+// so each thread reduces the transverse (y, z) sources of its own column X into
+//   A(X) = sum Wy Wz ggx,  B(X) = sum ey Wz ggy,  C(X) = sum Wy ez ggz
+// (the sources of the block's row), and the x shift combines neighbouring
+// columns through LDS: g_rho(x) = sum_ex [0.5 ex A + 0.5 (ic_y B + ic_z C) Wx(ex)](X)
+// over the x sources X of each ex.
+__device__ __forceinline__ void transverse_column(const float* __restrict__ gg, int X, int y, int z,
+                                                  const Consts& k, float& A, float& B, float& C) {
+  A = 0.0f; B = 0.0f; C = 0.0f;
+#pragma unroll
+  for (int ez = -1; ez <= 1; ++ez) {
+    int sz[2];
+    const int cz = stencil_sources(z, ez, k.nz, k.bb_z, sz);
+    const float wz = ez == 0 ? k.w0c[2] : k.w0s[2];
+#pragma unroll
+    for (int ey = -1; ey <= 1; ++ey) {
+      int sy[2];
+      const int cy = stencil_sources(y, ey, k.ny, k.bb_y, sy);
+      const float wy = ey == 0 ? k.w0c[1] : k.w0s[1];
+      for (int iz = 0; iz < cz; ++iz)
+        for (int iy = 0; iy < cy; ++iy) {
+          const int64_t src = ((int64_t)sz[iz] * k.ny + sy[iy]) * k.nx + X;
+          A += wy * wz * gg[src];
+          if (ey != 0) B += (float)ey * wz * gg[k.n + src];
+          if (ez != 0) C += wy * (float)ez * gg[2 * k.n + src];
+        }
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ gg, float* __restrict__ adj, Consts k) {
-  for (int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; node < k.n;
-       node += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(node % k.nx);
-    const int64_t t = node / k.nx;
-    const int y = (int)(t % k.ny), z = (int)(t / k.ny);
-    float acc = 0.0f;
-    for (int ez = -1; ez <= 1; ++ez) {
-      int sz[2];
-      const int cz = stencil_sources(z, ez, k.nz, k.bb_z, sz);
-      const float wz = ez == 0 ? k.w0c[2] : k.w0s[2];
-      for (int ey = -1; ey <= 1; ++ey) {
-        int sy[2];
-        const int cy = stencil_sources(y, ey, k.ny, k.bb_y, sy);
-        const float wy = ey == 0 ? k.w0c[1] : k.w0s[1];
-        for (int ex = -1; ex <= 1; ++ex) {
-          int sx[2];
-          const int cx = stencil_sources(x, ex, k.nx, k.bb_x, sx);
-          const float wx = ex == 0 ? k.w0c[0] : k.w0s[0];
-          // the factorised stencil's coefficients (density_gradient_block)
-          const float c0 = 0.5f * (float)ex * wy * wz;
-          const float c1 = 0.5f * k.ic[1] * (float)ey * wx * wz;
-          const float c2 = 0.5f * k.ic[2] * (float)ez * wx * wy;
-          for (int iz = 0; iz < cz; ++iz)
-            for (int iy = 0; iy < cy; ++iy)
-              for (int ix = 0; ix < cx; ++ix) {
-                const int64_t src = ((int64_t)sz[iz] * k.ny + sy[iy]) * k.nx + sx[ix];
-                acc += c0 * gg[src] + c1 * gg[k.n + src] + c2 * gg[2 * k.n + src];
-              }
-        }
-      }
+// v added to the node's 27 own elements (row start, chunk, x offset)
+template <int A = 0>
+__device__ __forceinline__ void add_own_row(float* __restrict__ row, uint32_t xo, float v) {
+  float* p = row + chunk_of(A) * kB + xo;
+  *p += v;
+  if constexpr (A + 1 < 27) add_own_row<A + 1>(row, xo, v);
+}
+
+// One block per row segment (like the step); every thread of the block calls the barrier.
+__global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ gg, float* __restrict__ adj, Consts k,
+                                                     uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  const int t = (int)threadIdx.x;
+  const bool active = x < k.nx;
+  // lds[c][t + 1]: column x of the block; [0] and [blockDim + 1]: the columns left and right of it
+  __shared__ float lds[3][258];
+  if (active) {
+    float A, B, C;
+    transverse_column(gg, x, y, z, k, A, B, C);
+    lds[0][t + 1] = A; lds[1][t + 1] = B; lds[2][t + 1] = C;
+    if (t == 0 && x > 0) {
+      transverse_column(gg, x - 1, y, z, k, A, B, C);
+      lds[0][0] = A; lds[1][0] = B; lds[2][0] = C;
     }
-    add_to_own_all(adj, x, y, z, k, acc);
+    if ((t == (int)blockDim.x - 1 || x == k.nx - 1) && x < k.nx - 1) {
+      transverse_column(gg, x + 1, y, z, k, A, B, C);
+      lds[0][t + 2] = A; lds[1][t + 2] = B; lds[2][t + 2] = C;
+    }
   }
+  __syncthreads();
+  if (!active) return;
+  // the row's ends: a periodic x wraps to the other end of the row, which another block holds
+  float Am, Bm, Cm, Ap, Bp, Cp;
+  if (x > 0) { Am = lds[0][t]; Bm = lds[1][t]; Cm = lds[2][t]; }
+  else transverse_column(gg, k.nx - 1, y, z, k, Am, Bm, Cm);
+  if (x < k.nx - 1) { Ap = lds[0][t + 2]; Bp = lds[1][t + 2]; Cp = lds[2][t + 2]; }
+  else transverse_column(gg, 0, y, z, k, Ap, Bp, Cp);
+  const float A0 = lds[0][t + 1], B0 = lds[1][t + 1], C0 = lds[2][t + 1];
+  const float hy = 0.5f * k.ic[1], hz = 0.5f * k.ic[2];
+  const float wc = k.w0c[0], ws = k.w0s[0];
+  // ex = 0: the column itself
+  float g = wc * (hy * B0 + hz * C0);
+  // ex = +1: source x - 1 (at an x wall, x = 0 has none; x = nx - 1 also itself)
+  // ex = -1: source x + 1 (at an x wall, x = nx - 1 has none; x = 0 also itself)
+  const bool wx = k.bb_x;
+  const bool has_m = !(wx && x == 0), has_p = !(wx && x == k.nx - 1);
+  if (has_m) g += 0.5f * Am + ws * (hy * Bm + hz * Cm);
+  if (has_p) g += -0.5f * Ap + ws * (hy * Bp + hz * Cp);
+  if (wx && x == k.nx - 1) g += 0.5f * A0 + ws * (hy * B0 + hz * C0);
+  if (wx && x == 0) g += -0.5f * A0 + ws * (hy * B0 + hz * C0);
+  add_own_row(adj + row_start(y, z, k), xoff((uint32_t)x), g);
 }
 
 // ------------------------------------------------------------------ observables adjoint
@@ -265,7 +309,11 @@ hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const flo
     if (e != hipSuccess) return e;
   }
   if (full) {
-    hipLaunchKernelGGL(k_density_vjp, (unsigned)g, 256, 0, st, grad_rho, adj_out, h.k);
+    const int block = h.block;
+    const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+    const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_density_vjp, dim3((unsigned)nb), dim3(block), 0, st, grad_rho, adj_out, h.k, bpr);
     e = hipGetLastError();
   }
   return e;
