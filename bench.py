@@ -74,7 +74,7 @@ PAPER_CONTEXT = {"source": "Sec. 6 shallow lid-driven cavity, L/H = 4, W/H = 2, 
 KERNEL_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_step.h",
                   "paper_2107_14774_amd/csrc/lbm_api.hip", "paper_2107_14774_amd/csrc/lbm_forward.hip")
 ADJOINT_SOURCES = ("paper_2107_14774_amd/csrc/lbm_device.h", "paper_2107_14774_amd/csrc/lbm_adjoint_step.h",
-                   "paper_2107_14774_amd/csrc/lbm_api.hip")
+                   "paper_2107_14774_amd/csrc/lbm_api.hip", "paper_2107_14774_amd/csrc/lbm_adjoint.hip")
 
 
 def log(*a):
@@ -373,6 +373,9 @@ PROFILE_KERNELS = {
     "aa_f16 (shifted)": "k_step_aa_pair<1, 2, true, false, false, true>",
     "adjoint_f32": "k_step_adjoint<0, 2, 1, false, false>", "adjoint_f32_hbm": "k_step_adjoint<0, 2, 1, false, false>",
     "adjoint_f16": "k_step_adjoint<1, 2, 0, false, false>",
+    # the adjoint of the full corrections: its step kernel and the stencil's transpose (the density pass
+    # is k_density, shared with the recomputed forward steps)
+    "adjoint_full (step)": "k_step_adjoint<0, 3, 1, false, false>", "adjoint_full (transpose)": "k_density_vjp",
     # the measured ceilings: streaming only (the FP32 step and the FP16 pair step without their
     # collisions) and the plain copy
     "stream_f32": "k_stream<0, 0>", "stream_f16": "k_stream_pair<1>", "copy": "k_copy16",
@@ -385,6 +388,8 @@ PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "aa_f32 (local)": (512, 512, 256, "512x512x256"), "aa_f32 (shifted)": (512, 512, 256, "512x512x256"),
     "aa_f16 (local)": (512, 512, 256, "512x512x256"), "aa_f16 (shifted)": (512, 512, 256, "512x512x256"),
     "adjoint_f16": (384, 384, 192, "384x384x192"), "adjoint_f32_hbm": (512, 512, 128, "512x512x128 duct"),
+    "adjoint_full (step)": (512, 512, 128, "512x512x128 duct"),
+    "adjoint_full (transpose)": (512, 512, 128, "512x512x128 duct"),
     "stream_f32": (512, 512, 256, "512x512x256"), "stream_f16": (512, 512, 256, "512x512x256"),
     "copy": (512, 512, 256, "one FP32 state"),
 }
@@ -427,6 +432,8 @@ def summarize_rocprof(out_dir):
             alg[v] = BYTES_PER_LUP[v.split()[0]]
     alg["stream_f32"] = BYTES_PER_LUP["f32"]
     alg["stream_f16"] = BYTES_PER_LUP["f16"]
+    alg["adjoint_full (step)"] = 108 + 108 + 108 + 12 + 24 + 4 + 12
+    alg["adjoint_full (transpose)"] = 12 + 108 + 108
     alg["copy"] = 2 * COPY_BYTES // (512 * 512 * 256)   # per node of the state copied
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",

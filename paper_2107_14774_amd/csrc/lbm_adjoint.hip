@@ -104,7 +104,8 @@ __global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ g
                                                      uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  int y, z;
+  tiled_row(rowid, (uint32_t)k.ytile, k, y, z);  // y-tiles, as the gradient's forward pass
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   const int t = (int)threadIdx.x;
   const bool active = x < k.nx;

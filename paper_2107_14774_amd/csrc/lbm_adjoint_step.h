@@ -353,7 +353,10 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
     const float* __restrict__ drho_src, float* __restrict__ grad_rho_out, Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
-  const int y = (int)(rowid % (uint32_t)k.ny), z = (int)(rowid / (uint32_t)k.ny);
+  // with the full corrections the rows run in y-tiles like the forward step's, so that the density
+  // rows of z - 1 and z + 1 that the gradient reads are still in L2
+  int y, z;
+  tiled_row(rowid, (uint32_t)(CORR == 3 ? k.ytile : 1), k, y, z);
   const int x = (int)(bxi * blockDim.x + threadIdx.x);
   float gfx = 0.0f, gfy = 0.0f, gfz = 0.0f;
   // full corrections: the node's density gradient from the density field of h(t), as the step
