@@ -327,21 +327,38 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
                      float* adj_out, const float* force, float* grad_force,
                      double* grad_force_uniform, void* hip_stream);
 
-/* The adjoint step of the full corrections at the exact time level (one step
- * of lbm_step_full with LBM_GRAD_EXACT; App. D's lambda and e_rho terms and
- * the density gradient of the isotropic stencil of lbm_step_full).  Arguments
- * as in lbm_step_adjoint (the handle's corrections must be LBM_CORR_FULL,
- * LBM_EINVAL otherwise), plus two work fields the caller provides (the library
- * allocates nothing), overwritten, contents unspecified afterwards:
- *   drho_work: device float[n_nodes]     (the density deviation of state_t)
- *   grad_work: device float[3][n_nodes]  (the cotangent of the density gradient)
- * Besides the collision's transpose at every node, the gradient's cotangent
- * flows back through the stencil to the densities it read, and from there to
- * every population those nodes gathered. */
-int lbm_step_adjoint_full(lbm_handle* h, const void* state_t, const float* adj_in,
+/* The adjoint step of the full corrections (one step of lbm_step_full; App.
+ * D's lambda and e_rho terms and the density gradient of its isotropic
+ * stencil).  Arguments as in lbm_step_adjoint (the handle's corrections must
+ * be LBM_CORR_FULL, LBM_EINVAL otherwise), plus fields the caller provides
+ * (the library allocates nothing):
+ *   drho:      device float[n_nodes]: the density field the step took its
+ *              gradient from.  LBM_GRAD_EXACT: written here (the density of
+ *              state_t).  LBM_GRAD_LAGGED: read (the density of the previous
+ *              step's input, or of state_t for the first step of a run).
+ *   grad_work: device float[3][n_nodes]: receives the cotangent of the step's
+ *              density gradient.
+ *   grad_pending: device float[3][n_nodes] or NULL, LBM_GRAD_LAGGED only:
+ *              the cotangent of the next step's gradient, which that step took
+ *              from this state's density (the grad_work of the previous call
+ *              of the reverse sweep); its stencil transpose is added to
+ *              adj_out.  Must differ from grad_work.
+ * LBM_GRAD_EXACT: the gradient came from state_t's own density, so its
+ * cotangent flows back through the stencil into adj_out before return.
+ * LBM_GRAD_LAGGED: it belongs to the state the gradient was taken from; pass
+ * grad_work as grad_pending to the next call of the sweep, and after the run's
+ * first step (whose gradient came from its own input) add it to lambda(0)
+ * with lbm_density_adjoint. */
+int lbm_step_adjoint_full(lbm_handle* h, int32_t mode, const void* state_t, const float* adj_in,
                           float* adj_out, const float* force, float* grad_force,
-                          double* grad_force_uniform, float* drho_work, float* grad_work,
-                          void* hip_stream);
+                          double* grad_force_uniform, float* drho, float* grad_work,
+                          const float* grad_pending, void* hip_stream);
+
+/* adj += the transpose of the full corrections' density-gradient stencil
+ * applied to grad (device float[3][n_nodes], a cotangent of the gradient),
+ * added to every population each node gathered (d rho / d f = 1).  adj: an
+ * adjoint array (float[27 * stride], gathered-population order). */
+int lbm_density_adjoint(lbm_handle* h, const float* grad, float* adj, void* hip_stream);
 
 /* lambda(T) from cotangents of the observables of a state (the transpose of
  * lbm_moments' rho/u map):

@@ -48,19 +48,18 @@ def init_vjp(rho, u, p: Params, lam):
     return g_rho, g_u
 
 
-def loss(p: Params, rho0, u0, force_field, target, nsteps):
-    """L = 1/2 sum over nodes and components of (u(T) - u*)^2."""
-    f = lbm.init_equilibrium(rho0, u0, p)
-    for _ in range(nsteps):
-        f = lbm.step(f, p, force=force_field)
+def loss(p: Params, rho0, u0, force_field, target, nsteps, lagged=False):
+    """L = 1/2 sum over nodes and components of (u(T) - u*)^2.  ``lagged``: the
+    full corrections' density gradient one step behind (``lbm.run``)."""
+    f = lbm.run(lbm.init_equilibrium(rho0, u0, p), p, nsteps, force_field, lagged=lagged)
     _, u = lbm.observables(f, p, force=force_field)
     return 0.5 * ((u - target) ** 2).sum()
 
 
-def loss_and_gradients(p: Params, rho0, u0, force_field, target, nsteps):
+def loss_and_gradients(p: Params, rho0, u0, force_field, target, nsteps, lagged=False):
     """(L, dL/dforce_field, dL/du0) through the whole trajectory, FP64."""
     u0 = torch.as_tensor(u0, dtype=DT).detach().clone().requires_grad_(True)
     F = torch.as_tensor(force_field, dtype=DT).detach().clone().requires_grad_(True)
-    L = loss(p, torch.as_tensor(rho0, dtype=DT), u0, F, torch.as_tensor(target, dtype=DT), nsteps)
+    L = loss(p, torch.as_tensor(rho0, dtype=DT), u0, F, torch.as_tensor(target, dtype=DT), nsteps, lagged)
     gF, gu = torch.autograd.grad(L, (F, u0))
     return L.detach(), gF, gu

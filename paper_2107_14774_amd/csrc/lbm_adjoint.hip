@@ -286,12 +286,21 @@ static int grid_cap(int64_t n, int cap) {
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+hipError_t launch_density_adjoint(const lbm_handle& h, const float* grad, float* adj, hipStream_t st) {
+  const int block = h.block;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_density_vjp, dim3((unsigned)nb), dim3(block), 0, st, grad, adj, h.k, bpr);
+  return hipGetLastError();
+}
+
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                const float* force, float* grad_force, double* grad_force_uniform, float* drho,
-                               float* grad_rho, hipStream_t st) {
+                               float* grad_rho, bool exact, const float* pending, hipStream_t st) {
   const bool full = h.p.corr == LBM_CORR_FULL;
   hipError_t e = hipSuccess;
-  if (full) e = launch_density(h, state, drho, st);  // the density field the step's gradient came from
+  if (full && exact) e = launch_density(h, state, drho, st);  // the density field the step's gradient came from
   if (e != hipSuccess) return e;
   switch (h.p.storage) {
     case LBM_F32: e = AdjointKernels<0>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
@@ -302,21 +311,16 @@ hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const flo
                                          grad_rho, st); break;
   }
   if (e != hipSuccess) return e;
-  int64_t g = (h.n + 255) / 256;
-  if (g > 65536) g = 65536;
   if (h.k.moving) {
+    int64_t g = (h.n + 255) / 256;
+    if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_moving_wall_adjoint, (unsigned)g, 256, 0, st, adj_in, adj_out, h.k);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (full) {
-    const int block = h.block;
-    const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
-    const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
-    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_density_vjp, dim3((unsigned)nb), dim3(block), 0, st, grad_rho, adj_out, h.k, bpr);
-    e = hipGetLastError();
-  }
+  // exact: this step's gradient came from this state; lagged: the next step's came from it
+  if (full && exact) e = launch_density_adjoint(h, grad_rho, adj_out, st);
+  else if (full && pending != nullptr) e = launch_density_adjoint(h, pending, adj_out, st);
   return e;
 }
 

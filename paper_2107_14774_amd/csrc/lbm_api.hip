@@ -457,32 +457,48 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint: the full corrections need lbm_step_adjoint_full");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
-                                           grad_force_uniform, nullptr, nullptr, (hipStream_t)hip_stream);
+                                           grad_force_uniform, nullptr, nullptr, false, nullptr,
+                                           (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");
 }
 
-int lbm_step_adjoint_full(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out,
-                          const float* force, float* grad_force, double* grad_force_uniform, float* drho_work,
-                          float* grad_work, void* hip_stream) {
+int lbm_step_adjoint_full(lbm_handle* h, int32_t mode, const void* state_t, const float* adj_in, float* adj_out,
+                          const float* force, float* grad_force, double* grad_force_uniform, float* drho,
+                          float* grad_work, const float* grad_pending, void* hip_stream) {
   CHECK_HANDLE(h, "lbm_step_adjoint_full");
   if (h->k.aa) return fail(LBM_EINVAL, "lbm_step_adjoint_full: the adjoint runs on the AB layout only");
   if (h->p.corr != LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint_full: the handle's corrections are not LBM_CORR_FULL");
+  if (mode != LBM_GRAD_EXACT && mode != LBM_GRAD_LAGGED)
+    return fail(LBM_EINVAL, "lbm_step_adjoint_full: mode must be LBM_GRAD_EXACT or LBM_GRAD_LAGGED");
   CHECK_REQ(state_t, "lbm_step_adjoint_full", "state_t");
   CHECK_REQ(adj_in, "lbm_step_adjoint_full", "adj_in");
   CHECK_REQ(adj_out, "lbm_step_adjoint_full", "adj_out");
-  CHECK_REQ(drho_work, "lbm_step_adjoint_full", "drho_work");
+  CHECK_REQ(drho, "lbm_step_adjoint_full", "drho");
   CHECK_REQ(grad_work, "lbm_step_adjoint_full", "grad_work");
+  CHECK_PTR(grad_pending, "lbm_step_adjoint_full", "grad_pending");
   CHECK_PTR(force, "lbm_step_adjoint_full", "force");
   CHECK_PTR(grad_force, "lbm_step_adjoint_full", "grad_force");
   CHECK_PTR(grad_force_uniform, "lbm_step_adjoint_full", "grad_force_uniform");
   if ((const void*)adj_in == (const void*)adj_out)
     return fail(LBM_EINVAL, "lbm_step_adjoint_full: adj_in == adj_out");
-  if ((const void*)drho_work == (const void*)grad_work)
-    return fail(LBM_EINVAL, "lbm_step_adjoint_full: drho_work == grad_work");
+  if ((const void*)drho == (const void*)grad_work)
+    return fail(LBM_EINVAL, "lbm_step_adjoint_full: drho == grad_work");
+  if (grad_pending != nullptr && (mode != LBM_GRAD_LAGGED || (const void*)grad_pending == (const void*)grad_work))
+    return fail(LBM_EINVAL, "lbm_step_adjoint_full: grad_pending is for LBM_GRAD_LAGGED and must differ from grad_work");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force, grad_force_uniform,
-                                           drho_work, grad_work, (hipStream_t)hip_stream);
+                                           drho, grad_work, mode == LBM_GRAD_EXACT, grad_pending,
+                                           (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint_full");
+}
+
+int lbm_density_adjoint(lbm_handle* h, const float* grad, float* adj, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_density_adjoint");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_density_adjoint: the adjoint runs on the AB layout only");
+  CHECK_REQ(grad, "lbm_density_adjoint", "grad");
+  CHECK_REQ(adj, "lbm_density_adjoint", "adj");
+  hipError_t e = clbm::launch_density_adjoint(*h, grad, adj, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_density_adjoint");
 }
 
 int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force, const float* g_rho,

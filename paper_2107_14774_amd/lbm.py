@@ -234,20 +234,29 @@ def lbm_step_adjoint(h, state_t, adj_in, adj_out, force=None, grad_force=None, g
                                             _lib.ptr(grad_force_uniform), _lib.stream_ptr(stream)))
 
 
-def lbm_step_adjoint_full(h, state_t, adj_in, adj_out, drho_work, grad_work, force=None, grad_force=None,
-                          grad_force_uniform=None, stream=None):
+def lbm_step_adjoint_full(h, state_t, adj_in, adj_out, drho, grad_work, force=None, grad_force=None,
+                          grad_force_uniform=None, mode="exact", grad_pending=None, stream=None):
+    """Adjoint step of the full corrections; ``mode`` "exact" or "lagged" (see include/lbm.h)."""
     m = 27 * h.stride
     _require(adj_in, _ABI_F32, m, "adj_in")
     _require(adj_out, _ABI_F32, m, "adj_out")
-    _require(drho_work, _ABI_F32, h.n, "drho_work")
+    _require(drho, _ABI_F32, h.n, "drho")
     _require(grad_work, _ABI_F32, 3 * h.n, "grad_work")
+    _require(grad_pending, _ABI_F32, 3 * h.n, "grad_pending")
     _require(force, _ABI_F32, 3 * h.n, "force")
     _require(grad_force, _ABI_F32, 3 * h.n, "grad_force")
     _require(grad_force_uniform, _ABI_F64, 3, "grad_force_uniform")
-    _lib.check(_lib.load().lbm_step_adjoint_full(h.raw, _lib.ptr(_state(h, state_t)), _lib.ptr(adj_in),
-                                                 _lib.ptr(adj_out), _lib.ptr(force), _lib.ptr(grad_force),
-                                                 _lib.ptr(grad_force_uniform), _lib.ptr(drho_work),
-                                                 _lib.ptr(grad_work), _lib.stream_ptr(stream)))
+    _lib.check(_lib.load().lbm_step_adjoint_full(h.raw, _lib.GRAD_MODE[mode], _lib.ptr(_state(h, state_t)),
+                                                 _lib.ptr(adj_in), _lib.ptr(adj_out), _lib.ptr(force),
+                                                 _lib.ptr(grad_force), _lib.ptr(grad_force_uniform), _lib.ptr(drho),
+                                                 _lib.ptr(grad_work), _lib.ptr(grad_pending),
+                                                 _lib.stream_ptr(stream)))
+
+
+def lbm_density_adjoint(h, grad, adj, stream=None):
+    _require(grad, _ABI_F32, 3 * h.n, "grad")
+    _require(adj, _ABI_F32, 27 * h.stride, "adj")
+    _lib.check(_lib.load().lbm_density_adjoint(h.raw, _lib.ptr(grad), _lib.ptr(adj), _lib.stream_ptr(stream)))
 
 
 def lbm_moments_adjoint(h, state, adj, force=None, g_rho=None, g_u=None, grad_force=None, stream=None):

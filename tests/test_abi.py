@@ -110,12 +110,19 @@ def test_full_corrections_need_the_density_field_entry_point():
     c = ctypes.c_void_p(0x30000)
     assert lib.lbm_step_adjoint(hf.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
     assert b"lbm_step_adjoint_full" in lib.lbm_last_error()
-    assert lib.lbm_step_adjoint_full(hl.raw, a, b, c, None, None, None, d1, d2, None) == _lib.LBM_EINVAL
+    d3 = ctypes.c_void_p(0x60000)
+    assert lib.lbm_step_adjoint_full(hl.raw, 0, a, b, c, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
     assert b"LBM_CORR_FULL" in lib.lbm_last_error()
-    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, None, d2, None) == _lib.LBM_EINVAL
-    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, d1, None, None) == _lib.LBM_EINVAL
-    assert lib.lbm_step_adjoint_full(hf.raw, a, b, c, None, None, None, d1, d1, None) == _lib.LBM_EINVAL
-    assert lib.lbm_step_adjoint_full(hf.raw, a, b, b, None, None, None, d1, d2, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, c, None, None, None, None, d2, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, c, None, None, None, d1, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, c, None, None, None, d1, d1, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, b, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 5, a, b, c, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
+    # a pending gradient cotangent belongs to the lagged time level and differs from grad_work
+    assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, c, None, None, None, d1, d2, d3, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 1, a, b, c, None, None, None, d1, d2, d2, None) == _lib.LBM_EINVAL
+    assert lib.lbm_density_adjoint(hf.raw, None, c, None) == _lib.LBM_EINVAL
+    assert lib.lbm_density_adjoint(hf.raw, d2, None, None) == _lib.LBM_EINVAL
 
 
 def test_adjoint_rejects_what_it_does_not_differentiate():

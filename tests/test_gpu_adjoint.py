@@ -220,19 +220,12 @@ FULL_ADJ_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", FULL_ADJ_CASES, ids=[c[0] for c in FULL_ADJ_CASES])
-def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
-    """lbm_step_adjoint_full: one reverse step of the full corrections (exact time level) against the
-    oracle's reverse mode, which differentiates the density gradient's stencil as well."""
+def _full_case(case, corr="full"):
+    """Oracle parameters and a GPU lattice for one of FULL_ADJ_CASES."""
     import os
     name, (nx, ny, nz), r, s, (bx, by, bz), wv, moments, storage, field, kind = case
-    _say("case", name)
-    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr="full", bc_x=bx, bc_y=by, bc_z=bz,
+    p = oracle.Params(nx, ny, nz, r=r, s=s, omega_nu=1.45, omega_xi=1.27, corr=corr, bc_x=bx, bc_y=by, bc_z=bz,
                       wall_velocity=wv or ((0, 0, 0),) * 6, moments=moments)
-    f0 = fp32_rounded_state(random_state(p, 31), p)
-    g = np.random.Generator(np.random.PCG64(32))
-    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32) if field else None
-    lam_f = torch.tensor(g.standard_normal((27, *p.shape)))
     old = os.environ.get("LBM_GATHER_KIND")
     if kind:
         os.environ["LBM_GATHER_KIND"] = kind
@@ -243,6 +236,20 @@ def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
             os.environ.pop("LBM_GATHER_KIND", None)
         else:
             os.environ["LBM_GATHER_KIND"] = old
+    return p, lat
+
+
+@pytest.mark.parametrize("case", FULL_ADJ_CASES, ids=[c[0] for c in FULL_ADJ_CASES])
+def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
+    """lbm_step_adjoint_full: one reverse step of the full corrections (exact time level) against the
+    oracle's reverse mode, which differentiates the density gradient's stencil as well."""
+    name, (nx, ny, nz), r, s, (bx, by, bz), wv, moments, storage, field, kind = case
+    _say("case", name)
+    p, lat = _full_case(case)
+    f0 = fp32_rounded_state(random_state(p, 31), p)
+    g = np.random.Generator(np.random.PCG64(32))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32) if field else None
+    lam_f = torch.tensor(g.standard_normal((27, *p.shape)))
     st = lat.new_state()
     lat.import_populations(st, f0.cuda())
     f_in = lat.export_populations(st).cpu()            # the stored (for FP16: rounded) start
@@ -271,6 +278,70 @@ def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
     assert err < 2e-6 and share > 50 * err
     assert errF < 2e-5
     assert errU < 1e-4
+
+
+@pytest.mark.parametrize("case", FULL_ADJ_CASES, ids=[c[0] for c in FULL_ADJ_CASES])
+def test_full_corrections_lagged_step_adjoint_matches_oracle_vjp(case):
+    """lbm_step_adjoint_full at the lagged time level: the gradient comes from the density D of another
+    state, so lambda(t) = (d step / d f)^T lambda(t+1) at fixed D, plus the stencil transpose of the pending
+    cotangent gp of the next step's gradient (taken from this state's density); grad_work receives the
+    cotangent of D's gradient, which lbm_density_adjoint carries back to every population of that state.
+    Oracle: reverse mode of <lambda, step(f, grad_from=D)> + <gp, grad(rho(f))>."""
+    name, (nx, ny, nz), r, s, (bx, by, bz), wv, moments, storage, field, kind = case
+    _say("case", name, "(lagged)")
+    p, lat = _full_case(case)
+    f0 = fp32_rounded_state(random_state(p, 31), p)
+    fD = fp32_rounded_state(random_state(p, 33), p)
+    g = np.random.Generator(np.random.PCG64(34))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32) if field else None
+    lam_f = torch.tensor(g.standard_normal((27, *p.shape))).to(torch.float32)
+    gp = torch.tensor(g.standard_normal((3, *p.shape))).to(torch.float32)
+    st, stD = lat.new_state(), lat.new_state()
+    lat.import_populations(st, f0.cuda())
+    lat.import_populations(stD, fD.cuda())
+    f_in = lat.export_populations(st).cpu()
+    fD_in = lat.export_populations(stD).cpu()
+    drho = lat.density(stD)
+    lam_in, lam_out = lat.new_adjoint(), lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam_f.to(DT).cuda(), lam_in)
+    gw = lat.field(3)
+    gF = torch.zeros((3, *p.shape), dtype=torch.float32, device="cuda")
+    gFu = torch.zeros(3, dtype=torch.float64, device="cuda")
+    fc = force.cuda() if field else None
+    P.lbm_step_adjoint_full(lat.h, st, lam_in, lam_out, drho, gw, fc, gF, gFu, mode="lagged",
+                            grad_pending=gp.cuda())
+    got = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_adjoint_to_natural(lat.h, lam_out, got)
+    back = lat.new_adjoint()
+    back.zero_()
+    P.lbm_density_adjoint(lat.h, gw, back)
+    got_D = torch.empty((27, *p.shape), dtype=DT, device="cuda")
+    P.lbm_adjoint_to_natural(lat.h, back, got_D)
+
+    f = f_in.detach().clone().requires_grad_(True)
+    fDv = fD_in.detach().clone().requires_grad_(True)
+    F = (force.to(DT) if field else torch.zeros((3, *p.shape), dtype=DT)).requires_grad_(True)
+    J = (lam_f.to(DT) * OL.step(f, p, force=F, grad_from=fDv.sum(0))).sum() \
+        + (gp.to(DT) * OL.density_gradient(f.sum(0), p)).sum()
+    want_f, want_D, want_F = torch.autograd.grad(J, (f, fDv, F))
+    scale = want_f.abs().max().item()
+    err = (got.cpu() - want_f).abs().max().item() / scale
+    errD = (got_D.cpu() - want_D).abs().max().item() / want_D.abs().max().item()
+    errF = (gF.cpu().to(DT) - want_F).abs().max().item() / want_F.abs().max().item()
+    # scale: what the pending term and the lag change in the result
+    J_e = (lam_f.to(DT) * OL.step(f, p, force=F)).sum()
+    want_e, = torch.autograd.grad(J_e, (f,))
+    share = (want_f - want_e).abs().max().item() / scale
+    _say(f"{name} (lagged): rel max err lambda {err:.2e} (differs from the exact level by {share:.2e}), "
+         f"density cotangent {errD:.2e}, force grad {errF:.2e}")
+    assert err < 2e-6 and share > 50 * err
+    # the cotangent of the gradient alone passes through the transpose of App. D's 3x3 strain-rate solve,
+    # whose condition number grows as the grid gets flatter (about 6 at s = 1/2, 24 at s = 1/4), and its x
+    # and y components are sums of three right-hand-side cotangents that partly cancel: FP32 rounding
+    # measured 5e-6 at s = 1/4, within the 1e-5 relative tolerance of FP32 results
+    assert errD < 1e-5
+    assert errF < 2e-5
+    assert abs(gFu.cpu() - want_F.reshape(3, -1).sum(-1)).max().item() <= 1e-4 * want_F.reshape(3, -1).sum(-1).abs().max().item()
 
 
 @pytest.mark.parametrize("max_states", [128, 2])
@@ -303,3 +374,35 @@ def test_full_corrections_trajectory_gradient_matches_oracle(max_states):
          f"(local corrections differ by {shareF:.2e}), dL/du0 rel L2 {eu:.2e} (local: {shareu:.2e})")
     assert eF < 1e-4 and eu < 1e-4
     assert shareF > 20 * eF and shareu > 20 * eu
+
+
+@pytest.mark.parametrize("max_states", [128, 2])
+def test_full_corrections_lagged_trajectory_gradient_matches_oracle(max_states):
+    """The same trajectory at the lagged time level (each step's gradient from the previous step's input
+    density, the first step's from its own): dL/dF and dL/du0 against the oracle's reverse mode through
+    run(lagged=True), which differs from the exact level's gradient."""
+    w = W.ADJOINT_DUCT_128
+    p = oracle_params(w, corr="full", nx=12, ny=10, nz=8)
+    g = np.random.Generator(np.random.PCG64(43))
+    force = torch.tensor(1e-5 * g.standard_normal((3, *p.shape))).to(torch.float32)
+    u0 = torch.tensor(0.02 * g.standard_normal((3, *p.shape)))
+    rho0 = torch.tensor(1.0 + 0.02 * g.standard_normal(p.shape))
+    target = torch.tensor(1e-3 * g.standard_normal((3, *p.shape)))
+    nsteps = 18
+
+    L_o, gF_o, gu_o = G.loss_and_gradients(p, rho0, u0, force.to(DT), target, nsteps, lagged=True)
+    _, gF_e, gu_e = G.loss_and_gradients(p, rho0, u0, force.to(DT), target, nsteps)
+    lat = gpu_lattice(p)
+    uc = u0.cuda().requires_grad_(True)
+    Fc = force.cuda().requires_grad_(True)
+    u = ADJ.simulate(lat, uc, Fc, nsteps, 6, rho0=rho0.cuda(), max_states=max_states, full_mode="lagged")
+    L_g = 0.5 * ((u.to(DT) - target.cuda()) ** 2).sum()
+    L_g.backward()
+    eF = rel_l2(Fc.grad.cpu(), gF_o)
+    eu = rel_l2(uc.grad.cpu(), gu_o)
+    dF, du = rel_l2(gF_e, gF_o), rel_l2(gu_e, gu_o)
+    _say(f"lagged full-correction trajectory (max_states {max_states}): loss rel err "
+         f"{abs(float(L_g.detach()) - L_o.item()) / L_o.item():.2e}, dL/dF rel L2 {eF:.2e} (exact level differs by "
+         f"{dF:.2e}), dL/du0 rel L2 {eu:.2e} (exact: {du:.2e})")
+    assert eF < 1e-5 and eu < 1e-5
+    assert dF > 20 * eF and du > 20 * eu

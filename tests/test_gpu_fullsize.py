@@ -349,8 +349,11 @@ def test_fp16_workload_gradient_1000_steps_against_oracle():
 
 
 # (gradient, loss) bounds of the 1000-step replica gradient against the oracle, about twice the
-# measured errors (f32 3.4e-5 / 2.4e-10, f16 2.3e-4 / 1.7e-6, bf16 1.9e-2 / 1.4e-4, bf16_sr 1.2e-3 / 5.2e-5)
-GRAD_BOUND = {"f32": (7e-5, 1e-9), "f16": (5e-4, 4e-6), "bf16": (4e-2, 3e-4), "bf16_sr": (2.5e-3, 1.2e-4)}
+# measured errors (f32 3.4e-5 / 2.4e-10, f16 2.3e-4 / 1.7e-6, bf16 2.0e-2 / 1.8e-4, bf16_sr 1.2e-3 / 5.2e-5).
+# The loss error of 16-bit storage is the projection of the storage's velocity error on u - u*, whose sign and
+# size follow the rounding pattern: FP16 measured 1.7e-6, and 1.1e-5 with collision arithmetic that differed
+# only in the last bit of one coefficient (both far inside 2 |du| / |u - u*|), so its bound allows for that
+GRAD_BOUND = {"f32": (7e-5, 1e-9), "f16": (5e-4, 3e-5), "bf16": (4e-2, 4e-4), "bf16_sr": (2.5e-3, 1.2e-4)}
 
 
 ADJ_FULL_CASES = [
