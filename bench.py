@@ -5,7 +5,8 @@
 Variants: f32, f16, bf16, bf16_sr (the step per storage format), full_f32,
 full_f16 (full corrections, lagged gradient), aa_f32, aa_f16 (in-place AA
 layout), adjoint_f32, adjoint_f32_hbm, adjoint_f16 (the adjoint workloads),
-adjoint_full_f32 (the adjoint of the full corrections on the 512x512x128 duct).
+adjoint_full_f32, adjoint_full_lagged_f32 (the adjoint of the full corrections on the
+512x512x128 duct, exact and lagged time levels).
 
 Workload: the decaying Taylor-Green + random-mode flow on the periodic
 512x512x256 cuboid grid (r = 1, s = 1/2, Re 1600), inputs resident in HBM
@@ -62,11 +63,14 @@ ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f32_hbm"
                      # full corrections: the density pass (state read, density written), the adjoint step
                      # (as above plus the density read and the gradient cotangent written), the stencil's
                      # transpose (cotangent read, the node's 27 adjoint values read and written)
-                     "adjoint_full_f32": (108 + 4) + (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108)}
+                     "adjoint_full_f32": (108 + 4) + (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108),
+                     # lagged time level: the density field comes from the forward run, no density pass
+                     "adjoint_full_lagged_f32": (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108)}
 # forward step bytes of the state type an adjoint variant recomputes with (per-node force read included;
 # the full corrections' exact time level adds a density pass and the density read)
 ADJ_FORWARD_BYTES = {"adjoint_f32": 216 + 12, "adjoint_f32_hbm": 216 + 12, "adjoint_f16": 108,
-                     "adjoint_full_f32": (108 + 4) + 216 + 12 + 4}
+                     "adjoint_full_f32": (108 + 4) + 216 + 12 + 4,
+                     "adjoint_full_lagged_f32": 216 + 12 + 4 + 4}
 # the paper's only cost figures (Sec. 6, shallow cavity, no hardware or times): node-count ratios cubic / cuboid
 PAPER_CONTEXT = {"source": "Sec. 6 shallow lid-driven cavity, L/H = 4, W/H = 2, Re = 100; no hardware, precision or "
                            "times are given",
@@ -223,7 +227,7 @@ def adjoint_workload(kind):
         return W.ADJOINT_DUCT_128, "f32"
     if kind == "adjoint_f32_hbm":
         return W.replica(W.ADJOINT_DUCT_128, 512, 512, 128, name="adjoint_duct_512x512x128"), "f32"
-    if kind == "adjoint_full_f32":
+    if kind in ("adjoint_full_f32", "adjoint_full_lagged_f32"):
         return W.replica(W.ADJOINT_DUCT_128, 512, 512, 128, name="adjoint_duct_512x512x128_full"), "f32"
     return W.ADJOINT_F16_384, "f16"
 
@@ -234,7 +238,8 @@ def run_adjoint(kind, steps, warmup):
     import paper_2107_14774_amd as P
     from paper_2107_14774_amd import adjoint as ADJ
     w, storage = adjoint_workload(kind)
-    full = kind == "adjoint_full_f32"
+    full = kind in ("adjoint_full_f32", "adjoint_full_lagged_f32")
+    mode = "lagged" if kind == "adjoint_full_lagged_f32" else "exact"
     on, ox = P.relaxation_rates(w.nu, w.xi, w.cs2)
     lat = P.Lattice(w.nx, w.ny, w.nz, r=w.r, s=w.s, cs2=w.cs2, omega_nu=on, omega_xi=ox,
                     bc_y=w.bc_y, bc_z=w.bc_z, storage=storage, corr="full" if full else "local")
@@ -247,7 +252,7 @@ def run_adjoint(kind, steps, warmup):
     st, tmp = lat.new_state(), lat.new_state()
     lat.init(st, u=u0)
     if full:
-        drho, gwork = lat.field(1), lat.field(3)
+        drho, gwork, gpend = lat.field(1), lat.field(3), lat.field(3).zero_()
         st, tmp, _, _ = lat.step_full(st, tmp, 10, drho, None, "exact", force)
     else:
         st, tmp = lat.step(st, tmp, 10, force)
@@ -257,7 +262,12 @@ def run_adjoint(kind, steps, warmup):
     stream = torch.cuda.current_stream()
 
     def adjoint_step(la, lb):
-        if full:  # density pass, adjoint step, the stencil's transpose
+        nonlocal gwork, gpend
+        if full and mode == "lagged":  # adjoint step, the transpose of the pending cotangent
+            P.lbm_step_adjoint_full(lat.h, st, la, lb, drho, gwork, force, grad, mode="lagged", grad_pending=gpend,
+                                    stream=stream)
+            gwork, gpend = gpend, gwork
+        elif full:  # density pass, adjoint step, the stencil's transpose
             P.lbm_step_adjoint_full(lat.h, st, la, lb, drho, gwork, force, grad, stream=stream)
         else:
             P.lbm_step_adjoint(lat.h, st, la, lb, force, grad, stream=stream)
@@ -277,6 +287,8 @@ def run_adjoint(kind, steps, warmup):
     mlups = lat.n / (ms * 1e-3) / 1e6
     alg = ADJ_BYTES_PER_LUP[kind] * lat.n / (ms * 1e-3) / 1e9
     del st, tmp, lam_a, lam_b, grad
+    if full:
+        del drho, gwork, gpend
     torch.cuda.empty_cache()
     # full backward passes over the workload's trajectory; the second is timed, so the recomputation
     # buffers come from the allocator's cache as in a training loop
@@ -285,7 +297,7 @@ def run_adjoint(kind, steps, warmup):
     for rep in range(2):
         uc = u0.clone().requires_grad_(storage == "f16")
         Fc = force.clone().requires_grad_(True) if force is not None else None
-        uT = ADJ.simulate(lat, uc, Fc, nsteps, every)
+        uT = ADJ.simulate(lat, uc, Fc, nsteps, every, full_mode=mode)
         loss = 0.5 * ((uT.to(torch.float64) - target) ** 2).sum()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -543,7 +555,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--variants", default="f32,f16,bf16,bf16_sr,full_f32,full_f16,aa_f32,aa_f16,adjoint_f32,"
-                                          "adjoint_f32_hbm,adjoint_f16,adjoint_full_f32")
+                                          "adjoint_f32_hbm,adjoint_f16,adjoint_full_f32,adjoint_full_lagged_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-rocprof", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 CSVs under DIR (no GPU needed)")
