@@ -64,8 +64,10 @@ ADJ_BYTES_PER_LUP = {"adjoint_f32": 108 + 108 + 108 + 12 + 24, "adjoint_f32_hbm"
                      # (as above plus the density read and the gradient cotangent written), the stencil's
                      # transpose (cotangent read, the node's 27 adjoint values read and written)
                      "adjoint_full_f32": (108 + 4) + (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108),
-                     # lagged time level: the density field comes from the forward run, no density pass
-                     "adjoint_full_lagged_f32": (108 + 108 + 108 + 12 + 24 + 4 + 12) + (12 + 108 + 108)}
+                     # lagged time level: the density field comes from the forward run (no density pass),
+                     # and the transpose of the previous call's cotangent is one value per node (cotangent
+                     # read, value written) that the adjoint step reads and adds to the node's outputs
+                     "adjoint_full_lagged_f32": (12 + 4) + (108 + 108 + 108 + 12 + 24 + 4 + 12 + 4)}
 # forward step bytes of the state type an adjoint variant recomputes with (per-node force read included;
 # the full corrections' exact time level adds a density pass and the density read)
 ADJ_FORWARD_BYTES = {"adjoint_f32": 216 + 12, "adjoint_f32_hbm": 216 + 12, "adjoint_f16": 108,
@@ -385,9 +387,11 @@ PROFILE_KERNELS = {
     "aa_f16 (shifted)": "k_step_aa_pair<1, 2, true, false, false, true>",
     "adjoint_f32": "k_step_adjoint<0, 2, 1, false, false>", "adjoint_f32_hbm": "k_step_adjoint<0, 2, 1, false, false>",
     "adjoint_f16": "k_step_adjoint<1, 2, 0, false, false>",
-    # the adjoint of the full corrections: its step kernel and the stencil's transpose (the density pass
-    # is k_density, shared with the recomputed forward steps)
-    "adjoint_full (step)": "k_step_adjoint<0, 3, 1, false, false>", "adjoint_full (transpose)": "k_density_vjp",
+    # the adjoint of the full corrections: its step kernel and the stencil's transpose added to the 27
+    # adjoint values of every node (exact time level), or written as one value per node that the next
+    # adjoint step adds (lagged); the density pass is k_density, shared with the recomputed forward steps
+    "adjoint_full (step)": "k_step_adjoint<0, 3, 1, false, false>",
+    "adjoint_full (transpose)": "k_density_vjp<false>", "adjoint_full (lagged transpose)": "k_density_vjp<true>",
     # the measured ceilings: streaming only (the FP32 step and the FP16 pair step without their
     # collisions) and the plain copy
     "stream_f32": "k_stream<0, 0>", "stream_f16": "k_stream_pair<1>", "copy": "k_copy16",
@@ -402,6 +406,7 @@ PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "adjoint_f16": (384, 384, 192, "384x384x192"), "adjoint_f32_hbm": (512, 512, 128, "512x512x128 duct"),
     "adjoint_full (step)": (512, 512, 128, "512x512x128 duct"),
     "adjoint_full (transpose)": (512, 512, 128, "512x512x128 duct"),
+    "adjoint_full (lagged transpose)": (512, 512, 128, "512x512x128 duct"),
     "stream_f32": (512, 512, 256, "512x512x256"), "stream_f16": (512, 512, 256, "512x512x256"),
     "copy": (512, 512, 256, "one FP32 state"),
 }
@@ -446,6 +451,7 @@ def summarize_rocprof(out_dir):
     alg["stream_f16"] = BYTES_PER_LUP["f16"]
     alg["adjoint_full (step)"] = 108 + 108 + 108 + 12 + 24 + 4 + 12
     alg["adjoint_full (transpose)"] = 12 + 108 + 108
+    alg["adjoint_full (lagged transpose)"] = 12 + 4
     alg["copy"] = 2 * COPY_BYTES // (512 * 512 * 256)   # per node of the state copied
     trace = list(csv.DictReader(open(os.path.join(out_dir, "prof_step", "step_kernel_trace.csv"))))
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",

@@ -337,7 +337,8 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
  *              state_t).  LBM_GRAD_LAGGED: read (the density of the previous
  *              step's input, or of state_t for the first step of a run).
  *   grad_work: device float[3][n_nodes]: receives the cotangent of the step's
- *              density gradient.
+ *              density gradient (LBM_GRAD_LAGGED also stages the transpose of
+ *              grad_pending in it during the call).
  *   grad_pending: device float[3][n_nodes] or NULL, LBM_GRAD_LAGGED only:
  *              the cotangent of the next step's gradient, which that step took
  *              from this state's density (the grad_work of the previous call

@@ -51,15 +51,7 @@ __global__ __launch_bounds__(256) void k_moving_wall_adjoint(const float* __rest
 // gathered gains g_rho(y) = sum_a sum_{x : nb(x, a) = y} c_a . gg(x), gg the
 // cotangent of the gradient that k_step_adjoint wrote.  Per axis the sources of
 // y are y - e (periodic: wrapped), plus y itself at a wall the shift points out of.
-__device__ __forceinline__ int stencil_sources(int v, int e, int n, bool wall, int (&out)[2]) {
-  if (e == 0) { out[0] = v; return 1; }
-  if (!wall) { out[0] = (v - e + n) % n; return 1; }
-  int c = 0;
-  if (v - e >= 0 && v - e < n) out[c++] = v - e;
-  if ((e < 0 && v == 0) || (e > 0 && v == n - 1)) out[c++] = v;
-  return c;
-}
-
+//
 // The stencil's coefficients factorise like the forward's (density_gradient_block):
 //   c_a = (0.5 ex Wy Wz, 0.5 ic_y ey Wx Wz, 0.5 ic_z ez Wx Wy),
 // so each thread reduces the transverse (y, z) sources of its own column X into
@@ -67,28 +59,71 @@ __device__ __forceinline__ int stencil_sources(int v, int e, int n, bool wall, i
 // (the sources of the block's row), and the x shift combines neighbouring
 // columns through LDS: g_rho(x) = sum_ex [0.5 ex A + 0.5 (ic_y B + ic_z C) Wx(ex)](X)
 // over the x sources X of each ex.
-__device__ __forceinline__ void transverse_column(const float* __restrict__ gg, int X, int y, int z,
+//
+// Grouped by source row, the transverse sums read the rows at offsets -1, 0, +1 in y and in z
+// with per-axis weights (the sum of W(e), resp. of e, over the shifts e whose source is that row):
+// nine rows of each component, all known to the whole block (one row per block).
+struct AxisWeights {
+  int row[3];       // source row at offset o = -1, 0, +1 (wrapped, or clamped where its weight is 0)
+  float w[3], e[3];
+};
+
+__device__ __forceinline__ AxisWeights axis_weights(int v, int n, bool wall, float wc, float ws) {
+  AxisWeights a;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    a.w[i] = 0.0f;
+    a.e[i] = 0.0f;
+    int r = v + i - 1;
+    if (wall) r = r < 0 ? 0 : (r >= n ? n - 1 : r);
+    else r = r < 0 ? r + n : (r >= n ? r - n : r);
+    a.row[i] = r;
+  }
+#pragma unroll
+  for (int e = -1; e <= 1; ++e) {
+    const float w = e == 0 ? wc : ws;
+    const int p = v - e;  // the source the shift e reads from (offset -e)
+    if (!wall || (p >= 0 && p < n)) { a.w[1 - e] += w; a.e[1 - e] += (float)e; }
+    if (wall && e != 0 && ((e < 0 && v == 0) || (e > 0 && v == n - 1))) { a.w[1] += w; a.e[1] += (float)e; }
+  }
+  return a;
+}
+
+struct TransverseWeights {
+  int64_t base[3][3];            // element index of source row (z offset, y offset), x = 0
+  float a[3][3], b[3][3], c[3][3];
+};
+
+__device__ __forceinline__ TransverseWeights transverse_weights(int y, int z, const Consts& k) {
+  const AxisWeights ay = axis_weights(y, k.ny, k.bb_y, k.w0c[1], k.w0s[1]);
+  const AxisWeights az = axis_weights(z, k.nz, k.bb_z, k.w0c[2], k.w0s[2]);
+  TransverseWeights t;
+#pragma unroll
+  for (int iz = 0; iz < 3; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy) {
+      t.base[iz][iy] = ((int64_t)az.row[iz] * k.ny + ay.row[iy]) * k.nx;
+      t.a[iz][iy] = az.w[iz] * ay.w[iy];
+      t.b[iz][iy] = az.w[iz] * ay.e[iy];
+      t.c[iz][iy] = az.e[iz] * ay.w[iy];
+    }
+  return t;
+}
+
+__device__ __forceinline__ void transverse_column(const float* __restrict__ gg, int X, const TransverseWeights& t,
                                                   const Consts& k, float& A, float& B, float& C) {
   A = 0.0f; B = 0.0f; C = 0.0f;
 #pragma unroll
-  for (int ez = -1; ez <= 1; ++ez) {
-    int sz[2];
-    const int cz = stencil_sources(z, ez, k.nz, k.bb_z, sz);
-    const float wz = ez == 0 ? k.w0c[2] : k.w0s[2];
+  for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
-    for (int ey = -1; ey <= 1; ++ey) {
-      int sy[2];
-      const int cy = stencil_sources(y, ey, k.ny, k.bb_y, sy);
-      const float wy = ey == 0 ? k.w0c[1] : k.w0s[1];
-      for (int iz = 0; iz < cz; ++iz)
-        for (int iy = 0; iy < cy; ++iy) {
-          const int64_t src = ((int64_t)sz[iz] * k.ny + sy[iy]) * k.nx + X;
-          A += wy * wz * gg[src];
-          if (ey != 0) B += (float)ey * wz * gg[k.n + src];
-          if (ez != 0) C += wy * (float)ez * gg[2 * k.n + src];
-        }
+    for (int iy = 0; iy < 3; ++iy) {
+      // every row index is valid (clamped where the weight is 0), so all 27 loads issue together
+      const int64_t src = t.base[iz][iy] + X;
+      const float g0 = gg[src], g1 = gg[k.n + src], g2 = gg[2 * k.n + src];
+      A += t.a[iz][iy] * g0;
+      B += t.b[iz][iy] * g1;
+      C += t.c[iz][iy] * g2;
     }
-  }
 }
 
 // v added to the node's 27 own elements (row start, chunk, x offset)
@@ -100,7 +135,10 @@ __device__ __forceinline__ void add_own_row(float* __restrict__ row, uint32_t xo
 }
 
 // One block per row segment (like the step); every thread of the block calls the barrier.
-__global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ gg, float* __restrict__ adj, Consts k,
+// FIELD: write the node's sum to out[node] (natural node order) instead of adding it to the node's
+// 27 own adjoint elements.
+template <bool FIELD>
+__global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ gg, float* __restrict__ out, Consts k,
                                                      uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
@@ -111,16 +149,17 @@ __global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ g
   const bool active = x < k.nx;
   // lds[c][t + 1]: column x of the block; [0] and [blockDim + 1]: the columns left and right of it
   __shared__ float lds[3][258];
+  const TransverseWeights tw = transverse_weights(y, z, k);
   if (active) {
     float A, B, C;
-    transverse_column(gg, x, y, z, k, A, B, C);
+    transverse_column(gg, x, tw, k, A, B, C);
     lds[0][t + 1] = A; lds[1][t + 1] = B; lds[2][t + 1] = C;
     if (t == 0 && x > 0) {
-      transverse_column(gg, x - 1, y, z, k, A, B, C);
+      transverse_column(gg, x - 1, tw, k, A, B, C);
       lds[0][0] = A; lds[1][0] = B; lds[2][0] = C;
     }
     if ((t == (int)blockDim.x - 1 || x == k.nx - 1) && x < k.nx - 1) {
-      transverse_column(gg, x + 1, y, z, k, A, B, C);
+      transverse_column(gg, x + 1, tw, k, A, B, C);
       lds[0][t + 2] = A; lds[1][t + 2] = B; lds[2][t + 2] = C;
     }
   }
@@ -129,9 +168,9 @@ __global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ g
   // the row's ends: a periodic x wraps to the other end of the row, which another block holds
   float Am, Bm, Cm, Ap, Bp, Cp;
   if (x > 0) { Am = lds[0][t]; Bm = lds[1][t]; Cm = lds[2][t]; }
-  else transverse_column(gg, k.nx - 1, y, z, k, Am, Bm, Cm);
+  else transverse_column(gg, k.nx - 1, tw, k, Am, Bm, Cm);
   if (x < k.nx - 1) { Ap = lds[0][t + 2]; Bp = lds[1][t + 2]; Cp = lds[2][t + 2]; }
-  else transverse_column(gg, 0, y, z, k, Ap, Bp, Cp);
+  else transverse_column(gg, 0, tw, k, Ap, Bp, Cp);
   const float A0 = lds[0][t + 1], B0 = lds[1][t + 1], C0 = lds[2][t + 1];
   const float hy = 0.5f * k.ic[1], hz = 0.5f * k.ic[2];
   const float wc = k.w0c[0], ws = k.w0s[0];
@@ -145,7 +184,8 @@ __global__ __launch_bounds__(256) void k_density_vjp(const float* __restrict__ g
   if (has_p) g += -0.5f * Ap + ws * (hy * Bp + hz * Cp);
   if (wx && x == k.nx - 1) g += 0.5f * A0 + ws * (hy * B0 + hz * C0);
   if (wx && x == 0) g += -0.5f * A0 + ws * (hy * B0 + hz * C0);
-  add_own_row(adj + row_start(y, z, k), xoff((uint32_t)x), g);
+  if constexpr (FIELD) st_off(out + ((int64_t)z * k.ny + y) * k.nx, (uint32_t)x, g);
+  else add_own_row(out + row_start(y, z, k), xoff((uint32_t)x), g);
 }
 
 // ------------------------------------------------------------------ observables adjoint
@@ -286,13 +326,20 @@ static int grid_cap(int64_t n, int cap) {
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-hipError_t launch_density_adjoint(const lbm_handle& h, const float* grad, float* adj, hipStream_t st) {
+// The stencil's transpose of a gradient cotangent: added to every own element of an adjoint array
+// (field = false), or written as one value per node into out[n] (field = true).
+static hipError_t launch_density_vjp(const lbm_handle& h, const float* grad, float* out, bool field, hipStream_t st) {
   const int block = h.block;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
   const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
   if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_density_vjp, dim3((unsigned)nb), dim3(block), 0, st, grad, adj, h.k, bpr);
+  if (field) hipLaunchKernelGGL(k_density_vjp<true>, dim3((unsigned)nb), dim3(block), 0, st, grad, out, h.k, bpr);
+  else hipLaunchKernelGGL(k_density_vjp<false>, dim3((unsigned)nb), dim3(block), 0, st, grad, out, h.k, bpr);
   return hipGetLastError();
+}
+
+hipError_t launch_density_adjoint(const lbm_handle& h, const float* grad, float* adj, hipStream_t st) {
+  return launch_density_vjp(h, grad, adj, false, st);
 }
 
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
@@ -302,13 +349,20 @@ hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const flo
   hipError_t e = hipSuccess;
   if (full && exact) e = launch_density(h, state, drho, st);  // the density field the step's gradient came from
   if (e != hipSuccess) return e;
+  // lagged: the next step took its gradient from this state's density, so the stencil's transpose of
+  // its cotangent (pending) belongs to every population of this state.  It goes, one value per node,
+  // into the first component of grad_rho, which the adjoint kernel reads before it writes the element
+  // and adds to the node's own outputs (instead of a pass over the 27 outputs afterwards).
+  const bool pend = full && !exact && pending != nullptr;
+  if (pend) e = launch_density_vjp(h, pending, grad_rho, true, st);
+  if (e != hipSuccess) return e;
   switch (h.p.storage) {
     case LBM_F32: e = AdjointKernels<0>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
-                                              grad_rho, st); break;
+                                              grad_rho, pend, st); break;
     case LBM_F16: e = AdjointKernels<1>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
-                                              grad_rho, st); break;
+                                              grad_rho, pend, st); break;
     default: e = AdjointKernels<2>::step(h, state, adj_in, adj_out, force, grad_force, grad_force_uniform, drho,
-                                         grad_rho, st); break;
+                                         grad_rho, pend, st); break;
   }
   if (e != hipSuccess) return e;
   if (h.k.moving) {
@@ -318,9 +372,8 @@ hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const flo
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  // exact: this step's gradient came from this state; lagged: the next step's came from it
+  // exact: this step's gradient came from this state
   if (full && exact) e = launch_density_adjoint(h, grad_rho, adj_out, st);
-  else if (full && pending != nullptr) e = launch_density_adjoint(h, pending, adj_out, st);
   return e;
 }
 

@@ -350,7 +350,7 @@ template <int ST, int CORR, int WALLS, bool RAW, bool HI>
 __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ_WAVES_16)) void k_step_adjoint(
     const typename Store<ST>::T* __restrict__ state, const float* __restrict__ lin, float* __restrict__ lout,
     const float* __restrict__ force, float* __restrict__ grad_force, double* __restrict__ grad_uniform,
-    const float* __restrict__ drho_src, float* __restrict__ grad_rho_out, Consts k, uint32_t bpr) {
+    const float* __restrict__ drho_src, float* __restrict__ grad_rho_out, int pend, Consts k, uint32_t bpr) {
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t bxi = lb % bpr, rowid = lb / bpr;
   // with the full corrections the rows run in y-tiles like the forward step's, so that the density
@@ -394,8 +394,22 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
       fy = ld_off(f + k.n, (uint32_t)x);
       fz = ld_off(f + 2 * k.n, (uint32_t)x);
     }
+    // pend (full corrections, lagged time level): the first component of grad_rho_out holds on entry
+    // the node's share of the previous call's gradient cotangent, sent back through the stencil; it
+    // belongs to every population the node gathered, so it joins the node's own outputs here (read
+    // before the same element is overwritten below)
+    float sp = 0.0f;
+    if constexpr (CORR == 3) {
+      if (pend) sp = ld_off(grad_rho_out + nrow, (uint32_t)x);
+    }
     float bgrad[3];
     collide_vjp<CORR, RAW, HI>(df, fx, fy, fz, k, lam, mu, gfx, gfy, gfz, grx, gry, grz, bgrad);
+    if constexpr (CORR == 3) {
+      if (pend) {
+#pragma unroll
+        for (int a = 0; a < 27; ++a) mu[a] += sp;
+      }
+    }
     store_own_adj(own_groups(lout, u), store_offset(u.xo[1]), mu);
     if constexpr (CORR == 3) {  // the cotangent of the node's density gradient, for k_density_vjp
       float* go = grad_rho_out + nrow;
@@ -428,7 +442,7 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
 template <int ST, bool HI>
 static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                         const float* force, float* grad_force, double* grad_uniform,
-                                        const float* drho, float* grad_rho, hipStream_t st) {
+                                        const float* drho, float* grad_rho, bool pend, hipStream_t st) {
   using T = typename Store<ST>::T;
   const int block = h.block;
   const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
@@ -443,7 +457,7 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
   const dim3 grid((unsigned)nb), blk(block);
 #define CLBM_ADJ(C, W, R)                                                                              \
   hipLaunchKernelGGL((k_step_adjoint<ST, C, W, R, HI>), grid, blk, 0, st, s, adj_in, adj_out, force, grad_force, \
-                     grad_uniform, drho, grad_rho, h.k, bpr)
+                     grad_uniform, drho, grad_rho, pend ? 1 : 0, h.k, bpr)
 #define CLBM_ADJ_CORR(W, R)                  \
   switch (h.p.corr) {                        \
     case 0: CLBM_ADJ(0, W, R); break;        \
@@ -467,11 +481,11 @@ static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, 
 template <int ST>
 hipError_t AdjointKernels<ST>::step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                     const float* force, float* grad_force, double* grad_uniform, const float* drho,
-                                    float* grad_rho, hipStream_t st) {
+                                    float* grad_rho, bool pend, hipStream_t st) {
   return h.k.hi ? launch_step_adjoint_t<ST, true>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, drho,
-                                                  grad_rho, st)
+                                                  grad_rho, pend, st)
                 : launch_step_adjoint_t<ST, false>(h, state, adj_in, adj_out, force, grad_force, grad_uniform, drho,
-                                                   grad_rho, st);
+                                                   grad_rho, pend, st);
 }
 
 }  // namespace clbm

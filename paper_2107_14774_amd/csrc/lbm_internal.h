@@ -47,10 +47,11 @@ extern template struct StepKernels<3>;
 template <int ST>
 struct AdjointKernels {
   // drho, grad_rho: the full corrections' density field of the state and the field that receives
-  // the cotangent of its gradient (NULL otherwise)
+  // the cotangent of its gradient (NULL otherwise); pend: grad_rho's first component holds on entry a
+  // per-node value to add to each of the node's 27 outputs
   static hipError_t step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                          const float* force, float* grad_force, double* grad_uniform, const float* drho,
-                         float* grad_rho, hipStream_t st);
+                         float* grad_rho, bool pend, hipStream_t st);
 };
 extern template struct AdjointKernels<0>;
 extern template struct AdjointKernels<1>;
