@@ -117,9 +117,10 @@ __device__ __forceinline__ void transverse_column(const float* __restrict__ gg, 
   for (int iz = 0; iz < 3; ++iz)
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy) {
-      // every row index is valid (clamped where the weight is 0), so all 27 loads issue together
-      const int64_t src = t.base[iz][iy] + X;
-      const float g0 = gg[src], g1 = gg[k.n + src], g2 = gg[2 * k.n + src];
+      // every row index is valid (clamped where the weight is 0), so all 27 loads issue together;
+      // uniform row pointers and one 32-bit x offset (SGPR base + VGPR offset addressing)
+      const float* r0 = gg + t.base[iz][iy];
+      const float g0 = ld_off(r0, (uint32_t)X), g1 = ld_off(r0 + k.n, (uint32_t)X), g2 = ld_off(r0 + 2 * k.n, (uint32_t)X);
       A += t.a[iz][iy] * g0;
       B += t.b[iz][iy] * g1;
       C += t.c[iz][iy] * g2;
