@@ -308,10 +308,15 @@ def run_adjoint(kind, steps, warmup):
         bwd = time.perf_counter() - t0
         del uT, loss, uc, Fc
     # algorithmic bytes of the backward: every adjoint step, plus the forward steps that recompute each
-    # checkpoint segment (all but its first state)
+    # checkpoint segment (all but its first state); at the exact level of the full corrections the
+    # recomputed steps leave each state's density behind, so only the adjoint step of a segment's last
+    # state runs the density pass (112 B/LUP)
     nseg = -(-nsteps // every)
     recomputed = nsteps - nseg
-    bwd_bytes = (ADJ_BYTES_PER_LUP[kind] * nsteps + ADJ_FORWARD_BYTES[kind] * recomputed) * lat.n
+    adj_bytes = ADJ_BYTES_PER_LUP[kind] * nsteps
+    if kind == "adjoint_full_f32":
+        adj_bytes -= (108 + 4) * (nsteps - nseg)
+    bwd_bytes = (adj_bytes + ADJ_FORWARD_BYTES[kind] * recomputed) * lat.n
     bwd_gbs = bwd_bytes / bwd / 1e9
     log(f"[bench] {kind}: {w.nx}x{w.ny}x{w.nz} {storage}: adjoint step {ms:.3f} ms, {mlups:.0f} MLUPS, "
         f"{alg:.0f} GB/s algorithmic; backward of {nsteps} steps (checkpoint {every}) {bwd:.3f} s "

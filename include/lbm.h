@@ -114,7 +114,7 @@ enum lbm_moments_basis { LBM_CENTRAL = 0, LBM_RAW = 1 };
 enum lbm_layout { LBM_LAYOUT_AB = 0, LBM_LAYOUT_AA = 1 };
 
 /* Time level of the density gradient of the full corrections (lbm_step_full). */
-enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1 };
+enum lbm_grad_mode { LBM_GRAD_EXACT = 0, LBM_GRAD_LAGGED = 1, LBM_GRAD_EXACT_DRHO = 2 };
 
 /* Walls.  On a bounce-back axis the walls sit half a cell outside the first
  * and last node.  A population whose upstream node lies beyond a wall is the
@@ -334,8 +334,12 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
  * (the library allocates nothing):
  *   drho:      device float[n_nodes]: the density field the step took its
  *              gradient from.  LBM_GRAD_EXACT: written here (the density of
- *              state_t).  LBM_GRAD_LAGGED: read (the density of the previous
- *              step's input, or of state_t for the first step of a run).
+ *              state_t).  LBM_GRAD_EXACT_DRHO: the exact level with drho
+ *              already holding state_t's density as lbm_density or the
+ *              LBM_GRAD_EXACT lbm_step_full step from state_t wrote it (read;
+ *              saves the density pass).  LBM_GRAD_LAGGED: read (the density of
+ *              the previous step's input, or of state_t for the first step of
+ *              a run).
  *   grad_work: device float[3][n_nodes]: receives the cotangent of the step's
  *              density gradient (LBM_GRAD_LAGGED also stages the transpose of
  *              grad_pending in it during the call).
@@ -344,7 +348,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in,
  *              from this state's density (the grad_work of the previous call
  *              of the reverse sweep); its stencil transpose is added to
  *              adj_out.  Must differ from grad_work.
- * LBM_GRAD_EXACT: the gradient came from state_t's own density, so its
+ * LBM_GRAD_EXACT(_DRHO): the gradient came from state_t's own density, so its
  * cotangent flows back through the stencil into adj_out before return.
  * LBM_GRAD_LAGGED: it belongs to the state the gradient was taken from; pass
  * grad_work as grad_pending to the next call of the sweep, and after the run's

@@ -16,7 +16,7 @@ LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ESTATE, LBM_ENONFINITE = 0, -1, -2, -3, -4
 BC = {"periodic": 0, "bounceback": 1}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "bf16_sr": 3}
 CORR = {"off": 0, "lowmach": 1, "local": 2, "full": 3}
-GRAD_MODE = {"exact": 0, "lagged": 1}
+GRAD_MODE = {"exact": 0, "lagged": 1, "exact_drho": 2}
 MOMENTS = {"central": 0, "raw": 1}
 LAYOUT = {"ab": 0, "aa": 1}
 

@@ -33,8 +33,9 @@ from . import lbm as L
 
 class _Steps:
     """Forward and adjoint steps of a lattice: plain, or with the full corrections at the exact or the
-    lagged time level of the density gradient (whose fields this holds).  ``dens`` is the density field
-    a step takes its gradient from (lagged level only; None otherwise)."""
+    lagged time level of the density gradient (whose fields this holds).  ``dens`` is a density field
+    that a state's adjoint step reads: at the lagged level the one its step took the gradient from, at
+    the exact level the state's own density where a recomputed step already wrote it (else None)."""
 
     def __init__(self, lat, mode):
         self.lat = lat
@@ -59,17 +60,29 @@ class _Steps:
         a, b = self.lat.step(a, b, n, force)
         return a, b, None
 
-    def step(self, src, dst, force, dens):
-        """One step src -> dst; returns the density field of the step after it."""
+    def recompute(self, states, start_dens, force):
+        """Step states[0] -> states[1] -> ... (each from the one before); returns for each state the
+        density field its adjoint step reads: lagged level, the field its step took the gradient from
+        (start_dens for the first); exact level, its own density as its step computed it (None for the
+        last state, which is not stepped from here: its adjoint step computes it)."""
+        h, n = self.lat.h, len(states)
         if self.lagged:
-            nxt = self.lat.field(1)
-            L.lbm_step_full(self.lat.h, 1, src, dst, dens, nxt, "lagged", force)
-            return nxt
+            dens = [start_dens]
+            for i in range(1, n):
+                nxt = self.lat.field(1)
+                L.lbm_step_full(h, 1, states[i - 1], states[i], dens[i - 1], nxt, "lagged", force)
+                dens.append(nxt)
+            return dens
         if self.full:
-            L.lbm_step_full(self.lat.h, 1, src, dst, self.drho, None, "exact", force)
-        else:
-            L.lbm_step(self.lat.h, 1, src, dst, force)
-        return None
+            dens = []
+            for i in range(1, n):
+                d = self.lat.field(1)
+                L.lbm_step_full(h, 1, states[i - 1], states[i], d, None, "exact", force)
+                dens.append(d)
+            return dens + [None]
+        for i in range(1, n):
+            L.lbm_step(h, 1, states[i - 1], states[i], force)
+        return [None] * n
 
     def adjoint(self, state, dens, lam, lam_next, force, grad_force):
         if not self.full:
@@ -78,7 +91,11 @@ class _Steps:
         if self.grad is None:
             self.grad = self.lat.field(3)
         if not self.lagged:
-            L.lbm_step_adjoint_full(self.lat.h, state, lam, lam_next, self.drho, self.grad, force, grad_force)
+            if dens is None:    # the density pass runs inside the call
+                L.lbm_step_adjoint_full(self.lat.h, state, lam, lam_next, self.drho, self.grad, force, grad_force)
+            else:               # the recomputed step from this state already wrote its density
+                L.lbm_step_adjoint_full(self.lat.h, state, lam, lam_next, dens, self.grad, force, grad_force,
+                                        mode="exact_drho")
             return
         # lagged: the cotangent of this step's gradient belongs to the state before it (the pending
         # transpose is added to that state's adjoint by the next call of the sweep)
@@ -175,10 +192,8 @@ def _reverse_segment(steps, start_state, start_dens, counter, n, lam, lam_next, 
     h = steps.lat.h
     if n <= max_states:
         states = [start_state] + [pool.get() for _ in range(n - 1)]
-        dens = [start_dens]
         L.lbm_set_step_counter(h, counter)
-        for i in range(1, n):
-            dens.append(steps.step(states[i - 1], states[i], force, dens[i - 1]))
+        dens = steps.recompute(states, start_dens, force)
         for i in reversed(range(n)):
             steps.adjoint(states[i], dens[i], lam, lam_next, force, grad_force)
             lam, lam_next = lam_next, lam

@@ -345,10 +345,12 @@ hipError_t launch_density_adjoint(const lbm_handle& h, const float* grad, float*
 
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                                const float* force, float* grad_force, double* grad_force_uniform, float* drho,
-                               float* grad_rho, bool exact, const float* pending, hipStream_t st) {
+                               float* grad_rho, bool exact, bool drho_given, const float* pending,
+                               hipStream_t st) {
   const bool full = h.p.corr == LBM_CORR_FULL;
   hipError_t e = hipSuccess;
-  if (full && exact) e = launch_density(h, state, drho, st);  // the density field the step's gradient came from
+  // the density field the step's gradient came from
+  if (full && exact && !drho_given) e = launch_density(h, state, drho, st);
   if (e != hipSuccess) return e;
   // lagged: the next step took its gradient from this state's density, so the stencil's transpose of
   // its cotangent (pending) belongs to every population of this state.  It goes, one value per node,

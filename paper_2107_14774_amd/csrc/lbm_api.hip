@@ -457,7 +457,7 @@ int lbm_step_adjoint(lbm_handle* h, const void* state_t, const float* adj_in, fl
   if (h->p.corr == LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint: the full corrections need lbm_step_adjoint_full");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force,
-                                           grad_force_uniform, nullptr, nullptr, false, nullptr,
+                                           grad_force_uniform, nullptr, nullptr, false, false, nullptr,
                                            (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint");
 }
@@ -469,8 +469,8 @@ int lbm_step_adjoint_full(lbm_handle* h, int32_t mode, const void* state_t, cons
   if (h->k.aa) return fail(LBM_EINVAL, "lbm_step_adjoint_full: the adjoint runs on the AB layout only");
   if (h->p.corr != LBM_CORR_FULL)
     return fail(LBM_EINVAL, "lbm_step_adjoint_full: the handle's corrections are not LBM_CORR_FULL");
-  if (mode != LBM_GRAD_EXACT && mode != LBM_GRAD_LAGGED)
-    return fail(LBM_EINVAL, "lbm_step_adjoint_full: mode must be LBM_GRAD_EXACT or LBM_GRAD_LAGGED");
+  if (mode != LBM_GRAD_EXACT && mode != LBM_GRAD_LAGGED && mode != LBM_GRAD_EXACT_DRHO)
+    return fail(LBM_EINVAL, "lbm_step_adjoint_full: mode must be LBM_GRAD_EXACT, LBM_GRAD_EXACT_DRHO or LBM_GRAD_LAGGED");
   CHECK_REQ(state_t, "lbm_step_adjoint_full", "state_t");
   CHECK_REQ(adj_in, "lbm_step_adjoint_full", "adj_in");
   CHECK_REQ(adj_out, "lbm_step_adjoint_full", "adj_out");
@@ -487,7 +487,8 @@ int lbm_step_adjoint_full(lbm_handle* h, int32_t mode, const void* state_t, cons
   if (grad_pending != nullptr && (mode != LBM_GRAD_LAGGED || (const void*)grad_pending == (const void*)grad_work))
     return fail(LBM_EINVAL, "lbm_step_adjoint_full: grad_pending is for LBM_GRAD_LAGGED and must differ from grad_work");
   hipError_t e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force, grad_force_uniform,
-                                           drho, grad_work, mode == LBM_GRAD_EXACT, grad_pending,
+                                           drho, grad_work, mode != LBM_GRAD_LAGGED, mode == LBM_GRAD_EXACT_DRHO,
+                                           grad_pending,
                                            (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_step_adjoint_full");
 }

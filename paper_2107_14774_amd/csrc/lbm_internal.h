@@ -80,12 +80,13 @@ hipError_t launch_export_nodes(const lbm_handle& h, const void* src, const int64
 hipError_t launch_moments(const lbm_handle& h, const void* src, const float* force, float* rho,
                           float* u, double* sums, hipStream_t st);
 // With the full corrections drho (float[n]) and grad_rho (float[3 n]) are the caller's fields:
-// exact = true computes drho from the state and adds the gradient's transpose to adj_out; else
-// drho is read, and pending (float[3 n] or NULL) is the transpose added to adj_out.
+// exact = true adds the gradient's transpose to adj_out and computes drho from the state unless
+// drho_given; else drho is read, and pending (float[3 n] or NULL) is a cotangent whose transpose is
+// added to adj_out.
 hipError_t launch_step_adjoint(const lbm_handle& h, const void* state, const float* adj_in,
                                float* adj_out, const float* force, float* grad_force,
                                double* grad_force_uniform, float* drho, float* grad_rho, bool exact,
-                               const float* pending, hipStream_t st);
+                               bool drho_given, const float* pending, hipStream_t st);
 // adj += the density-gradient stencil's transpose of grad (full corrections)
 hipError_t launch_density_adjoint(const lbm_handle& h, const float* grad, float* adj, hipStream_t st);
 hipError_t launch_moments_adjoint(const lbm_handle& h, const void* state, const float* force,

@@ -236,7 +236,8 @@ def lbm_step_adjoint(h, state_t, adj_in, adj_out, force=None, grad_force=None, g
 
 def lbm_step_adjoint_full(h, state_t, adj_in, adj_out, drho, grad_work, force=None, grad_force=None,
                           grad_force_uniform=None, mode="exact", grad_pending=None, stream=None):
-    """Adjoint step of the full corrections; ``mode`` "exact" or "lagged" (see include/lbm.h)."""
+    """Adjoint step of the full corrections; ``mode`` "exact", "exact_drho" (exact level, ``drho``
+    already holds the state's density) or "lagged" (see include/lbm.h)."""
     m = 27 * h.stride
     _require(adj_in, _ABI_F32, m, "adj_in")
     _require(adj_out, _ABI_F32, m, "adj_out")

@@ -120,6 +120,8 @@ def test_full_corrections_need_the_density_field_entry_point():
     assert lib.lbm_step_adjoint_full(hf.raw, 5, a, b, c, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
     # a pending gradient cotangent belongs to the lagged time level and differs from grad_work
     assert lib.lbm_step_adjoint_full(hf.raw, 0, a, b, c, None, None, None, d1, d2, d3, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 2, a, b, c, None, None, None, d1, d2, d3, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full(hf.raw, 3, a, b, c, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
     assert lib.lbm_step_adjoint_full(hf.raw, 1, a, b, c, None, None, None, d1, d2, d2, None) == _lib.LBM_EINVAL
     assert lib.lbm_density_adjoint(hf.raw, None, c, None) == _lib.LBM_EINVAL
     assert lib.lbm_density_adjoint(hf.raw, d2, None, None) == _lib.LBM_EINVAL

@@ -280,6 +280,34 @@ def test_full_corrections_step_adjoint_matches_oracle_vjp(case):
     assert errU < 1e-4
 
 
+@pytest.mark.parametrize("case", [FULL_ADJ_CASES[1], FULL_ADJ_CASES[3]], ids=[FULL_ADJ_CASES[1][0], FULL_ADJ_CASES[3][0]])
+def test_full_corrections_exact_drho_mode_equals_exact(case):
+    """Mode "exact_drho" (the state's density supplied, as lbm_density writes it) gives the exact level's
+    results bit for bit without its density pass."""
+    name, (nx, ny, nz), r, s, (bx, by, bz), wv, moments, storage, field, kind = case
+    p, lat = _full_case(case)
+    f0 = fp32_rounded_state(random_state(p, 35), p)
+    g = np.random.Generator(np.random.PCG64(36))
+    force = torch.tensor(1e-4 * g.standard_normal((3, *p.shape))).to(torch.float32).cuda() if field else None
+    lam_f = torch.tensor(g.standard_normal((27, *p.shape)))
+    st = lat.new_state()
+    lat.import_populations(st, f0.cuda())
+    lam_in = lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam_f.cuda(), lam_in)
+    outs = []
+    for mode in ("exact", "exact_drho"):
+        drho = lat.density(st) if mode == "exact_drho" else lat.field(1)
+        lam_out, gw = lat.new_adjoint(), lat.field(3)
+        gF = torch.zeros((3, *p.shape), dtype=torch.float32, device="cuda")
+        gFu = torch.zeros(3, dtype=torch.float64, device="cuda")
+        P.lbm_step_adjoint_full(lat.h, st, lam_in, lam_out, drho, gw, force, gF, gFu, mode=mode)
+        outs.append((lam_out, gw, gF, gFu))
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert torch.equal(a, b)
+    # the uniform-force gradient sums block totals with atomics, in any order
+    assert torch.allclose(outs[0][3], outs[1][3], rtol=1e-12, atol=0.0)
+
+
 @pytest.mark.parametrize("case", FULL_ADJ_CASES, ids=[c[0] for c in FULL_ADJ_CASES])
 def test_full_corrections_lagged_step_adjoint_matches_oracle_vjp(case):
     """lbm_step_adjoint_full at the lagged time level: the gradient comes from the density D of another
