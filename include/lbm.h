@@ -359,6 +359,21 @@ int lbm_step_adjoint_full(lbm_handle* h, int32_t mode, const void* state_t, cons
                           double* grad_force_uniform, float* drho, float* grad_work,
                           const float* grad_pending, void* hip_stream);
 
+/* lbm_step_adjoint_full at the exact time level (LBM_GRAD_EXACT) without work
+ * fields, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the density
+ * and the gradient cotangent go to a static 64 MiB device array of the library
+ * (one per device, held from library load to process exit), so the call
+ * allocates nothing.  Arguments, results and errors as lbm_step_adjoint_full
+ * with mode LBM_GRAD_EXACT; LBM_EINVAL if the grid needs more than the array
+ * (16 B per node: at most 4,194,288 nodes).  All calls on one device share the
+ * array: calls that overlap in time on one device (different streams, or
+ * different host threads) race; calls on one stream are ordered and safe.  No
+ * part of the array needs to start at zero. */
+int lbm_step_adjoint_full_noalloc(lbm_handle* h, const void* state_t, const float* adj_in,
+                                  float* adj_out, const float* force, float* grad_force,
+                                  double* grad_force_uniform, void* hip_stream);
+
 /* adj += the transpose of the full corrections' density-gradient stencil
  * applied to grad (device float[3][n_nodes], a cotangent of the gradient),
  * added to every population each node gathered (d rho / d f = 1).  adj: an

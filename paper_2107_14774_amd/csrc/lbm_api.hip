@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -36,6 +37,43 @@ uint32_t step_key(uint64_t seq) {
 
 // Before every step launch: the step's rounding key, then the counter moves on.
 void next_step(lbm_handle* h) { h->k.seq_hash = step_key(h->seq++); }
+
+}  // namespace
+
+// ------------------------------------------------------------ allocation-free adjoint step
+// The two work fields of lbm_step_adjoint_full at the exact time level (the density, float[n], then
+// the gradient cotangent, float[3 n], from the next 256-byte boundary) live in this static array, so
+// that lbm_step_adjoint_full_noalloc allocates nothing.  Each device holds its own copy from module
+// load to process exit; host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in).
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// floats of the array one call on an n-node grid uses
+size_t noalloc_floats(int64_t n) { return (size_t)((n + 63) / 64 * 64) + 3 * (size_t)n; }
+
+// The current device's copy of scratch, looked up on the first call on that device.
+hipError_t scratch_here(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -500,6 +538,40 @@ int lbm_density_adjoint(lbm_handle* h, const float* grad, float* adj, void* hip_
   CHECK_REQ(adj, "lbm_density_adjoint", "adj");
   hipError_t e = clbm::launch_density_adjoint(*h, grad, adj, (hipStream_t)hip_stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_density_adjoint");
+}
+
+// The allocation-free variant of lbm_step_adjoint_full (exact time level): its work fields come
+// from the static array above.
+int lbm_step_adjoint_full_noalloc(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out,
+                                  const float* force, float* grad_force, double* grad_force_uniform,
+                                  void* hip_stream) {
+  const char* name = "lbm_step_adjoint_full_noalloc";
+  CHECK_HANDLE(h, "lbm_step_adjoint_full_noalloc");
+  if (h->k.aa) return fail(LBM_EINVAL, std::string(name) + ": the adjoint runs on the AB layout only");
+  if (h->p.corr != LBM_CORR_FULL)
+    return fail(LBM_EINVAL, std::string(name) + ": the handle's corrections are not LBM_CORR_FULL");
+  CHECK_REQ(state_t, "lbm_step_adjoint_full_noalloc", "state_t");
+  CHECK_REQ(adj_in, "lbm_step_adjoint_full_noalloc", "adj_in");
+  CHECK_REQ(adj_out, "lbm_step_adjoint_full_noalloc", "adj_out");
+  CHECK_PTR(force, "lbm_step_adjoint_full_noalloc", "force");
+  CHECK_PTR(grad_force, "lbm_step_adjoint_full_noalloc", "grad_force");
+  CHECK_PTR(grad_force_uniform, "lbm_step_adjoint_full_noalloc", "grad_force_uniform");
+  if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, std::string(name) + ": adj_in == adj_out");
+  const size_t need = noalloc_floats(h->n) * sizeof(float);
+  if (need > kScratchBytes)
+    return fail(LBM_EINVAL, std::string(name) + ": the grid's " + std::to_string(h->n) + " nodes need " +
+                                std::to_string(need) + " bytes of work space, above the static array's " +
+                                std::to_string(kScratchBytes) + " (at most " +
+                                std::to_string(kScratchBytes / sizeof(float) / 4 - 16) +
+                                " nodes); use lbm_step_adjoint_full with work fields instead");
+  float* base = nullptr;
+  hipError_t e = scratch_here(&base);
+  if (e != hipSuccess) return hip_fail(e, name);
+  float* drho = base;                                         // float[n], written by the density pass
+  float* grad = base + (size_t)((h->n + 63) / 64 * 64);       // float[3 n], written by the adjoint kernel
+  e = clbm::launch_step_adjoint(*h, state_t, adj_in, adj_out, force, grad_force, grad_force_uniform, drho, grad,
+                                true, false, nullptr, (hipStream_t)hip_stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, name);
 }
 
 int lbm_moments_adjoint(lbm_handle* h, const void* state, const float* force, const float* g_rho,

@@ -254,6 +254,21 @@ def lbm_step_adjoint_full(h, state_t, adj_in, adj_out, drho, grad_work, force=No
                                                  _lib.stream_ptr(stream)))
 
 
+def lbm_step_adjoint_full_noalloc(h, state_t, adj_in, adj_out, force=None, grad_force=None,
+                                  grad_force_uniform=None, stream=None):
+    """lbm_step_adjoint_full at the exact time level with the library's static work array (allocates
+    nothing; see include/lbm.h)."""
+    m = 27 * h.stride
+    _require(adj_in, _ABI_F32, m, "adj_in")
+    _require(adj_out, _ABI_F32, m, "adj_out")
+    _require(force, _ABI_F32, 3 * h.n, "force")
+    _require(grad_force, _ABI_F32, 3 * h.n, "grad_force")
+    _require(grad_force_uniform, _ABI_F64, 3, "grad_force_uniform")
+    _lib.check(_lib.load().lbm_step_adjoint_full_noalloc(h.raw, _lib.ptr(_state(h, state_t)), _lib.ptr(adj_in),
+                                                         _lib.ptr(adj_out), _lib.ptr(force), _lib.ptr(grad_force),
+                                                         _lib.ptr(grad_force_uniform), _lib.stream_ptr(stream)))
+
+
 def lbm_density_adjoint(h, grad, adj, stream=None):
     _require(grad, _ABI_F32, 3 * h.n, "grad")
     _require(adj, _ABI_F32, 27 * h.stride, "adj")

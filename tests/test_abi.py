@@ -123,6 +123,13 @@ def test_full_corrections_need_the_density_field_entry_point():
     assert lib.lbm_step_adjoint_full(hf.raw, 2, a, b, c, None, None, None, d1, d2, d3, None) == _lib.LBM_EINVAL
     assert lib.lbm_step_adjoint_full(hf.raw, 3, a, b, c, None, None, None, d1, d2, None, None) == _lib.LBM_EINVAL
     assert lib.lbm_step_adjoint_full(hf.raw, 1, a, b, c, None, None, None, d1, d2, d2, None) == _lib.LBM_EINVAL
+    # the allocation-free variant: same checks, and grids beyond its static work array are refused
+    assert lib.lbm_step_adjoint_full_noalloc(hl.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full_noalloc(hf.raw, a, b, b, None, None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_adjoint_full_noalloc(hf.raw, None, b, c, None, None, None, None) == _lib.LBM_EINVAL
+    hbig = P.lbm_create(256, 128, 129, corr="full")
+    assert lib.lbm_step_adjoint_full_noalloc(hbig.raw, a, b, c, None, None, None, None) == _lib.LBM_EINVAL
+    assert b"static array" in lib.lbm_last_error()
     assert lib.lbm_density_adjoint(hf.raw, None, c, None) == _lib.LBM_EINVAL
     assert lib.lbm_density_adjoint(hf.raw, d2, None, None) == _lib.LBM_EINVAL
 
