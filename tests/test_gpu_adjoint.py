@@ -217,6 +217,9 @@ FULL_ADJ_CASES = [
     ("full_raw_aniso_f16", (16, 9, 12), 0.5, 0.25, ("periodic", "periodic", "bounceback"), None, "raw", "f16",
      True, None),
     ("full_duct_64bit_slots", (13, 9, 8), 0.75, 1.0, ("bounceback",) * 3, None, "central", "f32", True, "2"),
+    # one-node and three-node axes: the stencil and its transpose wrap onto the node itself
+    ("full_thin_axes_f32", (3, 1, 17), 1.0, 0.5, ("periodic", "periodic", "bounceback"), None, "central", "f32",
+     True, None),
 ]
 
 
