@@ -12,7 +12,9 @@ steps at the exact (default) or the lagged time level of the density gradient
 (lbm_step_full) and reverses through lbm_step_adjoint_full; at the lagged level
 the cotangent of each step's gradient belongs to the state one step earlier, so
 it is handed to the next call of the sweep, and the first step's (taken from
-its own input) goes to lambda(0) through lbm_density_adjoint.
+its own input) goes to lambda(0) through lbm_density_adjoint; at the exact
+level the recomputed steps keep the density of each state they step from, so
+its adjoint step reads it instead of computing it again.
 
 Memory: the forward keeps one state every ``checkpoint_every`` steps; the
 backward recomputes one segment at a time from its checkpoint, holding that
@@ -20,7 +22,8 @@ segment's states while it steps back through it.  A segment longer than
 ``max_states`` is split again: its sub-segment starts (about sqrt(K) of
 them) are recomputed and kept, then each sub-segment is recomputed and
 reversed in turn (one extra forward pass per segment).  Peak memory is about
-nsteps/K + min(K, 2 sqrt(K)) states plus two adjoint buffers.
+nsteps/K + min(K, 2 sqrt(K)) states plus two adjoint buffers (with the full
+corrections also one density field, 4 B per node, per held state).
 """
 
 import math
