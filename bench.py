@@ -288,6 +288,20 @@ def run_adjoint(kind, steps, warmup):
     ms = ev0.elapsed_time(ev1) / steps
     mlups = lat.n / (ms * 1e-3) / 1e6
     alg = ADJ_BYTES_PER_LUP[kind] * lat.n / (ms * 1e-3) / 1e9
+    pattern_gbs = None
+    if not full:  # the same bytes in the adjoint step's access pattern without its arithmetic
+        for _ in range(warmup):
+            P.lbm_adjoint_stream(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
+            lam_a, lam_b = lam_b, lam_a
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            P.lbm_adjoint_stream(lat.h, st, lam_a, lam_b, force, grad, stream=stream)
+            lam_a, lam_b = lam_b, lam_a
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pattern_gbs = ADJ_BYTES_PER_LUP[kind] * lat.n / (ev0.elapsed_time(ev1) / steps * 1e-3) / 1e9
+        log(f"[bench] {kind}: lbm_adjoint_stream (the adjoint step's data movement only) {pattern_gbs:.0f} GB/s")
     del st, tmp, lam_a, lam_b, grad
     if full:
         del drho, gwork, gpend
@@ -326,6 +340,8 @@ def run_adjoint(kind, steps, warmup):
     torch.cuda.empty_cache()
     return {"workload": w.name, "storage": storage, "mlups": round(mlups, 1), "ms_per_step": round(ms, 4),
             "hbm_gbs_algorithmic": round(alg, 1), "hbm_frac": round(alg / HBM_PEAK_GBS, 4),
+            "pattern_ceiling_gbs": None if pattern_gbs is None else round(pattern_gbs, 1),
+            "frac_of_pattern": None if pattern_gbs is None else round(alg / pattern_gbs, 4),
             "bytes_per_lup": ADJ_BYTES_PER_LUP[kind], "measured_bytes_per_launch": measured_traffic(kind),
             "backward_mlups_incl_recompute": round(n_nodes * nsteps / bwd / 1e6, 1),
             "backward_hbm_gbs_algorithmic": round(bwd_gbs, 1),
@@ -400,6 +416,9 @@ PROFILE_KERNELS = {
     # the measured ceilings: streaming only (the FP32 step and the FP16 pair step without their
     # collisions) and the plain copy
     "stream_f32": "k_stream<0, 0>", "stream_f16": "k_stream_pair<1>", "copy": "k_copy16",
+    # and the adjoint step's data movement without its arithmetic, on the adjoint workloads
+    "adjoint_stream_f32": "k_adjoint_stream<0, 1>", "adjoint_stream_f32_hbm": "k_adjoint_stream<0, 1>",
+    "adjoint_stream_f16": "k_adjoint_stream<1, 0>",
 }
 PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "f32": (512, 512, 256, "512x512x256"), "f16": (512, 512, 256, "512x512x256"),
@@ -414,6 +433,9 @@ PROFILE_WORKLOADS = {  # variant -> (nx, ny, nz, label)
     "adjoint_full (lagged transpose)": (512, 512, 128, "512x512x128 duct"),
     "stream_f32": (512, 512, 256, "512x512x256"), "stream_f16": (512, 512, 256, "512x512x256"),
     "copy": (512, 512, 256, "one FP32 state"),
+    "adjoint_stream_f32": (128, 128, 64, "128x128x64 duct"),
+    "adjoint_stream_f32_hbm": (512, 512, 128, "512x512x128 duct"),
+    "adjoint_stream_f16": (384, 384, 192, "384x384x192"),
 }
 COPY_BYTES = 27 * 512 * 512 * 256 * 4                 # bytes read (and written) by one lbm_copy of the bench
 # $OUT is any output directory (the three runs write their CSVs under it)
@@ -454,6 +476,8 @@ def summarize_rocprof(out_dir):
             alg[v] = BYTES_PER_LUP[v.split()[0]]
     alg["stream_f32"] = BYTES_PER_LUP["f32"]
     alg["stream_f16"] = BYTES_PER_LUP["f16"]
+    for v in ("adjoint_stream_f32", "adjoint_stream_f32_hbm", "adjoint_stream_f16"):
+        alg[v] = ADJ_BYTES_PER_LUP[v.replace("_stream", "")]
     alg["adjoint_full (step)"] = 108 + 108 + 108 + 12 + 24 + 4 + 12
     alg["adjoint_full (transpose)"] = 12 + 108 + 108
     alg["adjoint_full (lagged transpose)"] = 12 + 4
@@ -462,8 +486,8 @@ def summarize_rocprof(out_dir):
     lines = ["# rocprofv3 kernel trace: fused collide-and-stream step (512x512x256, r=1, s=1/2; local and full",
              "# corrections), its adjoint (128x128x64 and 512x512x128 ducts with force field; 384x384x192,",
              "# r=1/2, s=1/4, FP16), and the measured ceilings: streaming only (k_stream and k_stream_pair, the",
-             "# FP32 and FP16 steps' gathers and stores without the collisions) and the library copy (k_copy16,",
-             "# one FP32 state)",
+             "# FP32 and FP16 steps' gathers and stores without the collisions; k_adjoint_stream, the adjoint",
+             "# step's loads and stores without its arithmetic) and the library copy (k_copy16, one FP32 state)",
              "", "commands (repo root, one MI355X, TMPDIR=/tmp, $OUT an output directory):", "  " + TRACE_CMD,
              "  " + SUMMARY_CMD, "",
              f"{'kernel':38s} {'variant':16s} {'workload':16s} calls  avg_ms   min_ms   max_ms   "

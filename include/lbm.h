@@ -278,6 +278,19 @@ int lbm_step_full(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b,
  * LBM_EINVAL for the AA layout, for moving walls, or state_a == state_b. */
 int lbm_stream(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, void* hip_stream);
 
+/* The adjoint step's data movement with its arithmetic left out: gathers
+ * state_t as lbm_step does, reads adj_in where lbm_step_adjoint reads
+ * lambda(t+1), reads force and adds it to grad_force (both optional, as in
+ * lbm_step_adjoint), and writes adj_out = gathered population + that lambda
+ * value at each of the node's own elements.  It moves lbm_step_adjoint's bytes
+ * (without the moving-wall pass) in its access pattern, block shape and
+ * occupancy, so its throughput is the ceiling that pattern allows on the
+ * device: the reference the adjoint step's memory throughput is reported
+ * against.  Arrays as in lbm_step_adjoint.  LBM_EINVAL for the AA layout or
+ * adj_in == adj_out. */
+int lbm_adjoint_stream(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out,
+                       const float* force, float* grad_force, void* hip_stream);
+
 /* Device-to-device copy of `bytes` bytes (a multiple of 16; 0 does nothing)
  * with one 16-byte non-temporal load and store per thread: the reference for
  * the read-and-write bandwidth of the device.  dst and src: device, 16-byte

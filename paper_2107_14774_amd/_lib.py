@@ -71,6 +71,7 @@ _SIGNATURES = {
     "lbm_step_adjoint_full": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lbm_step_adjoint_full_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "lbm_density_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbm_adjoint_stream": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "lbm_moments_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "lbm_init_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "lbm_adjoint_to_natural": (ctypes.c_int, [_P, _P, _P, _P]),

@@ -438,6 +438,77 @@ __global__ __launch_bounds__(256, HI ? 1 : (ST == 0 ? LBM_ADJ_WAVES_32 : LBM_ADJ
   }
 }
 
+// ------------------------------------------------------------------ streaming only
+// The data movement of k_step_adjoint with its arithmetic left out, a measured ceiling: gather the
+// state, load lambda(t+1) where the adjoint step reads it, read the force and update its gradient,
+// and store mu = df + lambda at the node's own slots (same addressing, row order and block shape).
+template <int ST, int WALLS>
+__global__ __launch_bounds__(256) void k_adjoint_stream(const typename Store<ST>::T* __restrict__ state,
+                                                        const float* __restrict__ lin, float* __restrict__ lout,
+                                                        const float* __restrict__ force,
+                                                        float* __restrict__ grad_force, Consts k, uint32_t bpr) {
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxi = lb % bpr, rowid = lb / bpr;
+  int y, z;
+  tiled_row(rowid, 1u, k, y, z);
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  if (x >= k.nx) return;
+  Upstream u;
+  upstream(x, y, z, k, u);
+  float df[27], lam[27], mu[27];
+  WallFlags w;
+  if constexpr (WALLS == 2) {
+    gather_all<ST>(state, make_coord(x, y, z, k), k, df);
+    load_next_all(lin, make_coord(x, y, z, k), k, lam);
+  } else if constexpr (WALLS == 1) {
+    w = wall_flags(x, y, z, k);
+    gather_walls32<ST>(state, u, w, k, df);
+    load_next_walls32(lin, u, w, lam);
+  } else {
+    gather_periodic<ST>(pull_groups(state, u), u, k, df);
+    load_next_periodic(aa_odd_groups(lin, u), u, lam);
+  }
+#pragma unroll
+  for (int a = 0; a < 27; ++a) mu[a] = df[a] + lam[a];
+  store_own_adj(own_groups(lout, u), store_offset(u.xo[1]), mu);
+  if (force != nullptr && grad_force != nullptr) {
+    const int64_t nrow = ((int64_t)z * k.ny + y) * k.nx;
+    const float* f = force + nrow;
+    float* g = grad_force + nrow;
+    g[x] += ld_off(f, (uint32_t)x);
+    g[k.n + x] += ld_off(f + k.n, (uint32_t)x);
+    g[2 * k.n + x] += ld_off(f + 2 * k.n, (uint32_t)x);
+  }
+}
+
+template <int ST>
+hipError_t AdjointKernels<ST>::stream(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
+                                      const float* force, float* grad_force, hipStream_t st) {
+  using T = typename Store<ST>::T;
+  const int block = h.block;
+  const uint32_t bpr = (uint32_t)((h.p.nx + block - 1) / block);
+  const int64_t nb = (int64_t)bpr * h.p.ny * h.p.nz;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const bool any_wall = h.k.bb_x || h.k.bb_y || h.k.bb_z;
+  const bool fits32 = 27ull * (uint64_t)h.stride * 4u < (1ull << 32);
+  int kind = !any_wall ? 0 : (fits32 ? 1 : 2);
+  if (h.force_kind > kind && (h.force_kind == 2 || fits32)) kind = h.force_kind;
+  // the adjoint step's occupancy, 3 waves per SIMD (its registers there, reserved LDS here)
+  const int blocks_per_cu = 4 * 3 / (block / 64);
+  const unsigned lds = blocks_per_cu < 1 ? 0u : (unsigned)((163840 / blocks_per_cu) & ~511);
+  const dim3 grid((unsigned)nb), blk(block);
+  const T* s = (const T*)state;
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_adjoint_stream<ST, 0>), grid, blk, lds, st, s, adj_in, adj_out, force, grad_force,
+                               h.k, bpr); break;
+    case 1: hipLaunchKernelGGL((k_adjoint_stream<ST, 1>), grid, blk, lds, st, s, adj_in, adj_out, force, grad_force,
+                               h.k, bpr); break;
+    default: hipLaunchKernelGGL((k_adjoint_stream<ST, 2>), grid, blk, lds, st, s, adj_in, adj_out, force, grad_force,
+                                h.k, bpr); break;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launcher
 template <int ST, bool HI>
 static hipError_t launch_step_adjoint_t(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,

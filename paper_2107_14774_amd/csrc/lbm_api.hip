@@ -445,6 +445,26 @@ int lbm_stream(lbm_handle* h, int32_t nsteps, void* state_a, void* state_b, void
   return LBM_OK;
 }
 
+int lbm_adjoint_stream(lbm_handle* h, const void* state_t, const float* adj_in, float* adj_out, const float* force,
+                       float* grad_force, void* hip_stream) {
+  CHECK_HANDLE(h, "lbm_adjoint_stream");
+  if (h->k.aa) return fail(LBM_EINVAL, "lbm_adjoint_stream: the AB layout only");
+  CHECK_REQ(state_t, "lbm_adjoint_stream", "state_t");
+  CHECK_REQ(adj_in, "lbm_adjoint_stream", "adj_in");
+  CHECK_REQ(adj_out, "lbm_adjoint_stream", "adj_out");
+  CHECK_PTR(force, "lbm_adjoint_stream", "force");
+  CHECK_PTR(grad_force, "lbm_adjoint_stream", "grad_force");
+  if ((const void*)adj_in == (const void*)adj_out) return fail(LBM_EINVAL, "lbm_adjoint_stream: adj_in == adj_out");
+  const hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e;
+  switch (h->p.storage) {
+    case LBM_F32: e = clbm::AdjointKernels<0>::stream(*h, state_t, adj_in, adj_out, force, grad_force, st); break;
+    case LBM_F16: e = clbm::AdjointKernels<1>::stream(*h, state_t, adj_in, adj_out, force, grad_force, st); break;
+    default: e = clbm::AdjointKernels<2>::stream(*h, state_t, adj_in, adj_out, force, grad_force, st); break;
+  }
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_adjoint_stream");
+}
+
 int lbm_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   g_err.clear();
   if (bytes == 0) return LBM_OK;

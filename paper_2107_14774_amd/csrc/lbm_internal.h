@@ -52,6 +52,9 @@ struct AdjointKernels {
   static hipError_t step(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
                          const float* force, float* grad_force, double* grad_uniform, const float* drho,
                          float* grad_rho, bool pend, hipStream_t st);
+  // the data movement of step (local corrections) without its arithmetic
+  static hipError_t stream(const lbm_handle& h, const void* state, const float* adj_in, float* adj_out,
+                           const float* force, float* grad_force, hipStream_t st);
 };
 extern template struct AdjointKernels<0>;
 extern template struct AdjointKernels<1>;

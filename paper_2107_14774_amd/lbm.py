@@ -269,6 +269,17 @@ def lbm_step_adjoint_full_noalloc(h, state_t, adj_in, adj_out, force=None, grad_
                                                          _lib.ptr(grad_force_uniform), _lib.stream_ptr(stream)))
 
 
+def lbm_adjoint_stream(h, state_t, adj_in, adj_out, force=None, grad_force=None, stream=None):
+    """The adjoint step's data movement without its arithmetic (a measured ceiling; see include/lbm.h)."""
+    m = 27 * h.stride
+    _require(adj_in, _ABI_F32, m, "adj_in")
+    _require(adj_out, _ABI_F32, m, "adj_out")
+    _require(force, _ABI_F32, 3 * h.n, "force")
+    _require(grad_force, _ABI_F32, 3 * h.n, "grad_force")
+    _lib.check(_lib.load().lbm_adjoint_stream(h.raw, _lib.ptr(_state(h, state_t)), _lib.ptr(adj_in), _lib.ptr(adj_out),
+                                              _lib.ptr(force), _lib.ptr(grad_force), _lib.stream_ptr(stream)))
+
+
 def lbm_density_adjoint(h, grad, adj, stream=None):
     _require(grad, _ABI_F32, 3 * h.n, "grad")
     _require(adj, _ABI_F32, 27 * h.stride, "adj")
