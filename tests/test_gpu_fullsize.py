@@ -16,7 +16,9 @@
 * 64x128x32 duct (r = 1, s = 1/4, walls in y and z): 20,000 steps to steady
   state against the rectangular-duct series.
 * One adjoint step on the 512x512x128 duct (force field) and the 384x384x192
-  FP16 grid, sampled nodes (walls included) against the oracle's collision VJP.
+  FP16 grid, sampled nodes (walls included) against the oracle's collision VJP;
+  the same duct with the full corrections at both time levels, the oracle's
+  stencil and its transpose taken on each sampled node's neighbourhood.
 * 384x384x192 FP16 adjoint (r = 1/2, s = 1/4): gradient of the final-velocity
   loss with respect to the initial velocity after 1000 steps (checkpoint every
   100), FP16 storage against FP32 storage (stated error), and the FP16 path
@@ -432,6 +434,152 @@ def test_adjoint_step_full_size_sampled(case):
         assert errF < 2e-5
     _say(msg)
     assert err < 2e-6
+
+
+def _wrap_or_clamp(v, n, wall):
+    return (0 if v < 0 else (n - 1 if v >= n else v)) if wall else v % n
+
+
+def _stencil_neighbours(c, p):
+    """The distinct nodes y = c + o (o in {-1, 0, 1}^3) whose density-gradient stencil reads node c:
+    periodic axes wrap, and across a wall there is none (the stencil's clamp maps back onto c itself)."""
+    walls = (p.bc_z == "bounceback", p.bc_y == "bounceback", p.bc_x == "bounceback")
+    dims = (p.nz, p.ny, p.nx)
+    out = set()
+    for oz in (-1, 0, 1):
+        for oy in (-1, 0, 1):
+            for ox in (-1, 0, 1):
+                y = []
+                for v, o, n, wl in zip(c, (oz, oy, ox), dims, walls):
+                    if wl and not 0 <= v + o < n:
+                        break
+                    y.append((v + o) % n)
+                else:
+                    out.add(tuple(y))
+    return sorted(out)
+
+
+FULL_CORR_ADJ_MODES = ["exact", "lagged"]
+
+
+@pytest.mark.parametrize("mode", FULL_CORR_ADJ_MODES)
+def test_full_corrections_adjoint_step_full_size_sampled(mode):
+    """One adjoint step of the full corrections on the bench's 512x512x128 duct (force field) in its
+    launch configuration, at both time levels, 64 seeded nodes plus 8 on the walls' faces, edges and
+    corners against the oracle: the VJP of the oracle's collision at each node with the density
+    gradient as an input (the oracle's stencil on the node's neighbourhood), plus the stencil's
+    transpose of the gradient cotangents, by reverse mode through the oracle's stencil on the
+    neighbourhood (exact level: the cotangents of the neighbours' own collisions; lagged level: a
+    given pending cotangent field, the gradient taken from another state's density).  Also the
+    gradient cotangent the call returns, at the same nodes."""
+    _say("mode", mode)
+    w = W.replica(W.ADJOINT_DUCT_128, 512, 512, 128)
+    p = oracle_params(w, corr="full")
+    p3 = oracle.Params(3, 3, 3, r=p.r, s=p.s, cs2=p.cs2, omega_nu=p.omega_nu, omega_xi=p.omega_xi)
+    dev_ = torch.device("cuda")
+    gen = torch.Generator(device=dev_).manual_seed(91)
+    lat = gpu_lattice(p)
+    st, tmp = lat.new_state(), lat.new_state()
+    lat.init(st, rho=1.0 + 0.01 * torch.randn(p.shape, dtype=DT, device=dev_, generator=gen),
+             u=0.03 * torch.randn((3, *p.shape), dtype=DT, device=dev_, generator=gen))
+    force = 1e-4 * torch.randn((3, *p.shape), device=dev_, generator=gen)
+    st, tmp, _, _ = lat.step_full(st, tmp, 2, lat.field(1), None, "exact", force)   # away from equilibrium
+    nat = lat.export_populations(st)                            # FP64, the gathered values
+    if mode == "exact":
+        D = nat.sum(0)                                          # the gradient's density: the state's own
+        drho = lat.field(1)
+        pending = None
+    else:
+        drho = lat.density(tmp)                                 # another state's density (FP32 deviation)
+        D = drho.to(DT)
+        pending = torch.randn((3, *p.shape), device=dev_, generator=gen)
+    lam_nat = torch.randn((27, *p.shape), dtype=DT, device=dev_, generator=gen)
+    lam_in, lam_out = lat.new_adjoint(), lat.new_adjoint()
+    P.lbm_adjoint_from_natural(lat.h, lam_nat, lam_in)
+    lam_nat = lam_nat.to(torch.float32).to(DT)
+    gF = torch.zeros((3, *p.shape), dtype=torch.float32, device=dev_)
+    gw = lat.field(3)
+    P.lbm_step_adjoint_full(lat.h, st, lam_in, lam_out, drho, gw, force, gF, mode=mode, grad_pending=pending)
+    got_nat = torch.empty((27, *p.shape), dtype=DT, device=dev_)
+    P.lbm_adjoint_to_natural(lat.h, lam_out, got_nat)
+    del lam_in, lam_out
+
+    samples = W.sample_indices(64, p.n, 92)
+    zi, yi, xi = np.unravel_index(samples, p.shape)
+    yb, zb = [0, p.ny - 1, 0, p.ny - 1, 0, p.ny - 1, p.ny // 2, p.ny // 3], [0, 0, p.nz - 1, p.nz - 1, p.nz // 2,
+                                                                            p.nz // 3, 0, p.nz - 1]
+    xb = [0, p.nx - 1, 1, p.nx // 2, p.nx - 2, 3, p.nx - 1, 0]
+    nodes = [tuple(int(v) for v in c) for c in zip(np.concatenate([zi, zb]), np.concatenate([yi, yb]),
+                                                   np.concatenate([xi, xb]))]
+    # nodes whose collision VJP is needed: the samples, and at the exact level their stencil neighbours
+    neigh = {c: _stencil_neighbours(c, p) for c in nodes}
+    vjp_nodes = sorted(set(nodes) | (set(y for c in nodes for y in neigh[c]) if mode == "exact" else set()))
+    # the density values every gradient below reads, as one leaf (so reverse mode sums over duplicates)
+    walls = (p.bc_z == "bounceback", p.bc_y == "bounceback", p.bc_x == "bounceback")
+    dims = (p.nz, p.ny, p.nx)
+
+    def window(c):
+        return [[_wrap_or_clamp(v + o, n, wl) for o in (-1, 0, 1)] for v, n, wl in zip(c, dims, walls)]
+
+    grad_nodes = sorted(set(vjp_nodes) | set(y for c in nodes for y in neigh[c]))
+    coords = sorted(set((a, b, c) for y in grad_nodes for a in window(y)[0] for b in window(y)[1]
+                        for c in window(y)[2]))
+    where = {c: i for i, c in enumerate(coords)}
+    cz, cy, cx = (torch.tensor(v, device=dev_) for v in zip(*coords))
+    D_leaf = D[cz, cy, cx].cpu().clone().requires_grad_(True)
+
+    def gradient(y):
+        wz, wy, wx = window(y)
+        idx = torch.tensor([[[where[(a, b, c)] for c in wx] for b in wy] for a in wz])
+        return OL.density_gradient(D_leaf[idx], p3)[:, 1, 1, 1]
+
+    Gs = {y: gradient(y) for y in grad_nodes}
+    # collision VJPs at vjp_nodes: cotangents of the outputs where the next step gathers them
+    vz, vy, vx = (torch.tensor(v, device=dev_) for v in zip(*vjp_nodes))
+    eb, opp = LT.ebar(), LT.opposite()
+    lam_own = torch.empty((len(vjp_nodes), 27), dtype=DT)
+    for b_ in range(27):
+        ex, ey, ez = (int(v) for v in eb[b_])
+        yy, zz = vy + ey, vz + ez
+        wall = (yy < 0) | (yy >= p.ny) | (zz < 0) | (zz >= p.nz)
+        down = lam_nat[b_, zz % p.nz, yy % p.ny, (vx + ex) % p.nx]
+        lam_own[:, b_] = torch.where(wall, lam_nat[int(opp[b_]), vz, vy, vx], down).cpu()
+    f_v = nat[:, vz, vy, vx].T.cpu().clone().requires_grad_(True)
+    F_v = force[:, vz, vy, vx].T.cpu().to(DT).clone().requires_grad_(True)
+    G_v = torch.stack([Gs[y].detach() for y in vjp_nodes]).requires_grad_(True)
+    out = C.collide(f_v, F_v, p, grad_rho=G_v)
+    want_f, want_F, want_G = torch.autograd.grad(out, (f_v, F_v, G_v), grad_outputs=lam_own)
+    row = {y: i for i, y in enumerate(vjp_nodes)}
+    # the stencil's transpose of the cotangent field v at the samples: reverse mode of sum_y v(y) . G(y)
+    if mode == "exact":
+        v_of = {y: want_G[row[y]] for y in grad_nodes if y in row}
+    else:
+        pz, py, px = (torch.tensor(v, device=dev_) for v in zip(*grad_nodes))
+        pv = pending[:, pz, py, px].T.cpu().to(DT)
+        v_of = {y: pv[i] for i, y in enumerate(grad_nodes)}
+    # per sample c: the derivative with respect to D(c) of sum over its stencil neighbours y of v(y) . G(y)
+    trans = []
+    for c in nodes:
+        Jc = sum((v_of[y] * Gs[y]).sum() for y in neigh[c])
+        (dc,) = torch.autograd.grad(Jc, (D_leaf,), retain_graph=True)
+        trans.append(dc[where[c]])
+    trans = torch.stack(trans)
+    want = torch.stack([want_f[row[c]] for c in nodes]) + trans[:, None]
+    sz, sy, sx = (torch.tensor(v, device=dev_) for v in zip(*nodes))
+    got = got_nat[:, sz, sy, sx].T.cpu()
+    err = (got - want).abs().max().item() / want.abs().max().item()
+    share = trans.abs().max().item() / want.abs().max().item()
+    want_gw = torch.stack([want_G[row[c]] for c in nodes])
+    got_gw = gw[:, sz, sy, sx].T.cpu().to(DT)
+    errG = (got_gw - want_gw).abs().max().item() / want_gw.abs().max().item()
+    want_Fs = torch.stack([want_F[row[c]] for c in nodes])
+    errF = (gF[:, sz, sy, sx].T.cpu().to(DT) - want_Fs).abs().max().item() / want_Fs.abs().max().item()
+    _say(f"full corrections, {mode} level, 512x512x128 duct, {len(nodes)} sampled nodes: rel max err {err:.2e} "
+         f"(the stencil's transpose is {share:.1e} of the result), gradient cotangent {errG:.2e}, "
+         f"force gradient {errF:.2e}")
+    assert err < 2e-6
+    assert errG < 1e-5
+    assert errF < 2e-5
 
 
 def _replica_fixture():
