@@ -220,6 +220,8 @@ FULL_ADJ_CASES = [
     # one-node and three-node axes: the stencil and its transpose wrap onto the node itself
     ("full_thin_axes_f32", (3, 1, 17), 1.0, 0.5, ("periodic", "periodic", "bounceback"), None, "central", "f32",
      True, None),
+    ("full_duct_bf16", (18, 7, 6), 1.0, 0.5, ("periodic", "bounceback", "bounceback"), None, "central", "bf16",
+     True, None),
 ]
 
 
